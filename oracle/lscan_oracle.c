@@ -1,0 +1,275 @@
+/*
+ * lscan_oracle.c -- sequential CPU reference for the device-wide scan.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path links, loads or
+ * calls this file: only the test suite, the smoke check and the CPU-baseline
+ * leg of the benchmark do.  It shares no code, header or constant with the
+ * HIP library; it is plain C written from the problem statement of the paper
+ * (Section 1: inclusive scan y_j = x_0 (+) ... (+) x_j, exclusive scan
+ * y_j = x_0 (+) ... (+) x_{j-1}).
+ *
+ * Every scan here is one left fold over the input in index order, which is
+ * the definition itself.  The method of the paper (Section 4) only splits
+ * this fold into data blocks and re-associates it; for the exact operators
+ * (integer add modulo 2^w, integer max/min, float max/min under totalOrder)
+ * any association gives the same bits, so the fold is the exact answer.
+ * Float add is re-associated by every parallel scan, so for it the oracle
+ * returns the exact prefix sums computed in FP64 with Neumaier compensation,
+ * plus the running sum of magnitudes A_j = sum_{i<=j} |x_i| that scales the
+ * accepted error.
+ *
+ * Readings of points the paper leaves open (each is listed in the design
+ * notes of the repository):
+ *   - identity element e of each operator (the paper writes a literal 0,
+ *     which is only right for add): add -> 0, max -> the smallest value,
+ *     min -> the largest value; for floats -inf / +inf;
+ *   - integer overflow wraps modulo 2^w (two's complement);
+ *   - float max/min follow IEEE 754 totalOrder restricted to non-NaN values
+ *     (so -0 < +0); NaN inputs are outside the contract;
+ *   - bf16 inputs are widened exactly to f32 (the 16 bits become the high
+ *     half of the f32 word) and the scan is an f32 scan of those values;
+ *   - segmented scan = the plain scan applied to each segment
+ *     x[off[s], off[s+1]) independently; empty segments are allowed.
+ *
+ * Build: gcc -O2 -std=c11 -ffp-contract=off -fPIC -shared
+ * (no -ffast-math: the compensated FP64 fold needs strict IEEE order).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <string.h>
+
+enum { OR_I32 = 0, OR_I64 = 1, OR_F32 = 2, OR_BF16 = 3 };
+enum { OR_ADD = 0, OR_MAX = 1, OR_MIN = 2 };
+enum { OR_OK = 0, OR_BAD_ARG = -1 };
+
+/* ------------------------------------------------------------------ */
+/* integer scans (exact)                                               */
+/* ------------------------------------------------------------------ */
+
+int oracle_scan_i32(const int32_t *x, int32_t *y, int64_t n, int op,
+                    int exclusive)
+{
+    if (n < 0 || op < OR_ADD || op > OR_MIN) return OR_BAD_ARG;
+    int32_t acc = (op == OR_ADD) ? 0 : (op == OR_MAX) ? INT32_MIN : INT32_MAX;
+    for (int64_t j = 0; j < n; ++j) {
+        int32_t v = x[j];          /* read before the write: y may be x */
+        if (exclusive) y[j] = acc;
+        if (op == OR_ADD)
+            acc = (int32_t)((uint32_t)acc + (uint32_t)v);   /* mod 2^32 */
+        else if (op == OR_MAX)
+            acc = (v > acc) ? v : acc;
+        else
+            acc = (v < acc) ? v : acc;
+        if (!exclusive) y[j] = acc;
+    }
+    return OR_OK;
+}
+
+int oracle_scan_i64(const int64_t *x, int64_t *y, int64_t n, int op,
+                    int exclusive)
+{
+    if (n < 0 || op < OR_ADD || op > OR_MIN) return OR_BAD_ARG;
+    int64_t acc = (op == OR_ADD) ? 0 : (op == OR_MAX) ? INT64_MIN : INT64_MAX;
+    for (int64_t j = 0; j < n; ++j) {
+        int64_t v = x[j];
+        if (exclusive) y[j] = acc;
+        if (op == OR_ADD)
+            acc = (int64_t)((uint64_t)acc + (uint64_t)v);   /* mod 2^64 */
+        else if (op == OR_MAX)
+            acc = (v > acc) ? v : acc;
+        else
+            acc = (v < acc) ? v : acc;
+        if (!exclusive) y[j] = acc;
+    }
+    return OR_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* float max / min under IEEE 754 totalOrder (non-NaN), exact          */
+/* ------------------------------------------------------------------ */
+
+/* a precedes b in totalOrder: numeric order, and -0 before +0. */
+static int total_less(float a, float b)
+{
+    if (a < b) return 1;
+    if (a > b) return 0;
+    /* a == b numerically: only the two zeros can still differ */
+    return signbit(a) && !signbit(b);
+}
+
+static float widen_bf16(uint16_t h)
+{
+    uint32_t bits = (uint32_t)h << 16;
+    float f;
+    memcpy(&f, &bits, sizeof f);
+    return f;
+}
+
+static void fold_order(float v, float *acc, int op)
+{
+    if (op == OR_MAX) {
+        if (total_less(*acc, v)) *acc = v;
+    } else {
+        if (total_less(v, *acc)) *acc = v;
+    }
+}
+
+int oracle_scan_f32_order(const float *x, float *y, int64_t n, int op,
+                          int exclusive)
+{
+    if (n < 0 || (op != OR_MAX && op != OR_MIN)) return OR_BAD_ARG;
+    float acc = (op == OR_MAX) ? -INFINITY : INFINITY;
+    for (int64_t j = 0; j < n; ++j) {
+        float v = x[j];
+        if (exclusive) y[j] = acc;
+        fold_order(v, &acc, op);
+        if (!exclusive) y[j] = acc;
+    }
+    return OR_OK;
+}
+
+int oracle_scan_bf16_order(const uint16_t *x, float *y, int64_t n, int op,
+                           int exclusive)
+{
+    if (n < 0 || (op != OR_MAX && op != OR_MIN)) return OR_BAD_ARG;
+    float acc = (op == OR_MAX) ? -INFINITY : INFINITY;
+    for (int64_t j = 0; j < n; ++j) {
+        float v = widen_bf16(x[j]);
+        if (exclusive) y[j] = acc;
+        fold_order(v, &acc, op);
+        if (!exclusive) y[j] = acc;
+    }
+    return OR_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* float add: exact prefix sums in FP64 (Neumaier), and A_j = sum |x_i| */
+/* ------------------------------------------------------------------ */
+
+/* One Neumaier step: (s, c) accumulates v; s + c is the running sum. */
+static void neumaier_add(double *s, double *c, double v)
+{
+    double t = *s + v;
+    if (fabs(*s) >= fabs(v))
+        *c += (*s - t) + v;
+    else
+        *c += (v - t) + *s;
+    *s = t;
+}
+
+int oracle_scan_f32_add(const float *x, double *y64, double *absum,
+                        int64_t n, int exclusive)
+{
+    if (n < 0) return OR_BAD_ARG;
+    double s = 0.0, c = 0.0, a = 0.0;
+    for (int64_t j = 0; j < n; ++j) {
+        double v = (double)x[j];
+        if (exclusive) {
+            y64[j] = s + c;
+            if (absum) absum[j] = a;
+        }
+        neumaier_add(&s, &c, v);
+        a += fabs(v);
+        if (!exclusive) {
+            y64[j] = s + c;
+            if (absum) absum[j] = a;
+        }
+    }
+    return OR_OK;
+}
+
+int oracle_scan_bf16_add(const uint16_t *x, double *y64, double *absum,
+                         int64_t n, int exclusive)
+{
+    if (n < 0) return OR_BAD_ARG;
+    double s = 0.0, c = 0.0, a = 0.0;
+    for (int64_t j = 0; j < n; ++j) {
+        double v = (double)widen_bf16(x[j]);
+        if (exclusive) {
+            y64[j] = s + c;
+            if (absum) absum[j] = a;
+        }
+        neumaier_add(&s, &c, v);
+        a += fabs(v);
+        if (!exclusive) {
+            y64[j] = s + c;
+            if (absum) absum[j] = a;
+        }
+    }
+    return OR_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* generic entry points                                                */
+/* ------------------------------------------------------------------ */
+
+/*
+ * oracle_scan: one scan of n elements.
+ *   dtype OR_I32 / OR_I64: y has the input type, exact.
+ *   dtype OR_F32 / OR_BF16 with OR_MAX / OR_MIN: y is float[n], exact.
+ *   dtype OR_F32 / OR_BF16 with OR_ADD: y is double[n] (exact prefix sums
+ *     to FP64 rounding) and absum, if not NULL, receives A_j.
+ * Returns OR_OK or OR_BAD_ARG.
+ */
+int oracle_scan(const void *x, void *y, double *absum, int64_t n, int dtype,
+                int op, int exclusive)
+{
+    if (n < 0) return OR_BAD_ARG;
+    switch (dtype) {
+    case OR_I32:
+        return oracle_scan_i32((const int32_t *)x, (int32_t *)y, n, op,
+                               exclusive);
+    case OR_I64:
+        return oracle_scan_i64((const int64_t *)x, (int64_t *)y, n, op,
+                               exclusive);
+    case OR_F32:
+        if (op == OR_ADD)
+            return oracle_scan_f32_add((const float *)x, (double *)y, absum,
+                                       n, exclusive);
+        return oracle_scan_f32_order((const float *)x, (float *)y, n, op,
+                                     exclusive);
+    case OR_BF16:
+        if (op == OR_ADD)
+            return oracle_scan_bf16_add((const uint16_t *)x, (double *)y,
+                                        absum, n, exclusive);
+        return oracle_scan_bf16_order((const uint16_t *)x, (float *)y, n, op,
+                                      exclusive);
+    default:
+        return OR_BAD_ARG;
+    }
+}
+
+static int64_t in_size(int dtype)
+{
+    return dtype == OR_I64 ? 8 : dtype == OR_BF16 ? 2 : 4;
+}
+
+static int64_t out_size(int dtype, int op)
+{
+    if (dtype == OR_I64) return 8;
+    if (dtype == OR_I32) return 4;
+    return op == OR_ADD ? 8 : 4;   /* float add -> double reference */
+}
+
+/*
+ * oracle_segscan: the plain scan applied to every segment
+ * x[off[s], off[s+1]), s = 0 .. num_segments-1.  off has num_segments + 1
+ * non-decreasing entries with off[0] = 0; elements past off[num_segments]
+ * are not touched.  Layout of y and absum as in oracle_scan.
+ */
+int oracle_segscan(const void *x, void *y, double *absum, const int64_t *off,
+                   int64_t num_segments, int dtype, int op, int exclusive)
+{
+    if (num_segments < 0) return OR_BAD_ARG;
+    if (num_segments > 0 && off[0] != 0) return OR_BAD_ARG;
+    int64_t isz = in_size(dtype), osz = out_size(dtype, op);
+    for (int64_t s = 0; s < num_segments; ++s) {
+        int64_t lo = off[s], hi = off[s + 1];
+        if (hi < lo) return OR_BAD_ARG;
+        int rc = oracle_scan((const char *)x + lo * isz, (char *)y + lo * osz,
+                             absum ? absum + lo : NULL, hi - lo, dtype, op,
+                             exclusive);
+        if (rc != OR_OK) return rc;
+    }
+    return OR_OK;
+}

@@ -1,0 +1,315 @@
+"""Pins of the CPU oracle: checks against what the paper and mathematics fix.
+
+Each check takes an ``Oracle`` (a compiled oracle library) and raises
+``AssertionError`` on a mismatch.  ``tests/test_oracle.py`` runs them on the
+real oracle; ``tests/test_oracle_mutants.py`` runs them on copies of the
+oracle with planted mistakes and requires every mutant to fail one.
+
+The expected values never come from the oracle itself: they are hand-worked
+fixtures (``tests/golden``), closed forms, brute force over Python integers
+and ``math.fsum``, and numpy library routines.
+"""
+from __future__ import annotations
+
+import functools
+import math
+import os
+
+import numpy as np
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "scan_small.txt")
+
+NP_OF = {"int32": np.int32, "int64": np.int64, "float32": np.float32}
+
+
+def wrap(v: int, bits: int) -> int:
+    """Two's complement wrap of a Python integer to ``bits`` bits."""
+    m = 1 << bits
+    v %= m
+    return v - m if v >= m // 2 else v
+
+
+# --------------------------------------------------------------------------
+# golden fixtures
+# --------------------------------------------------------------------------
+
+def load_golden():
+    cases = []
+    with open(GOLDEN) as f:
+        for line in f:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            parts = [p.strip() for p in line.split("|")]
+            name, dtype, op, kind = parts[:4]
+            if kind.startswith("seg"):
+                off = [int(v) for v in parts[4].split()]
+                xs, ys = parts[5].split(), parts[6].split()
+            else:
+                off = None
+                xs, ys = parts[4].split(), parts[5].split()
+            conv = float if dtype == "float32" else int
+            cases.append(dict(name=name, dtype=dtype, op=op, kind=kind, off=off,
+                              x=[conv(v) for v in xs], y=[conv(v) for v in ys]))
+    return cases
+
+
+def check_golden(orc):
+    for c in load_golden():
+        x = np.array(c["x"], dtype=NP_OF[c["dtype"]])
+        excl = c["kind"].endswith("excl")
+        if c["off"] is not None:
+            y = orc.segscan(x, np.array(c["off"], dtype=np.int64), c["dtype"], c["op"], excl)
+        else:
+            y = orc.scan(x, c["dtype"], c["op"], excl)
+        want = c["y"]
+        if c["dtype"] == "float32":
+            got = [float(v) for v in y]
+            assert all(g == w and math.copysign(1, g) == math.copysign(1, w)
+                       for g, w in zip(got, want)), (c["name"], got, want)
+        else:
+            assert [int(v) for v in y] == want, (c["name"], list(y), want)
+
+
+# --------------------------------------------------------------------------
+# closed forms
+# --------------------------------------------------------------------------
+
+def check_closed_forms(orc):
+    n = 1 << 17                                   # crosses the int32 wrap of j(j+1)/2
+    j = np.arange(n, dtype=np.int64)
+    ones32 = np.ones(n, dtype=np.int32)
+    assert np.array_equal(orc.scan(ones32, "int32", "add"), (j + 1).astype(np.int32))
+    assert np.array_equal(orc.scan(ones32, "int32", "add", exclusive=True), j.astype(np.int32))
+    assert np.array_equal(orc.scan(np.ones(n, np.int64), "int64", "add"), j + 1)
+
+    # x_i = i  ->  y_j = j (j + 1) / 2, modulo 2^32 for int32
+    tri = [wrap(k * (k + 1) // 2, 32) for k in range(0, n, 997)]
+    got = orc.scan(j.astype(np.int32), "int32", "add")[::997]
+    assert [int(v) for v in got] == tri
+    got64 = orc.scan(j, "int64", "add")
+    assert np.array_equal(got64, j * (j + 1) // 2)
+
+    # monotone inputs: max of increasing is the identity map, of decreasing is x_0
+    inc = np.arange(-500, 500, dtype=np.int32)
+    dec = inc[::-1].copy()
+    assert np.array_equal(orc.scan(inc, "int32", "max"), inc)
+    assert np.array_equal(orc.scan(dec, "int32", "max"), np.full_like(dec, dec[0]))
+    assert np.array_equal(orc.scan(inc, "int32", "min"), np.full_like(inc, inc[0]))
+    assert np.array_equal(orc.scan(dec, "int32", "min"), dec)
+    inc64 = np.arange(-(1 << 40), -(1 << 40) + 300, dtype=np.int64)
+    assert np.array_equal(orc.scan(inc64, "int64", "max"), inc64)
+    assert np.array_equal(orc.scan(inc64[::-1].copy(), "int64", "min"), inc64[::-1])
+    incf = np.linspace(-3.0, 7.0, 257, dtype=np.float32)
+    assert np.array_equal(orc.scan(incf, "float32", "max"), incf)
+    assert np.array_equal(orc.scan(incf, "float32", "min"), np.full_like(incf, incf[0]))
+
+    # float all-ones: exact prefix j + 1, A_j = j + 1
+    y64, a = orc.scan(np.ones(n, np.float32), "float32", "add", with_absum=True)
+    assert np.array_equal(y64, (j + 1).astype(np.float64))
+    assert np.array_equal(a, (j + 1).astype(np.float64))
+    # bf16 1.0 = 0x3f80: widened exactly, prefix j + 1
+    yb = orc.scan(np.full(n, 0x3F80, np.uint16), "bfloat16", "add")
+    assert np.array_equal(yb, (j + 1).astype(np.float64))
+    # bf16 max of increasing bit patterns of positive numbers is the identity map
+    hb = np.arange(0x3F80, 0x4000, dtype=np.uint16)
+    wide = (hb.astype(np.uint32) << 16).view(np.float32)
+    assert np.array_equal(orc.scan(hb, "bfloat16", "max"), wide)
+    assert np.array_equal(orc.scan(hb, "bfloat16", "min"), np.full_like(wide, wide[0]))
+
+
+# --------------------------------------------------------------------------
+# brute force on tiny inputs
+# --------------------------------------------------------------------------
+
+def _total_order_key(v: float):
+    """Sort key for IEEE totalOrder on non-NaN floats (-0 before +0)."""
+    return (v, math.copysign(1.0, v))
+
+
+def check_brute_force(orc, seed=7):
+    g = np.random.default_rng(seed)
+    for n in (0, 1, 2, 3, 17, 63, 64):
+        for dtype, bits in (("int32", 32), ("int64", 64)):
+            lo, hi = (-(2 ** 31), 2 ** 31) if bits == 32 else (-(2 ** 63), 2 ** 63)
+            x = g.integers(lo, hi, size=n, dtype=np.int64 if bits == 64 else np.int64)
+            x = x.astype(NP_OF[dtype])
+            xs = [int(v) for v in x]
+            for op, f, e in (("add", lambda a, b: a + b, 0),
+                             ("max", max, -(2 ** (bits - 1))),
+                             ("min", min, 2 ** (bits - 1) - 1)):
+                want_in = [wrap(functools.reduce(f, xs[: k + 1]), bits) for k in range(n)]
+                want_ex = [wrap(functools.reduce(f, xs[:k], e), bits) for k in range(n)]
+                assert [int(v) for v in orc.scan(x, dtype, op)] == want_in, (dtype, op, n)
+                assert [int(v) for v in orc.scan(x, dtype, op, exclusive=True)] == want_ex, (dtype, op, n)
+
+        # float32 add: exact sum by math.fsum, A_j by fsum of magnitudes
+        xf = (g.standard_normal(n) * np.exp(g.uniform(-8, 8, n))).astype(np.float32)
+        y64, a = orc.scan(xf, "float32", "add", with_absum=True)
+        for k in range(n):
+            exact = math.fsum(float(v) for v in xf[: k + 1])
+            mag = math.fsum(abs(float(v)) for v in xf[: k + 1])
+            assert abs(y64[k] - exact) <= 1e-15 * mag, (k, y64[k], exact)
+            assert abs(a[k] - mag) <= 1e-15 * mag
+        y64e, ae = orc.scan(xf, "float32", "add", exclusive=True, with_absum=True)
+        for k in range(n):
+            exact = math.fsum(float(v) for v in xf[:k])
+            mag = math.fsum(abs(float(v)) for v in xf[:k])
+            assert abs(y64e[k] - exact) <= 1e-15 * mag and abs(ae[k] - mag) <= 1e-15 * mag
+
+        # float32 max / min under totalOrder, with signed zeros and infinities mixed in
+        pool = np.array([-0.0, 0.0, 1.5, -1.5, np.inf, -np.inf, 3.0, -7.25], dtype=np.float32)
+        xo = pool[g.integers(0, pool.size, n)]
+        for op, pick in (("max", max), ("min", min)):
+            y = orc.scan(xo, "float32", op)
+            for k in range(n):
+                want = pick((float(v) for v in xo[: k + 1]), key=_total_order_key)
+                assert float(y[k]) == want and math.copysign(1, y[k]) == math.copysign(1, want), (op, k)
+
+
+# --------------------------------------------------------------------------
+# invariants and library special cases on larger random inputs
+# --------------------------------------------------------------------------
+
+def check_invariants(orc, seed=11):
+    g = np.random.default_rng(seed)
+    n = 100_003
+    x32 = g.integers(-(2 ** 31), 2 ** 31, size=n, dtype=np.int64).astype(np.int32)
+    x64 = g.integers(-(2 ** 63), 2 ** 63, size=n, dtype=np.int64)
+    for x, dtype, bits in ((x32, "int32", 32), (x64, "int64", 64)):
+        inc = orc.scan(x, dtype, "add")
+        exc = orc.scan(x, dtype, "add", exclusive=True)
+        # y_{N-1} equals the full reduction (Python integers, wrapped)
+        assert int(inc[-1]) == wrap(sum(int(v) for v in x), bits)
+        # exclusive is inclusive shifted by one, identity first
+        assert exc[0] == 0 and np.array_equal(exc[1:], inc[:-1])
+        # numpy's sequential accumulate wraps the same way
+        assert np.array_equal(inc, np.add.accumulate(x, dtype=x.dtype))
+        assert np.array_equal(orc.scan(x, dtype, "max"), np.maximum.accumulate(x))
+        assert np.array_equal(orc.scan(x, dtype, "min"), np.minimum.accumulate(x))
+        info = np.iinfo(x.dtype)
+        excm = orc.scan(x, dtype, "max", exclusive=True)
+        assert excm[0] == info.min and np.array_equal(excm[1:], np.maximum.accumulate(x)[:-1])
+        excn = orc.scan(x, dtype, "min", exclusive=True)
+        assert excn[0] == info.max and np.array_equal(excn[1:], np.minimum.accumulate(x)[:-1])
+        # in-place gives the same bits
+        xi = x.copy()
+        orc.scan(xi, dtype, "add", out=xi)
+        assert np.array_equal(xi, inc)
+        xi = x.copy()
+        orc.scan(xi, dtype, "add", exclusive=True, out=xi)
+        assert np.array_equal(xi, exc)
+
+    # float exactness: small integers as float32 sum exactly in any order
+    xi = g.integers(-1000, 1000, size=1 << 14, endpoint=True).astype(np.float32)
+    y64 = orc.scan(xi, "float32", "add")
+    assert np.array_equal(y64, np.cumsum(xi.astype(np.int64)).astype(np.float64))
+    # f32 max/min equals numpy's accumulate for data without zeros
+    xf = (g.standard_normal(n) * 100).astype(np.float32)
+    xf[xf == 0] = 1.0
+    assert np.array_equal(orc.scan(xf, "float32", "max"), np.maximum.accumulate(xf))
+    assert np.array_equal(orc.scan(xf, "float32", "min"), np.minimum.accumulate(xf))
+    exf = orc.scan(xf, "float32", "max", exclusive=True)
+    assert exf[0] == -np.inf and np.array_equal(exf[1:], np.maximum.accumulate(xf)[:-1])
+    # float add on random data: within FP64 rounding of math.fsum at sampled points
+    y64, a = orc.scan(xf, "float32", "add", with_absum=True)
+    for k in (0, 1, 999, 50_000, n - 1):
+        exact = math.fsum(float(v) for v in xf[: k + 1])
+        assert abs(y64[k] - exact) <= 1e-14 * a[k]
+    y64e = orc.scan(xf, "float32", "add", exclusive=True)
+    assert y64e[0] == 0.0 and np.array_equal(y64e[1:], y64[:-1])
+    # bf16 add equals the float32 add of the widened values, bit for bit
+    hb = g.integers(0, 1 << 16, size=4096, dtype=np.uint16)
+    hb = hb[((hb >> 7) & 0xFF) != 0xFF]            # drop inf / nan patterns
+    wide = (hb.astype(np.uint32) << 16).view(np.float32)
+    yb, ab = orc.scan(hb, "bfloat16", "add", with_absum=True)
+    yf, af = orc.scan(wide, "float32", "add", with_absum=True)
+    assert np.array_equal(yb, yf) and np.array_equal(ab, af)
+
+
+# --------------------------------------------------------------------------
+# compensated-sum pin: cancellation pattern with an exact answer
+# --------------------------------------------------------------------------
+
+def check_cancellation(orc):
+    big = float(2 ** 24)
+    x = np.array([big, 1.0, -big, 1.0] * 256, dtype=np.float32)
+    y64, a = orc.scan(x, "float32", "add", with_absum=True)
+    want = []
+    s = 0
+    for v in x:
+        s += int(v)
+        want.append(float(s))
+    assert np.array_equal(y64, np.array(want))
+    assert a[-1] == 256 * (2 * big + 2)
+    # The same pattern at 2^60 defeats a plain FP64 fold (2^60 + 1 rounds to
+    # 2^60, so 2^60 + 1 - 2^60 would give 0): only a compensated fold returns
+    # the exact small prefixes.  Expected: the exact integer prefix, rounded
+    # once to FP64 by Python's correctly rounded int -> float conversion.
+    huge = float(2 ** 60)
+    x = np.array([huge, 1.0, -huge, 1.0] * 64, dtype=np.float32)
+    y64 = orc.scan(x, "float32", "add")
+    s = 0
+    for k, v in enumerate(x):
+        s += int(v)
+        assert y64[k] == float(s), (k, y64[k], s)
+
+
+# --------------------------------------------------------------------------
+# segmented scan
+# --------------------------------------------------------------------------
+
+def check_segmented(orc, seed=13):
+    g = np.random.default_rng(seed)
+    n = 5000
+    x = g.integers(-1000, 1000, size=n, endpoint=True).astype(np.int32)
+    # one segment == plain scan
+    off1 = np.array([0, n], dtype=np.int64)
+    for op in ("add", "max", "min"):
+        assert np.array_equal(orc.segscan(x, off1, "int32", op), orc.scan(x, "int32", op))
+    # all segments of length one: inclusive gives x, exclusive gives the identity
+    offs = np.arange(n + 1, dtype=np.int64)
+    assert np.array_equal(orc.segscan(x, offs, "int32", "add"), x)
+    assert np.array_equal(orc.segscan(x, offs, "int32", "add", exclusive=True), np.zeros(n, np.int32))
+    assert np.array_equal(orc.segscan(x, offs, "int32", "max", exclusive=True),
+                          np.full(n, np.iinfo(np.int32).min, np.int32))
+    # random segments with empty ones, against a per-segment Python fold
+    cuts = np.sort(g.integers(0, n + 1, size=60))
+    off = np.concatenate([[0], cuts, cuts[:5], [n]]).astype(np.int64)
+    off.sort()
+    for op, f in (("add", lambda a, b: a + b), ("max", max), ("min", min)):
+        got = orc.segscan(x, off, "int32", op)
+        gote = orc.segscan(x, off, "int32", op, exclusive=True)
+        e = {"add": 0, "max": -(2 ** 31), "min": 2 ** 31 - 1}[op]
+        want, wante = [], []
+        for s in range(off.size - 1):
+            acc = e
+            for v in x[off[s]:off[s + 1]]:
+                wante.append(acc)
+                acc = f(acc, int(v))
+                want.append(acc)
+        assert [int(v) for v in got] == want, op
+        assert [int(v) for v in gote] == wante, op
+    # float add per segment: restarts the sum and the magnitude sum
+    xf = g.random(n).astype(np.float32)
+    y64, a = orc.segscan(xf, off, "float32", "add", with_absum=True)
+    for s in range(off.size - 1):
+        lo, hi = off[s], off[s + 1]
+        if hi > lo:
+            assert abs(y64[hi - 1] - math.fsum(float(v) for v in xf[lo:hi])) <= 1e-14 * a[hi - 1]
+            assert a[lo] == abs(float(xf[lo]))
+
+
+ALL_CHECKS = (check_golden, check_closed_forms, check_brute_force, check_invariants,
+              check_cancellation, check_segmented)
+
+
+def failing_checks(orc):
+    """Names of the pin checks that fail (or crash) on ``orc``."""
+    bad = []
+    for chk in ALL_CHECKS:
+        try:
+            chk(orc)
+        except Exception as exc:  # noqa: BLE001 - a crash counts as a failure
+            bad.append(f"{chk.__name__}: {type(exc).__name__}")
+    return bad

@@ -1,0 +1,191 @@
+/*
+ * lscan.h -- C ABI of a single-pass, device-wide scan for AMD MI355X (gfx950).
+ *
+ * Operation (paper, Section 1): given a binary associative operator (+) and
+ * x_0 .. x_{N-1}, the inclusive scan writes y_j = x_0 (+) ... (+) x_j and the
+ * exclusive scan writes y_j = x_0 (+) ... (+) x_{j-1}, with y_0 = e, the
+ * identity of (+).  The device method follows Section 4 of the paper: the
+ * input is cut into M data blocks of L elements, a fixed set of B resident
+ * workgroups takes the blocks round-robin (block i -> workgroup i mod B),
+ * each block is scanned in registers (per-lane values, wave-wide cross-lane
+ * scan, cross-wave pass through LDS), and block prefixes travel between
+ * workgroups through flag words in device memory, so every x is read once
+ * and every y written once in one kernel launch.
+ *
+ * Types and operators:
+ *   LSCAN_I32, LSCAN_I64 : add (wraps modulo 2^32 / 2^64), max, min; exact.
+ *   LSCAN_F32            : add (rounded; see LSCAN_F_COMPENSATED), max, min
+ *                          (IEEE 754 totalOrder on non-NaN values, -0 < +0;
+ *                          exact).  Output float32.
+ *   LSCAN_BF16           : input bfloat16 (2-byte bit patterns), widened
+ *                          exactly to float32; the scan runs in float32 and
+ *                          the output is float32.
+ * Identities: add 0; max: INT_MIN / -inf; min: INT_MAX / +inf.
+ *
+ * Pointers: x, y and offsets are DEVICE pointers owned by the caller, who
+ * keeps them valid until the work completes (stream order).  x and y must be
+ * aligned to their element size; 16-byte alignment selects the vector path.
+ * y == x (in place) is allowed when input and output types are equal
+ * (Section 4.5 of the paper: every element is read once before it is written
+ * once); any other overlap is rejected.  Streams are hipStream_t passed as
+ * void* (NULL = the null stream).  Calls are asynchronous: they validate,
+ * enqueue one kernel launch and return.
+ *
+ * Errors are negative lscan_status values; arguments are checked before any
+ * device work, so a rejected call has no effect.  HIP failures map to
+ * LSCAN_ERR_DEVICE (the HIP code is kept per thread, see
+ * lscan_last_device_error).  A workgroup that waits too long for a block
+ * prefix (a forward-progress failure) stops, and the next lscan_check on
+ * that stream reports LSCAN_ERR_TIMEOUT.
+ *
+ * Thread safety: every entry point may be called from any thread.  Each
+ * (device, stream) pair owns its own flag workspace, so launches on one
+ * stream are ordered and launches on different streams never share flags.
+ */
+#ifndef LSCAN_H
+#define LSCAN_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    LSCAN_I32 = 0,
+    LSCAN_I64 = 1,
+    LSCAN_F32 = 2,
+    LSCAN_BF16 = 3 /* input only; the output is float32 */
+} lscan_dtype;
+
+typedef enum { LSCAN_ADD = 0, LSCAN_MAX = 1, LSCAN_MIN = 2 } lscan_op;
+
+/* flags */
+#define LSCAN_F_COMPENSATED 0x1u /* F32/BF16 add: carry a TwoSum error term */
+#define LSCAN_F_EXCLUSIVE 0x4u   /* lscan_segmented only: exclusive scan */
+
+typedef int32_t lscan_status;
+#define LSCAN_OK 0
+#define LSCAN_PENDING 1
+#define LSCAN_ERR_INVALID_ARG (-1)
+#define LSCAN_ERR_UNSUPPORTED (-2)
+#define LSCAN_ERR_NO_MEMORY (-3)
+#define LSCAN_ERR_DEVICE (-4)
+#define LSCAN_ERR_AGAIN (-5)
+#define LSCAN_ERR_TIMEOUT (-6)
+#define LSCAN_ERR_NOT_FOUND (-7)
+
+/*
+ * lscan_inclusive -- y_j = x_0 (+) ... (+) x_j for j < n (paper Section 1;
+ * device method of Section 4).
+ *   x      device pointer, n elements of dt
+ *   y      device pointer, n elements of the output type (F32 for BF16)
+ *   n      element count, n >= 0; n == 0 is a no-op returning LSCAN_OK
+ *   flags  0 or LSCAN_F_COMPENSATED (F32/BF16 with LSCAN_ADD only, else
+ *          LSCAN_ERR_UNSUPPORTED)
+ * Float add results depend on the association fixed by the launch
+ * parameters; for a fixed parameter set they are deterministic.
+ */
+lscan_status lscan_inclusive(const void *x, void *y, int64_t n, lscan_dtype dt,
+                             lscan_op op, uint32_t flags, void *stream);
+
+/*
+ * lscan_exclusive -- y_0 = e, y_j = x_0 (+) ... (+) x_{j-1} (paper Section 1,
+ * the variant it notes can be derived from the inclusive scan).  Arguments
+ * as lscan_inclusive.
+ */
+lscan_status lscan_exclusive(const void *x, void *y, int64_t n, lscan_dtype dt,
+                             lscan_op op, uint32_t flags, void *stream);
+
+/*
+ * lscan_segmented -- the scan of Section 1 applied independently to each
+ * segment x[offsets[s], offsets[s+1]), s < num_segments, in ONE persistent
+ * launch (the segmented operator on (head flag, value) pairs, which is
+ * associative, so the block method of Section 4 applies unchanged).
+ *   offsets  DEVICE pointer to num_segments + 1 non-decreasing int64 values
+ *            with offsets[0] == 0; empty segments are allowed; n is
+ *            offsets[num_segments], which the caller passes as n_total
+ *   flags    LSCAN_F_EXCLUSIVE for the exclusive form, LSCAN_F_COMPENSATED
+ *            as above
+ * The offsets are not validated on the device (that would need a device
+ * read); malformed offsets give unspecified values in y but stay in bounds:
+ * every access is limited to [0, n_total).
+ */
+lscan_status lscan_segmented(const void *x, void *y, int64_t n_total,
+                             const int64_t *offsets, int64_t num_segments,
+                             lscan_dtype dt, lscan_op op, uint32_t flags,
+                             void *stream);
+
+/*
+ * Launch parameters (the paper's T, K and B of Section 5.1, chosen by
+ * measurement here):
+ *   block_threads     T: threads per workgroup (multiple of 64)
+ *   vectors_per_lane  16-byte input vectors each lane holds per data block
+ *                     (so K = vectors_per_lane * 16 / sizeof(input))
+ *   groups_per_cu     resident workgroups per compute unit; B = this times
+ *                     the CU count, capped by the occupancy limit and by M
+ */
+typedef struct {
+    int32_t block_threads;
+    int32_t vectors_per_lane;
+    int32_t groups_per_cu;
+    int32_t reserved;
+} lscan_params;
+
+/* Number of compiled (block_threads, vectors_per_lane) tile shapes, and the
+ * shape with index idx (groups_per_cu is returned as 0). */
+int32_t lscan_num_tile_shapes(void);
+lscan_status lscan_tile_shape(int32_t idx, lscan_params *out);
+
+/* Default parameters for (dt, op, flags) with segmented != 0 selecting the
+ * segmented kernel; set replaces them (e.g. from an autotuner). */
+lscan_status lscan_get_params(lscan_dtype dt, lscan_op op, uint32_t flags,
+                              int32_t segmented, lscan_params *out);
+lscan_status lscan_set_params(lscan_dtype dt, lscan_op op, uint32_t flags,
+                              int32_t segmented, const lscan_params *p);
+
+/* As lscan_inclusive / lscan_exclusive / lscan_segmented with explicit
+ * parameters (p == NULL: the defaults).  exclusive selects the form for the
+ * plain scan. */
+lscan_status lscan_scan_with_params(const void *x, void *y, int64_t n,
+                                    lscan_dtype dt, lscan_op op,
+                                    uint32_t flags, int32_t exclusive,
+                                    const lscan_params *p, void *stream);
+lscan_status lscan_segmented_with_params(const void *x, void *y,
+                                         int64_t n_total,
+                                         const int64_t *offsets,
+                                         int64_t num_segments, lscan_dtype dt,
+                                         lscan_op op, uint32_t flags,
+                                         const lscan_params *p, void *stream);
+
+/* Shape of the last launch made by the calling thread. */
+typedef struct {
+    int64_t n;             /* elements */
+    int64_t num_blocks;    /* M */
+    int64_t tile_elems;    /* L */
+    int32_t grid;          /* B */
+    int32_t block_threads; /* T */
+    int32_t slot_words;    /* 64-bit flag words per data block */
+    int32_t vector_path;   /* 1 if the 16-byte path was used */
+} lscan_launch_info;
+lscan_status lscan_last_launch(lscan_launch_info *out);
+
+/* Wait for the stream and report LSCAN_ERR_TIMEOUT if a launch on it stopped
+ * waiting for a block prefix since the previous check (the flag is then
+ * cleared), else LSCAN_OK. */
+lscan_status lscan_check(void *stream);
+
+/* Release every flag workspace of the calling thread's current device
+ * (synchronizes the device first). */
+lscan_status lscan_release_workspaces(void);
+
+/* Text of a status code; the HIP error of the last LSCAN_ERR_DEVICE on the
+ * calling thread (0 if none). */
+const char *lscan_status_string(lscan_status s);
+int32_t lscan_last_device_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LSCAN_H */

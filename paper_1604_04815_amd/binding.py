@@ -1,0 +1,263 @@
+"""Python binding of the C ABI in ``include/lscan.h`` (argument marshalling only).
+
+Every scan runs in the HIP kernels of ``liblscan.so``; this module converts
+torch tensors to device pointers, sizes and the current HIP stream, calls the
+C entry point of the same name and turns negative status codes into
+exceptions.  There is no CPU fallback: if the library is not built, or there
+is no GPU, the calls raise.
+
+torch is imported before the library is loaded so that both share one HIP
+runtime (torch ships ``libamdhip64.so.7``, the soname the library links).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "liblscan.so")
+
+I32, I64, F32, BF16 = 0, 1, 2, 3
+ADD, MAX, MIN = 0, 1, 2
+F_COMPENSATED = 0x1
+F_EXCLUSIVE = 0x4
+
+OK, PENDING = 0, 1
+ERR_INVALID_ARG, ERR_UNSUPPORTED, ERR_NO_MEMORY, ERR_DEVICE = -1, -2, -3, -4
+ERR_AGAIN, ERR_TIMEOUT, ERR_NOT_FOUND = -5, -6, -7
+
+OPS = {"add": ADD, "max": MAX, "min": MIN}
+
+
+class LscanError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        self.status = status
+        super().__init__(f"{what}: {status_string(status)} (status {status})")
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("block_threads", ctypes.c_int32), ("vectors_per_lane", ctypes.c_int32),
+                ("groups_per_cu", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class LaunchInfo(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("num_blocks", ctypes.c_int64), ("tile_elems", ctypes.c_int64),
+                ("grid", ctypes.c_int32), ("block_threads", ctypes.c_int32),
+                ("slot_words", ctypes.c_int32), ("vector_path", ctypes.c_int32)]
+
+
+_lib = None
+
+# Every symbol declared in include/lscan.h, with its ctypes signature.
+_vp, _i64, _i32, _u32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_uint32
+SIGNATURES = {
+    "lscan_inclusive": ([_vp, _vp, _i64, _i32, _i32, _u32, _vp], _i32),
+    "lscan_exclusive": ([_vp, _vp, _i64, _i32, _i32, _u32, _vp], _i32),
+    "lscan_segmented": ([_vp, _vp, _i64, _vp, _i64, _i32, _i32, _u32, _vp], _i32),
+    "lscan_num_tile_shapes": ([], _i32),
+    "lscan_tile_shape": ([_i32, ctypes.POINTER(Params)], _i32),
+    "lscan_get_params": ([_i32, _i32, _u32, _i32, ctypes.POINTER(Params)], _i32),
+    "lscan_set_params": ([_i32, _i32, _u32, _i32, ctypes.POINTER(Params)], _i32),
+    "lscan_scan_with_params": ([_vp, _vp, _i64, _i32, _i32, _u32, _i32, ctypes.POINTER(Params), _vp], _i32),
+    "lscan_segmented_with_params": ([_vp, _vp, _i64, _vp, _i64, _i32, _i32, _u32,
+                                     ctypes.POINTER(Params), _vp], _i32),
+    "lscan_last_launch": ([ctypes.POINTER(LaunchInfo)], _i32),
+    "lscan_check": ([_vp], _i32),
+    "lscan_release_workspaces": ([], _i32),
+    "lscan_status_string": ([_i32], ctypes.c_char_p),
+    "lscan_last_device_error": ([], _i32),
+}
+
+
+def load(path: str | None = None):
+    """Load ``liblscan.so`` (raises if it has not been built)."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    import torch  # noqa: F401  -- share torch's HIP runtime
+
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise RuntimeError(f"{p} is not built: run __graft_entry__.build() "
+                           "(python -m paper_1604_04815_amd.build)")
+    lib = ctypes.CDLL(p)
+    for name, (args, res) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    if path is None:
+        _lib = lib
+    return lib
+
+
+def status_string(status: int) -> str:
+    try:
+        return load().lscan_status_string(int(status)).decode()
+    except Exception:  # noqa: BLE001 - used while formatting errors
+        return "status"
+
+
+def _check(status: int, what: str) -> int:
+    if status < 0:
+        if status == ERR_DEVICE:
+            raise LscanError(status, f"{what} (hip error {load().lscan_last_device_error()})")
+        raise LscanError(status, what)
+    return status
+
+
+# ---------------------------------------------------------------------------
+# C entry points under their own names (raw pointers and sizes).
+# ---------------------------------------------------------------------------
+
+def lscan_inclusive(x: int, y: int, n: int, dt: int, op: int, flags: int = 0, stream: int = 0) -> int:
+    return _check(load().lscan_inclusive(x, y, n, dt, op, flags, stream), "lscan_inclusive")
+
+
+def lscan_exclusive(x: int, y: int, n: int, dt: int, op: int, flags: int = 0, stream: int = 0) -> int:
+    return _check(load().lscan_exclusive(x, y, n, dt, op, flags, stream), "lscan_exclusive")
+
+
+def lscan_segmented(x: int, y: int, n_total: int, offsets: int, num_segments: int, dt: int, op: int,
+                    flags: int = 0, stream: int = 0) -> int:
+    return _check(load().lscan_segmented(x, y, n_total, offsets, num_segments, dt, op, flags, stream),
+                  "lscan_segmented")
+
+
+def lscan_scan_with_params(x, y, n, dt, op, flags, exclusive, params: Params | None, stream=0) -> int:
+    p = ctypes.byref(params) if params is not None else None
+    return _check(load().lscan_scan_with_params(x, y, n, dt, op, flags, int(exclusive), p, stream),
+                  "lscan_scan_with_params")
+
+
+def lscan_segmented_with_params(x, y, n_total, offsets, num_segments, dt, op, flags,
+                                params: Params | None, stream=0) -> int:
+    p = ctypes.byref(params) if params is not None else None
+    return _check(load().lscan_segmented_with_params(x, y, n_total, offsets, num_segments, dt, op, flags,
+                                                     p, stream), "lscan_segmented_with_params")
+
+
+def lscan_tile_shapes() -> list[tuple[int, int]]:
+    lib = load()
+    out = []
+    for i in range(lib.lscan_num_tile_shapes()):
+        p = Params()
+        _check(lib.lscan_tile_shape(i, ctypes.byref(p)), "lscan_tile_shape")
+        out.append((p.block_threads, p.vectors_per_lane))
+    return out
+
+
+def lscan_get_params(dt, op, flags=0, segmented=False) -> Params:
+    p = Params()
+    _check(load().lscan_get_params(dt, op, flags, int(segmented), ctypes.byref(p)), "lscan_get_params")
+    return p
+
+
+def lscan_set_params(dt, op, flags, segmented, params: Params) -> None:
+    _check(load().lscan_set_params(dt, op, flags, int(segmented), ctypes.byref(params)), "lscan_set_params")
+
+
+def lscan_last_launch() -> LaunchInfo:
+    info = LaunchInfo()
+    _check(load().lscan_last_launch(ctypes.byref(info)), "lscan_last_launch")
+    return info
+
+
+def lscan_check(stream: int = 0) -> None:
+    _check(load().lscan_check(stream), "lscan_check")
+
+
+def lscan_release_workspaces() -> None:
+    _check(load().lscan_release_workspaces(), "lscan_release_workspaces")
+
+
+# ---------------------------------------------------------------------------
+# torch tensor marshalling
+# ---------------------------------------------------------------------------
+
+def dtype_code(t) -> int:
+    import torch
+
+    table = {torch.int32: I32, torch.int64: I64, torch.float32: F32, torch.bfloat16: BF16}
+    if t.dtype not in table:
+        raise TypeError(f"unsupported dtype {t.dtype}")
+    return table[t.dtype]
+
+
+def out_dtype(t):
+    import torch
+
+    return torch.float32 if t.dtype == torch.bfloat16 else t.dtype
+
+
+def _stream(stream) -> int:
+    import torch
+
+    if stream is None:
+        return torch.cuda.current_stream().cuda_stream
+    return stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+
+
+def _flat(t, name):
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if t.dim() != 1 or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous 1-D tensor")
+    return t
+
+
+def _out_for(x, out):
+    import torch
+
+    if out is None:
+        return torch.empty(x.shape[0], dtype=out_dtype(x), device=x.device)
+    _flat(out, "out")
+    if out.dtype != out_dtype(x) or out.shape[0] != x.shape[0]:
+        raise ValueError("out has the wrong dtype or length")
+    return out
+
+
+def inclusive(x, op="add", compensated=False, out=None, stream=None, params: Params | None = None):
+    """y_j = x_0 (+) ... (+) x_j on the device; returns y."""
+    _flat(x, "x")
+    y = _out_for(x, out)
+    flags = F_COMPENSATED if compensated else 0
+    if params is None:
+        lscan_inclusive(x.data_ptr(), y.data_ptr(), x.shape[0], dtype_code(x), OPS[op], flags, _stream(stream))
+    else:
+        lscan_scan_with_params(x.data_ptr(), y.data_ptr(), x.shape[0], dtype_code(x), OPS[op], flags, 0,
+                               params, _stream(stream))
+    return y
+
+
+def exclusive(x, op="add", compensated=False, out=None, stream=None, params: Params | None = None):
+    """y_0 = e, y_j = x_0 (+) ... (+) x_{j-1} on the device; returns y."""
+    _flat(x, "x")
+    y = _out_for(x, out)
+    flags = F_COMPENSATED if compensated else 0
+    if params is None:
+        lscan_exclusive(x.data_ptr(), y.data_ptr(), x.shape[0], dtype_code(x), OPS[op], flags, _stream(stream))
+    else:
+        lscan_scan_with_params(x.data_ptr(), y.data_ptr(), x.shape[0], dtype_code(x), OPS[op], flags, 1,
+                               params, _stream(stream))
+    return y
+
+
+def segmented(x, offsets, op="add", exclusive=False, compensated=False, out=None, stream=None,
+              params: Params | None = None):
+    """Scan of every segment x[off[s]:off[s+1]] in one launch; returns y."""
+    import torch
+
+    _flat(x, "x")
+    _flat(offsets, "offsets")
+    if offsets.dtype != torch.int64:
+        raise TypeError("offsets must be int64")
+    y = _out_for(x, out)
+    flags = (F_COMPENSATED if compensated else 0) | (F_EXCLUSIVE if exclusive else 0)
+    nseg = offsets.shape[0] - 1
+    if params is None:
+        lscan_segmented(x.data_ptr(), y.data_ptr(), x.shape[0], offsets.data_ptr(), nseg, dtype_code(x),
+                        OPS[op], flags, _stream(stream))
+    else:
+        lscan_segmented_with_params(x.data_ptr(), y.data_ptr(), x.shape[0], offsets.data_ptr(), nseg,
+                                    dtype_code(x), OPS[op], flags, params, _stream(stream))
+    return y

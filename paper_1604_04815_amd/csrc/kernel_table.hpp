@@ -1,0 +1,65 @@
+// kernel_table.hpp -- what the host runtime knows about each compiled scan
+// kernel.  Shared by the runtime and the kernel instantiation units only.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lscan {
+
+// Arguments of one persistent scan launch.
+struct ScanArgs {
+    const void* x;            // input, n elements
+    void* y;                  // output, n elements (may equal x)
+    int64_t n;                // N
+    int64_t num_blocks;       // M = ceil(N / L)
+    const int64_t* offsets;   // segmented: S + 1 offsets (device), else null
+    int64_t num_segments;     // S
+    uint64_t* slots;          // M * slot_words flag words (epoch tag | data)
+    uint32_t* ctrl;           // [0] last epoch tag, [1] exit counter, [2] timeout flag
+    uint64_t spin_limit;      // wall-clock ticks one wait may last
+    int32_t exclusive;        // 1: exclusive scan
+    int32_t vec_ok;           // 1: x and y allow full-width vector access
+};
+
+using LaunchFn = hipError_t (*)(const ScanArgs&, int grid, hipStream_t);
+
+struct KernelEntry {
+    const void* func;         // the __global__ function (occupancy queries)
+    LaunchFn launch;
+    int32_t block_threads;    // T
+    int32_t vectors_per_lane; // vector loads per lane per data block
+    int32_t elems_per_vec;    // elements per lane per vector load
+    int32_t slot_words;       // 64-bit flag words per data block
+    int32_t in_bytes;         // sizeof input element
+    int32_t out_bytes;        // sizeof output element
+    int64_t tile_elems;       // L
+};
+
+// Operator codes (dtype x operator x precision).
+enum OpCode : int {
+    kI32Add = 0, kI32Max, kI32Min,
+    kI64Add, kI64Max, kI64Min,
+    kF32Add, kF32AddComp, kF32Max, kF32Min,
+    kBF16Add, kBF16AddComp, kBF16Max, kBF16Min,
+    kNumOpCodes
+};
+
+// Compiled tile shapes (T, vectors per lane).
+constexpr int kNumShapes = 5;
+constexpr int kShapeThreads[kNumShapes] = {256, 512, 512, 256, 1024};
+constexpr int kShapeVectors[kNumShapes] = {8, 8, 4, 16, 4};
+
+// table[segmented][opcode][shape]
+using KernelTable = KernelEntry[2][kNumOpCodes][kNumShapes];
+
+void register_i32_kernels(KernelTable& t);
+void register_i64_kernels(KernelTable& t);
+void register_f32_kernels(KernelTable& t);
+void register_bf16_kernels(KernelTable& t);
+void register_i32_seg_kernels(KernelTable& t);
+void register_i64_seg_kernels(KernelTable& t);
+void register_f32_seg_kernels(KernelTable& t);
+void register_bf16_seg_kernels(KernelTable& t);
+
+}  // namespace lscan

@@ -1,0 +1,412 @@
+// scan_kernel.hpp -- the persistent single-pass scan kernel for gfx950.
+//
+// Method (paper, Section 4, restated for CDNA4):
+//   * The input is cut into M data blocks of L = T * R * E elements.  A fixed
+//     grid of B resident workgroups takes the blocks round-robin: block i is
+//     processed by workgroup i mod B, in increasing i (Section 4, cyclic
+//     distribution; no atomic ticket decides the order).
+//   * Per block, each lane loads R vectors of E consecutive elements; wave w
+//     owns R consecutive "rows" of 64 * E elements, so every vector load of a
+//     wave reads one contiguous span (coalesced, each x read once).
+//   * Intra-wave local scan (Algorithm 2): a sequential scan of each lane's E
+//     elements, a wave64 cross-lane scan of the lane totals per row (DPP, in
+//     place of warp shuffles), and the rows chained through their totals.
+//   * Intra-block local scan (Algorithm 3): wave totals go through LDS; wave
+//     0 folds them into the block aggregate A(i); every wave folds the totals
+//     of the waves before it.
+//   * Inter-block communication (Algorithm 4), re-designed: A(i) is published
+//     at once in a flag slot (epoch tag and data in one 64-bit word per 32
+//     data bits, written with a device-scope atomic store, so one store is
+//     one indivisible update, as the paper requires of its (u, v) pair).  A
+//     workgroup already holds P(i - B), the inclusive prefix through its own
+//     previous block, so it obtains
+//         P(i - 1) = P(i - B) (+) A(i - B + 1) (+) ... (+) A(i - 1)
+//     from the aggregates of the B - 1 blocks in between, read 64 slots per
+//     wave load, without waiting for any other workgroup's prefix.  The
+//     serial prefix chain of the paper (one cross-workgroup hop per block)
+//     becomes one hop per block plus a chain of M / B steps that stays inside
+//     each workgroup, and the association is fixed, so float results are
+//     deterministic for a given (T, R, B).
+//   * Intra-block global scan (Algorithm 5): each element becomes
+//     P(i - 1) (+) wave prefix (+) row prefix (+) lane prefix (+) its in-lane
+//     scan value, and is stored once, coalesced.
+//
+// Forward progress: all B workgroups must be resident at once (Section 5.1
+// notes the deadlock otherwise); the host caps B by the occupancy limit.  A
+// wait that outlasts spin_limit raises a timeout flag and the workgroup stops,
+// so every wave always exits.
+#pragma once
+
+#include <type_traits>
+
+#include "kernel_table.hpp"
+#include "scan_ops.hpp"
+
+namespace lscan {
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+
+// Streaming vector access (non-temporal: each byte is touched once).
+template <class T, int E>
+__device__ __forceinline__ void load_vector(const T* p, T (&out)[E])
+{
+    constexpr int kBytes = int(sizeof(T)) * E;
+    static_assert(kBytes == 16 || kBytes == 8, "16- or 8-byte vectors");
+    if constexpr (kBytes == 16) {
+        u32x4 w = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(p));
+        __builtin_memcpy(out, &w, 16);
+    } else {
+        u32x2 w = __builtin_nontemporal_load(reinterpret_cast<const u32x2*>(p));
+        __builtin_memcpy(out, &w, 8);
+    }
+}
+
+template <class T, int E>
+__device__ __forceinline__ void store_vector(T* p, const T (&v)[E])
+{
+    static_assert(int(sizeof(T)) * E == 16, "16-byte output vectors");
+    u32x4 w;
+    __builtin_memcpy(&w, v, 16);
+    __builtin_nontemporal_store(w, reinterpret_cast<u32x4*>(p));
+}
+
+// ---------------------------------------------------------------------------
+// Flag slots: one 64-bit word per 32 bits of payload, (tag << 32) | data.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t slot_load(const uint64_t* p)
+{
+    return __hip_atomic_load(const_cast<uint64_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void slot_store(uint64_t* p, uint64_t w)
+{
+    __hip_atomic_store(p, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Lanes 0 .. W-1 each publish one word of the (wave-uniform) value v.
+template <class V>
+__device__ __forceinline__ void publish_slot(uint64_t* slot, const V& v, uint32_t tag, int lane)
+{
+    constexpr int W = sizeof(V) / 4;
+    uint32_t w[W];
+    __builtin_memcpy(w, &v, sizeof(V));
+    if (lane < W) {
+        uint32_t mine = w[0];
+#pragma unroll
+        for (int k = 1; k < W; ++k) mine = (lane == k) ? w[k] : mine;
+        slot_store(slot + lane, (uint64_t(tag) << 32) | mine);
+    }
+}
+
+// Re-read a flag word until it carries this launch's tag, or give up after
+// `limit` wall-clock ticks (ok = false).
+__device__ __forceinline__ uint64_t await_word(const uint64_t* p, uint64_t w, uint32_t tag,
+                                               uint64_t limit, bool& ok)
+{
+    if (uint32_t(w >> 32) == tag || !ok) return w;
+    const uint64_t t0 = wall_clock64();
+    do {
+        __builtin_amdgcn_s_sleep(1);
+        w = slot_load(p);
+        if (uint32_t(w >> 32) == tag) return w;
+    } while (wall_clock64() - t0 < limit);
+    ok = false;
+    return w;
+}
+
+// Fold of the aggregates in slots [lo, lo + cnt) in index order, read by one
+// wave: 64 consecutive slots per load round, each round reduced with the
+// cross-lane scan (a fixed tree), rounds folded left to right.
+template <class Op>
+__device__ typename Op::V window_fold(const uint64_t* slots, int64_t lo, int64_t cnt, uint32_t tag,
+                                      uint64_t limit, int lane, bool& ok)
+{
+    using V = typename Op::V;
+    constexpr int W = sizeof(V) / 4;
+    constexpr int QC = (W == 1) ? 8 : (W == 2) ? 4 : 2;  // load rounds in flight
+    V acc = Op::identity();
+    for (int64_t q0 = 0; q0 < cnt; q0 += 64 * QC) {
+        uint64_t w[QC][W];
+#pragma unroll
+        for (int q = 0; q < QC; ++q) {
+            const int64_t j = q0 + 64 * q + lane;
+#pragma unroll
+            for (int k = 0; k < W; ++k)
+                w[q][k] = (j < cnt) ? slot_load(slots + (lo + j) * W + k) : (uint64_t(tag) << 32);
+        }
+#pragma unroll
+        for (int q = 0; q < QC; ++q) {
+            const int64_t j = q0 + 64 * q + lane;
+            if (j < cnt) {
+#pragma unroll
+                for (int k = 0; k < W; ++k)
+                    w[q][k] = await_word(slots + (lo + j) * W + k, w[q][k], tag, limit, ok);
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < QC; ++q) {
+            if (q0 + 64 * q < cnt) {
+                const int64_t j = q0 + 64 * q + lane;
+                V v = Op::identity();
+                if (j < cnt) {
+                    uint32_t d[W];
+#pragma unroll
+                    for (int k = 0; k < W; ++k) d[k] = uint32_t(w[q][k]);
+                    __builtin_memcpy(&v, d, sizeof(V));
+                }
+                const V s = wave_inclusive_scan<Op>(v);
+                acc = Op::combine(acc, read_lane(s, 63));
+            }
+        }
+    }
+    return acc;
+}
+
+// First index k in [lo, hi) with off[k] >= v, or hi.
+__device__ __forceinline__ int64_t lower_bound_i64(const int64_t* off, int64_t lo, int64_t hi, int64_t v)
+{
+    while (lo < hi) {
+        const int64_t mid = lo + ((hi - lo) >> 1);
+        if (off[mid] < v)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+template <class BaseOp, bool SEG>
+struct ScanOpOf {
+    using type = BaseOp;
+};
+template <class BaseOp>
+struct ScanOpOf<BaseOp, true> {
+    using type = Seg<BaseOp>;
+};
+
+template <class BaseOp, int T, int R, bool SEG>
+__global__ void __launch_bounds__(T) scan_kernel(ScanArgs a)
+{
+    using SOp = typename ScanOpOf<BaseOp, SEG>::type;
+    using V = typename SOp::V;
+    using In = typename BaseOp::In;
+    using Out = typename BaseOp::Out;
+    constexpr int E = BaseOp::E;
+    constexpr int NWAVE = T / 64;
+    constexpr int W = sizeof(V) / 4;
+    constexpr int ROW = 64 * E;                  // elements per wave-row
+    constexpr int64_t L = int64_t(T) * R * E;    // elements per data block
+    static_assert(T % 64 == 0 && NWAVE <= 16, "wave64 workgroups of up to 1024 threads");
+
+    __shared__ V s_wave_total[2][NWAVE];
+    __shared__ V s_block_prefix[2];
+    __shared__ int s_abort[2];
+
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const In* x = static_cast<const In*>(a.x);
+    Out* y = static_cast<Out*>(a.y);
+    const int64_t B = gridDim.x;
+    const uint32_t tag = __hip_atomic_load(a.ctrl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1u;
+
+    V carry = SOp::identity();  // wave 0: P(i - B), the prefix through this group's previous block
+    int parity = 0;
+    for (int64_t i = blockIdx.x; i < a.num_blocks; i += B, parity ^= 1) {
+        const int64_t tile0 = i * L;
+        const int64_t lane0 = tile0 + int64_t(wave) * (R * ROW) + int64_t(lane) * E;
+        const bool full = a.vec_ok && (tile0 + L <= a.n);
+
+        // -- segment heads inside this lane's vectors (segmented scans only)
+        uint32_t head[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) head[r] = 0;
+        if constexpr (SEG) {
+            const int64_t S = a.num_segments;
+            const int64_t s_lo = lower_bound_i64(a.offsets, 0, S, tile0);
+            const int64_t s_hi = lower_bound_i64(a.offsets, s_lo, S, tile0 + L);
+            if (s_lo < s_hi) {
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const int64_t p = lane0 + int64_t(r) * ROW;
+                    int64_t k = lower_bound_i64(a.offsets, s_lo, s_hi, p);
+                    uint32_t h = 0;
+                    for (; k < s_hi; ++k) {
+                        const int64_t o = a.offsets[k];
+                        if (o >= p + E) break;
+                        h |= 1u << uint32_t(o - p);
+                    }
+                    head[r] = h;
+                }
+            }
+        }
+
+        // -- 1. load (each x read exactly once) and lift to scan values
+        V e[R][E];
+        if (full) {
+            In raw[R][E];
+#pragma unroll
+            for (int r = 0; r < R; ++r) load_vector<In, E>(x + lane0 + int64_t(r) * ROW, raw[r]);
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+#pragma unroll
+                for (int k = 0; k < E; ++k) {
+                    if constexpr (SEG)
+                        e[r][k] = SOp::make(BaseOp::lift(raw[r][k]), (head[r] >> k) & 1u);
+                    else
+                        e[r][k] = BaseOp::lift(raw[r][k]);
+                }
+        } else {
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+#pragma unroll
+                for (int k = 0; k < E; ++k) {
+                    const int64_t p = lane0 + int64_t(r) * ROW + k;
+                    if (p < a.n) {
+                        if constexpr (SEG)
+                            e[r][k] = SOp::make(BaseOp::lift(x[p]), (head[r] >> k) & 1u);
+                        else
+                            e[r][k] = BaseOp::lift(x[p]);
+                    } else {
+                        e[r][k] = SOp::identity();
+                    }
+                }
+        }
+
+        // -- 2. intra-wave local scan: in-lane, then across lanes per row
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int k = 1; k < E; ++k) e[r][k] = SOp::combine(e[r][k - 1], e[r][k]);
+
+        V lane_prefix[R];  // exclusive cross-lane prefix within the row
+        V row_total[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const V s = wave_inclusive_scan<SOp>(e[r][E - 1]);
+            row_total[r] = read_lane(s, 63);
+            lane_prefix[r] = wave_shift_right<SOp>(s);
+        }
+        V row_prefix[R];  // rows chained in order (wave-uniform)
+        row_prefix[0] = SOp::identity();
+#pragma unroll
+        for (int r = 1; r < R; ++r) row_prefix[r] = SOp::combine(row_prefix[r - 1], row_total[r - 1]);
+        const V wave_total = SOp::combine(row_prefix[R - 1], row_total[R - 1]);
+
+        // -- 3. intra-block local scan through LDS
+        if (lane == 0) s_wave_total[parity][wave] = wave_total;
+        __syncthreads();
+
+        // -- 4. inter-block communication (wave 0)
+        if (wave == 0) {
+            V agg = s_wave_total[parity][0];
+#pragma unroll
+            for (int w = 1; w < NWAVE; ++w) agg = SOp::combine(agg, s_wave_total[parity][w]);
+            publish_slot(a.slots + i * W, agg, tag, lane);
+
+            const int64_t cnt = (i < B - 1) ? i : (B - 1);
+            bool ok = true;
+            const V win = window_fold<SOp>(a.slots, i - cnt, cnt, tag, a.spin_limit, lane, ok);
+            const V prefix = SOp::combine(carry, win);  // P(i - 1)
+            carry = SOp::combine(prefix, agg);          // P(i)
+            const bool abort = __ballot(!ok) != 0;
+            if (lane == 0) {
+                s_block_prefix[parity] = prefix;
+                s_abort[parity] = abort ? 1 : 0;
+                if (abort) __hip_atomic_store(a.ctrl + 2, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
+        __syncthreads();
+        if (s_abort[parity]) break;
+
+        // -- 5. intra-block global scan and one coalesced store per vector
+        V prefix = s_block_prefix[parity];
+        for (int w = 0; w < wave; ++w) prefix = SOp::combine(prefix, s_wave_total[parity][w]);
+
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const V lp = SOp::combine(SOp::combine(prefix, row_prefix[r]), lane_prefix[r]);
+            Out out[E];
+            if (!a.exclusive) {
+#pragma unroll
+                for (int k = 0; k < E; ++k) {
+                    const V v = SOp::combine(lp, e[r][k]);
+                    if constexpr (SEG)
+                        out[k] = BaseOp::lower(v.v);
+                    else
+                        out[k] = BaseOp::lower(v);
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < E; ++k) {
+                    const V v = (k == 0) ? lp : SOp::combine(lp, e[r][k - 1]);
+                    if constexpr (SEG)
+                        out[k] = ((head[r] >> k) & 1u) ? BaseOp::lower(BaseOp::identity()) : BaseOp::lower(v.v);
+                    else
+                        out[k] = BaseOp::lower(v);
+                }
+            }
+            const int64_t p = lane0 + int64_t(r) * ROW;
+            if (full) {
+                store_vector<Out, E>(y + p, out);
+            } else {
+#pragma unroll
+                for (int k = 0; k < E; ++k)
+                    if (p + k < a.n) y[p + k] = out[k];
+            }
+        }
+    }
+
+    // Every workgroup counts itself out; the last one advances the epoch so
+    // the next launch on this workspace uses a fresh tag (no memset needed).
+    if (threadIdx.x == 0) {
+        const uint32_t prev = __hip_atomic_fetch_add(a.ctrl + 1, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (prev == uint32_t(gridDim.x) - 1u) {
+            __hip_atomic_store(a.ctrl + 1, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(a.ctrl, tag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Registration helpers used by the instantiation units.
+// ---------------------------------------------------------------------------
+template <class BaseOp, bool SEG, int T, int R>
+hipError_t launch_scan(const ScanArgs& a, int grid, hipStream_t stream)
+{
+    (void)hipGetLastError();  // a stale error from earlier work must not be read as this launch's
+    hipLaunchKernelGGL((scan_kernel<BaseOp, T, R, SEG>), dim3(grid), dim3(T), 0, stream, a);
+    return hipGetLastError();
+}
+
+template <class BaseOp, bool SEG, int S>
+KernelEntry make_entry()
+{
+    constexpr int T = kShapeThreads[S];
+    constexpr int R = kShapeVectors[S];
+    using SOp = typename ScanOpOf<BaseOp, SEG>::type;
+    KernelEntry k;
+    k.func = reinterpret_cast<const void*>(&scan_kernel<BaseOp, T, R, SEG>);
+    k.launch = &launch_scan<BaseOp, SEG, T, R>;
+    k.block_threads = T;
+    k.vectors_per_lane = R;
+    k.elems_per_vec = BaseOp::E;
+    k.slot_words = int(sizeof(typename SOp::V) / 4);
+    k.in_bytes = int(sizeof(typename BaseOp::In));
+    k.out_bytes = int(sizeof(typename BaseOp::Out));
+    k.tile_elems = int64_t(T) * R * BaseOp::E;
+    return k;
+}
+
+template <class BaseOp, bool SEG>
+void fill_row(KernelTable& t, int opcode)
+{
+    KernelEntry* row = t[SEG ? 1 : 0][opcode];
+    row[0] = make_entry<BaseOp, SEG, 0>();
+    row[1] = make_entry<BaseOp, SEG, 1>();
+    row[2] = make_entry<BaseOp, SEG, 2>();
+    row[3] = make_entry<BaseOp, SEG, 3>();
+    row[4] = make_entry<BaseOp, SEG, 4>();
+    static_assert(kNumShapes == 5, "one entry per compiled shape");
+}
+
+}  // namespace lscan

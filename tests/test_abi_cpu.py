@@ -1,0 +1,123 @@
+"""The C ABI library on the CPU host: it loads, exports every symbol that
+include/lscan.h declares, and rejects bad arguments before any device work
+(no GPU call is made by these tests)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1604_04815_amd import binding
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lscan.h")
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lscan_[a-z_0-9]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(binding.LIB_PATH):
+        pytest.fail("liblscan.so is not built (run __graft_entry__.build())")
+    return binding.load()
+
+
+def test_header_declares_the_abi():
+    syms = declared_symbols()
+    for name in ("lscan_inclusive", "lscan_exclusive", "lscan_segmented", "lscan_check",
+                 "lscan_status_string"):
+        assert name in syms
+
+
+def test_every_declared_symbol_is_exported(lib):
+    for name in declared_symbols():
+        assert hasattr(lib, name), name
+        assert name in binding.SIGNATURES, f"binding lacks {name}"
+
+
+def test_status_strings(lib):
+    for code in (0, -1, -2, -3, -4, -5, -6, -7):
+        assert lib.lscan_status_string(code)
+    assert binding.status_string(-1) == "invalid argument"
+
+
+def test_tile_shapes(lib):
+    shapes = binding.lscan_tile_shapes()
+    assert len(shapes) >= 1
+    for t, r in shapes:
+        assert t % 64 == 0 and 64 <= t <= 1024 and r >= 1
+
+
+def test_default_params_roundtrip(lib):
+    p = binding.lscan_get_params(binding.I32, binding.ADD)
+    assert (p.block_threads, p.vectors_per_lane) in binding.lscan_tile_shapes()
+    assert p.groups_per_cu >= 1
+    q = binding.Params(p.block_threads, p.vectors_per_lane, p.groups_per_cu + 1, 0)
+    binding.lscan_set_params(binding.I32, binding.ADD, 0, False, q)
+    r = binding.lscan_get_params(binding.I32, binding.ADD)
+    assert r.groups_per_cu == p.groups_per_cu + 1
+    binding.lscan_set_params(binding.I32, binding.ADD, 0, False, p)
+    with pytest.raises(binding.LscanError):
+        binding.lscan_set_params(binding.I32, binding.ADD, 0, False, binding.Params(100, 3, 1, 0))
+
+
+FAKE_X = 1 << 20     # never dereferenced: every call below is rejected or a no-op
+FAKE_Y = 1 << 30
+
+
+@pytest.mark.parametrize("call,status", [
+    # n < 0
+    (lambda l: l.lscan_inclusive(FAKE_X, FAKE_Y, -1, 0, 0, 0, None), binding.ERR_INVALID_ARG),
+    # bad dtype / op / flags
+    (lambda l: l.lscan_inclusive(FAKE_X, FAKE_Y, 8, 9, 0, 0, None), binding.ERR_INVALID_ARG),
+    (lambda l: l.lscan_inclusive(FAKE_X, FAKE_Y, 8, 0, 5, 0, None), binding.ERR_INVALID_ARG),
+    (lambda l: l.lscan_inclusive(FAKE_X, FAKE_Y, 8, 0, 0, 0x100, None), binding.ERR_INVALID_ARG),
+    # the exclusive flag belongs to lscan_segmented only
+    (lambda l: l.lscan_inclusive(FAKE_X, FAKE_Y, 8, 0, 0, binding.F_EXCLUSIVE, None), binding.ERR_INVALID_ARG),
+    # null pointers with n > 0
+    (lambda l: l.lscan_inclusive(None, FAKE_Y, 8, 0, 0, 0, None), binding.ERR_INVALID_ARG),
+    (lambda l: l.lscan_exclusive(FAKE_X, None, 8, 0, 0, 0, None), binding.ERR_INVALID_ARG),
+    # compensation only for float add
+    (lambda l: l.lscan_inclusive(FAKE_X, FAKE_Y, 8, binding.I32, binding.ADD, binding.F_COMPENSATED, None),
+     binding.ERR_UNSUPPORTED),
+    (lambda l: l.lscan_inclusive(FAKE_X, FAKE_Y, 8, binding.F32, binding.MAX, binding.F_COMPENSATED, None),
+     binding.ERR_UNSUPPORTED),
+    # misaligned element pointers
+    (lambda l: l.lscan_inclusive(FAKE_X + 2, FAKE_Y, 8, binding.I32, 0, 0, None), binding.ERR_INVALID_ARG),
+    (lambda l: l.lscan_inclusive(FAKE_X, FAKE_Y + 4, 8, binding.I64, 0, 0, None), binding.ERR_INVALID_ARG),
+    # partial overlap (in place is allowed, a shifted alias is not)
+    (lambda l: l.lscan_inclusive(FAKE_X, FAKE_X + 4, 8, binding.I32, 0, 0, None), binding.ERR_INVALID_ARG),
+    # bf16 in place is impossible (2-byte input, 4-byte output)
+    (lambda l: l.lscan_inclusive(FAKE_X, FAKE_X, 8, binding.BF16, 0, 0, None), binding.ERR_INVALID_ARG),
+    # n == 0 is a no-op, even with null pointers
+    (lambda l: l.lscan_inclusive(None, None, 0, 0, 0, 0, None), binding.OK),
+    (lambda l: l.lscan_exclusive(None, None, 0, binding.F32, binding.MIN, 0, None), binding.OK),
+    # segmented: negative count, zero segments with elements, null offsets, bad flag
+    (lambda l: l.lscan_segmented(FAKE_X, FAKE_Y, 8, FAKE_X, -1, 0, 0, 0, None), binding.ERR_INVALID_ARG),
+    (lambda l: l.lscan_segmented(FAKE_X, FAKE_Y, 8, FAKE_X, 0, 0, 0, 0, None), binding.ERR_INVALID_ARG),
+    (lambda l: l.lscan_segmented(FAKE_X, FAKE_Y, 8, None, 2, 0, 0, 0, None), binding.ERR_INVALID_ARG),
+    (lambda l: l.lscan_segmented(FAKE_X, FAKE_Y, 8, FAKE_X + 4, 2, 0, 0, 0, None), binding.ERR_INVALID_ARG),
+    (lambda l: l.lscan_segmented(FAKE_X, FAKE_Y, 8, FAKE_X, 2, 0, 0, 0x80, None), binding.ERR_INVALID_ARG),
+    (lambda l: l.lscan_segmented(None, None, 0, None, 0, 0, 0, binding.F_EXCLUSIVE, None), binding.OK),
+])
+def test_argument_validation(lib, call, status):
+    assert call(lib) == status
+
+
+def test_params_validation(lib):
+    bad_shape = binding.Params(192, 3, 1, 0)
+    st = lib.lscan_scan_with_params(FAKE_X, FAKE_Y, 8, 0, 0, 0, 0, ctypes.byref(bad_shape), None)
+    assert st == binding.ERR_UNSUPPORTED
+    neg = binding.Params(0, 0, -1, 0)
+    st = lib.lscan_scan_with_params(FAKE_X, FAKE_Y, 8, 0, 0, 0, 0, ctypes.byref(neg), None)
+    assert st == binding.ERR_INVALID_ARG
+
+
+def test_raising_wrappers(lib):
+    with pytest.raises(binding.LscanError) as ei:
+        binding.lscan_inclusive(FAKE_X, FAKE_Y, -5, binding.I32, binding.ADD)
+    assert ei.value.status == binding.ERR_INVALID_ARG

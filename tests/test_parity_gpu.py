@@ -1,0 +1,183 @@
+"""Parity of the HIP scan (through the C ABI) with the CPU oracle, element by
+element, on seeded inputs at sizes that span several tiles, several rounds of
+the persistent grid and ragged tails."""
+import numpy as np
+import pytest
+import torch
+
+from gpu_util import TAU_COMP, compare, log, make_input, to_device, to_host
+
+pytestmark = pytest.mark.gpu
+
+CASES = [
+    ("int32", "add", False), ("int32", "max", False), ("int32", "min", False),
+    ("int64", "add", False), ("int64", "max", False), ("int64", "min", False),
+    ("float32", "add", False), ("float32", "add", True), ("float32", "max", False), ("float32", "min", False),
+    ("bfloat16", "add", False), ("bfloat16", "add", True), ("bfloat16", "max", False), ("bfloat16", "min", False),
+]
+
+
+def sizes_for(gpu_lib, dtype, op, comp):
+    """Edge sizes around the tile length L and the grid span B*L of the default launch."""
+    import ctypes
+    x = torch.zeros(1 << 16, dtype={"int32": torch.int32, "int64": torch.int64, "float32": torch.float32,
+                                    "bfloat16": torch.bfloat16}[dtype], device="cuda")
+    fn = gpu_lib.inclusive
+    fn(x, op, comp)
+    info = gpu_lib.lscan_last_launch()
+    L = int(info.tile_elems)
+    # grid of a launch with many blocks
+    big = torch.zeros(L * 2048, dtype=x.dtype, device="cuda")
+    fn(big, op, comp)
+    B = int(gpu_lib.lscan_last_launch().grid)
+    del big
+    return L, B, [1, 2, 3, 63, 64, 65, 255, 256, 257, 1000, L - 1, L, L + 1, 5 * L + 7,
+                  B * L - 1, B * L + 1, 2 * B * L + L // 2 + 3]
+
+
+@pytest.mark.parametrize("dtype,op,comp", CASES, ids=[f"{d}-{o}{'-comp' if c else ''}" for d, o, c in CASES])
+def test_inclusive_exclusive(gpu_lib, dtype, op, comp):
+    L, B, sizes = sizes_for(gpu_lib, dtype, op, comp)
+    log(f"[parity] {dtype} {op} comp={comp} L={L} B={B}")
+    for k, n in enumerate(sizes):
+        x = make_input(dtype, op, n, seed=1000 + k)
+        xd = to_device(x, dtype)
+        for excl in (False, True):
+            fn = gpu_lib.exclusive if excl else gpu_lib.inclusive
+            y = fn(xd, op, comp)
+            gpu_lib.lscan_check(torch.cuda.current_stream().cuda_stream)
+            compare(to_host(y), x, dtype, op, excl, comp, what=f"{dtype}/{op}/n={n}/excl={excl}")
+
+
+@pytest.mark.parametrize("shape", range(5))
+@pytest.mark.parametrize("groups", [1, 2, 4])
+def test_every_tile_shape(gpu_lib, shape, groups):
+    t, r = gpu_lib.lscan_tile_shapes()[shape]
+    p = gpu_lib.Params(t, r, groups, 0)
+    log(f"[shapes] T={t} R={r} groups/CU={groups}")
+    for dtype, op, comp in (("int32", "add", False), ("int64", "max", False), ("float32", "add", False),
+                            ("float32", "add", True), ("bfloat16", "min", False)):
+        for n in (777, 3_000_001):
+            x = make_input(dtype, op, n, seed=77 + n + shape)
+            xd = to_device(x, dtype)
+            for excl in (False, True):
+                fn = gpu_lib.exclusive if excl else gpu_lib.inclusive
+                y = fn(xd, op, comp, params=p)
+                gpu_lib.lscan_check(torch.cuda.current_stream().cuda_stream)
+                info = gpu_lib.lscan_last_launch()
+                assert info.block_threads == t
+                compare(to_host(y), x, dtype, op, excl, comp, what=f"T={t} R={r} g={groups} {dtype}/{op}/n={n}")
+
+
+def test_float_results_are_deterministic(gpu_lib):
+    x = make_input("float32", "add", 20_000_003, seed=5)
+    xd = to_device(x, "float32")
+    for comp in (False, True):
+        a = to_host(gpu_lib.inclusive(xd, "add", comp))
+        b = to_host(gpu_lib.inclusive(xd, "add", comp))
+        assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
+
+
+def test_float_exact_cases(gpu_lib):
+    # small integers as float32: every association is exact, so the float
+    # path must be bit-exact (catches lost or doubled elements)
+    from paper_1604_04815_amd import workloads as w
+    n = 1 << 14
+    for k in range(3):
+        x = w.uniform_int(n, -1000, 1000, seed=k).astype(np.float32)
+        want = np.cumsum(x.astype(np.int64)).astype(np.float32)
+        for comp in (False, True):
+            got = to_host(gpu_lib.inclusive(to_device(x, "float32"), "add", comp))
+            assert np.array_equal(got, want)
+    # all ones: y_j = j + 1 exactly while below 2^24
+    n = 3_000_000
+    ones = np.ones(n, np.float32)
+    got = to_host(gpu_lib.inclusive(to_device(ones, "float32"), "add"))
+    assert np.array_equal(got, np.arange(1, n + 1, dtype=np.float32))
+    hb = np.full(n, 0x3F80, np.uint16)  # bf16 1.0
+    got = to_host(gpu_lib.inclusive(to_device(hb, "bfloat16"), "add"))
+    assert np.array_equal(got, np.arange(1, n + 1, dtype=np.float32))
+
+
+def test_compensated_cancellation(gpu_lib):
+    # (2^24, 1, -2^24, 1, ...): the exact prefixes after each cancellation are
+    # small integers that float32 represents; the compensated scan returns
+    # them exactly, and within 2e-7 * A_j everywhere
+    big = float(2 ** 24)
+    x = np.array([big, 1.0, -big, 1.0] * 250_000, dtype=np.float32)
+    got = to_host(gpu_lib.inclusive(to_device(x, "float32"), "add", True))
+    exact = np.cumsum(x.astype(np.float64))
+    idx = np.arange(2, x.size, 4)
+    assert np.array_equal(got[idx].astype(np.float64), exact[idx])
+    compare(got, x, "float32", "add", False, True, what="cancellation")
+
+
+def test_in_place(gpu_lib):
+    for dtype, op in (("int32", "add"), ("int64", "min"), ("float32", "max"), ("float32", "add")):
+        n = 4_000_037
+        x = make_input(dtype, op, n, seed=3)
+        xd = to_device(x, dtype)
+        gpu_lib.inclusive(xd, op, out=xd)
+        compare(to_host(xd), x, dtype, op, False, what=f"in-place {dtype}/{op}")
+        xd = to_device(x, dtype)
+        gpu_lib.exclusive(xd, op, out=xd)
+        compare(to_host(xd), x, dtype, op, True, what=f"in-place excl {dtype}/{op}")
+
+
+def test_unaligned_pointers(gpu_lib):
+    for dtype, op in (("int32", "add"), ("int64", "add"), ("float32", "min"), ("bfloat16", "add")):
+        n = 2_000_003
+        x = make_input(dtype, op, n + 1, seed=9)
+        base = to_device(x, dtype)
+        xd = base[1:]
+        y_base = torch.empty(n + 1, dtype=gpu_lib.out_dtype(base), device="cuda")
+        y = gpu_lib.inclusive(xd, op, out=y_base[1:])
+        info = gpu_lib.lscan_last_launch()
+        assert info.vector_path == 0
+        compare(to_host(y), x[1:], dtype, op, False, what=f"unaligned {dtype}/{op}")
+
+
+def test_repeated_launches_reuse_flags(gpu_lib):
+    # flag slots are never cleared between launches (epoch tags): many
+    # launches of varying sizes on one stream must all be right
+    rng = np.random.default_rng(2024)
+    for k in range(60):
+        n = int(rng.integers(1, 3_000_000))
+        dtype, op = [("int32", "add"), ("int64", "max"), ("float32", "min")][k % 3]
+        x = make_input(dtype, op, n, seed=500 + k)
+        y = gpu_lib.inclusive(to_device(x, dtype), op)
+        compare(to_host(y), x, dtype, op, False, what=f"repeat {k} n={n}")
+    gpu_lib.lscan_check(torch.cuda.current_stream().cuda_stream)
+
+
+def test_other_stream(gpu_lib):
+    s = torch.cuda.Stream()
+    x = make_input("int32", "add", 5_000_000, seed=1)
+    xd = to_device(x, "int32")
+    torch.cuda.synchronize()
+    with torch.cuda.stream(s):
+        y = gpu_lib.inclusive(xd, "add")
+    s.synchronize()
+    gpu_lib.lscan_check(s.cuda_stream)
+    compare(to_host(y), x, "int32", "add", False, what="side stream")
+
+
+def test_max_min_special_floats(gpu_lib):
+    pool = np.array([-0.0, 0.0, np.inf, -np.inf, 1.0, -1.0, 3.5e38, -3.5e38, 1e-45, -1e-45],
+                    dtype=np.float32)
+    rng = np.random.default_rng(4)
+    x = pool[rng.integers(0, pool.size, 1_000_003)]
+    for op in ("max", "min"):
+        for excl in (False, True):
+            fn = gpu_lib.exclusive if excl else gpu_lib.inclusive
+            y = fn(to_device(x, "float32"), op)
+            compare(to_host(y), x, "float32", op, excl, what=f"special {op}")
+
+
+def test_int_wraparound(gpu_lib):
+    n = 3_000_000
+    x = np.full(n, 2 ** 31 - 1, dtype=np.int32)
+    compare(to_host(gpu_lib.inclusive(to_device(x, "int32"), "add")), x, "int32", "add", False, what="wrap32")
+    x64 = np.full(n, 2 ** 62 + 12345, dtype=np.int64)
+    compare(to_host(gpu_lib.inclusive(to_device(x64, "int64"), "add")), x64, "int64", "add", False,
+            what="wrap64")

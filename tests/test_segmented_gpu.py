@@ -1,0 +1,83 @@
+"""Parity of the segmented scan (one persistent launch over many arrays) with
+the oracle's per-segment scans."""
+import numpy as np
+import pytest
+import torch
+
+from gpu_util import compare, log, make_input, to_device, to_host
+
+pytestmark = pytest.mark.gpu
+
+
+def run(gpu_lib, x, off, dtype, op, excl=False, comp=False, params=None):
+    xd = to_device(x, dtype)
+    od = torch.from_numpy(off).to("cuda")
+    y = gpu_lib.segmented(xd, od, op, exclusive=excl, compensated=comp, params=params)
+    gpu_lib.lscan_check(torch.cuda.current_stream().cuda_stream)
+    return to_host(y)
+
+
+CASES = [("int32", "add", False), ("int32", "max", False), ("int64", "add", False), ("int64", "min", False),
+         ("float32", "add", False), ("float32", "add", True), ("float32", "max", False),
+         ("bfloat16", "add", False), ("bfloat16", "add", True), ("bfloat16", "min", False)]
+
+
+@pytest.mark.parametrize("dtype,op,comp", CASES, ids=[f"{d}-{o}{'-comp' if c else ''}" for d, o, c in CASES])
+def test_log_uniform_segments(gpu_lib, dtype, op, comp):
+    from paper_1604_04815_amd import workloads as w
+    off = w.segment_offsets(4096, 1 << 13, seed=w.seed_for(3))
+    n = int(off[-1])
+    x = make_input(dtype, op, n, seed=31)
+    log(f"[seg] {dtype} {op} comp={comp} n={n}")
+    for excl in (False, True):
+        got = run(gpu_lib, x, off, dtype, op, excl, comp)
+        compare(got, x, dtype, op, excl, comp, offsets=off, what=f"seg {dtype}/{op}/excl={excl}")
+
+
+def test_one_segment_equals_plain(gpu_lib):
+    n = 3_333_333
+    x = make_input("int32", "add", n, seed=2)
+    off = np.array([0, n], dtype=np.int64)
+    got = run(gpu_lib, x, off, "int32", "add")
+    plain = to_host(gpu_lib.inclusive(to_device(x, "int32"), "add"))
+    assert np.array_equal(got, plain)
+    compare(got, x, "int32", "add", False, what="one segment")
+
+
+def test_all_length_one(gpu_lib):
+    n = 200_003
+    x = make_input("int32", "add", n, seed=3)
+    off = np.arange(n + 1, dtype=np.int64)
+    assert np.array_equal(run(gpu_lib, x, off, "int32", "add"), x)
+    assert np.array_equal(run(gpu_lib, x, off, "int32", "add", excl=True), np.zeros(n, np.int32))
+    xf = make_input("float32", "max", n, seed=4)
+    got = run(gpu_lib, xf, off, "float32", "max", excl=True)
+    assert np.all(got == -np.inf)
+
+
+def test_empty_and_boundary_segments(gpu_lib):
+    info_x = torch.zeros(1 << 16, dtype=torch.int32, device="cuda")
+    gpu_lib.segmented(info_x, torch.tensor([0, 1 << 16], dtype=torch.int64, device="cuda"))
+    L = int(gpu_lib.lscan_last_launch().tile_elems)
+    lens = [0, 0, L, L - 1, L + 1, 0, 1, 0, 2 * L, 3, L // 2, 0, 5 * L + 11, 64, 0, 0]
+    off = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    n = int(off[-1])
+    for dtype, op in (("int32", "add"), ("int64", "max"), ("float32", "add")):
+        x = make_input(dtype, op, n, seed=6)
+        for excl in (False, True):
+            got = run(gpu_lib, x, off, dtype, op, excl)
+            compare(got, x, dtype, op, excl, offsets=off, what=f"boundary {dtype}/{op}/excl={excl}")
+
+
+@pytest.mark.parametrize("shape", range(5))
+def test_segmented_every_shape(gpu_lib, shape):
+    from paper_1604_04815_amd import workloads as w
+    t, r = gpu_lib.lscan_tile_shapes()[shape]
+    off = w.segment_offsets(1000, 1 << 12, seed=77 + shape)
+    n = int(off[-1])
+    for dtype, op, comp in (("int32", "add", False), ("float32", "add", True)):
+        x = make_input(dtype, op, n, seed=8)
+        for groups in (1, 2):
+            p = gpu_lib.Params(t, r, groups, 0)
+            got = run(gpu_lib, x, off, dtype, op, False, comp, params=p)
+            compare(got, x, dtype, op, False, comp, offsets=off, what=f"seg T={t} R={r} g={groups} {dtype}")

@@ -1,0 +1,371 @@
+#!/usr/bin/env python3
+"""Benchmark of the single-pass device-wide scan on one MI355X.
+
+One step = one inclusive scan (all stages of the method: tiled loads, wave
+and block scans, inter-block prefix hand-off, fix-up and stores) of the
+workload "int32 add, N = 2^28, x uniform in [-1024, 1024]", inputs resident
+in HBM.  The headline value is scan GB/s = 2 * N * sizeof(int32) / t, with t
+the mean device time per step measured with HIP events on the stream the
+kernel is launched on.
+
+Prints ONE JSON line on stdout.  Besides the contract keys it carries
+  roofline      the scan kernel against the 8 TB/s HBM peak, with the HBM
+                traffic measured by rocprofv3 counters (from profiles/) when
+                the kernel sources still match the profiled build,
+  cpu_baseline  the sequential CPU oracle timed on this host on the same
+                array,
+  configs       the other workloads (int64 add, int32 max, float32 add plain
+                and compensated, bf16 -> float32, a 4096-array segmented scan
+                against 4096 plain launches, and the 2^20 latency case), plus
+                a device copy of the same size as the practical ceiling.
+
+Progress lines go to stderr.  ``--gpus N`` with N > 1 is refused: this build
+runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import glob
+import hashlib
+import json
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "traffic_int32_add_2p28.txt")
+
+
+def log(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    files = sorted(glob.glob(os.path.join(ROOT, "paper_1604_04815_amd", "csrc", "*")))
+    for f in files:
+        if f.endswith((".hip", ".hpp", ".cpp", ".h")):
+            h.update(os.path.basename(f).encode())
+            h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic():
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or
+    None when it is missing or was taken on different kernel sources."""
+    if not os.path.exists(PROFILE_TRAFFIC):
+        return None
+    kv = {}
+    for line in open(PROFILE_TRAFFIC):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    try:
+        return float(kv["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+# ---------------------------------------------------------------------------
+# device timing
+# ---------------------------------------------------------------------------
+
+def time_steps(fn, steps: int, warmup: int):
+    """Run fn warmup + steps times on the current stream; returns
+    (mean ms per step over the whole timed region, per-step ms list)."""
+    import torch
+
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    begin, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    stops = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    torch.cuda.synchronize()
+    begin.record()
+    for k in range(steps):
+        starts[k].record()
+        fn()
+        stops[k].record()
+    end.record()
+    torch.cuda.synchronize()
+    per = [s.elapsed_time(e) for s, e in zip(starts, stops)]
+    return begin.elapsed_time(end) / steps, per
+
+
+def pct(values, q):
+    v = sorted(values)
+    if not v:
+        return float("nan")
+    k = min(len(v) - 1, max(0, int(round(q / 100.0 * (len(v) - 1)))))
+    return v[k]
+
+
+def rate_entry(nbytes: float, n: int, ms: float, per=None):
+    d = {"ms": round(ms, 5), "gbs": round(nbytes / (ms * 1e-3) / 1e9, 1),
+         "gelem_s": round(n / (ms * 1e-3) / 1e9, 2),
+         "frac_hbm_peak": round(nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    if per:
+        d["ms_p50"] = round(pct(per, 50), 5)
+        d["ms_min"] = round(min(per), 5)
+        d["ms_p99"] = round(pct(per, 99), 5)
+    return d
+
+
+# ---------------------------------------------------------------------------
+# workloads
+# ---------------------------------------------------------------------------
+
+def to_device(x, dtype):
+    import numpy as np
+    import torch
+
+    if dtype == "bfloat16":
+        return torch.from_numpy(x.view(np.int16)).view(torch.bfloat16).to("cuda")
+    return torch.from_numpy(x).to("cuda")
+
+
+def bench_plain(binding, x_host, dtype, op, comp, steps, warmup, oracle_check=False):
+    import torch
+
+    xd = to_device(x_host, dtype)
+    n = xd.shape[0]
+    y = torch.empty(n, dtype=binding.out_dtype(xd), device="cuda")
+    fn = lambda: binding.inclusive(xd, op, comp, out=y)  # noqa: E731
+    ms, per = time_steps(fn, steps, warmup)
+    binding.lscan_check(torch.cuda.current_stream().cuda_stream)
+    info = binding.lscan_last_launch()
+    in_b = 2 if dtype == "bfloat16" else xd.element_size()
+    nbytes = n * (in_b + y.element_size())
+    entry = rate_entry(nbytes, n, ms, per)
+    entry.update({"n": n, "dtype": dtype, "op": op, "compensated": comp, "bytes": nbytes,
+                  "grid": info.grid, "block_threads": info.block_threads, "tile_elems": info.tile_elems,
+                  "num_blocks": info.num_blocks})
+    if oracle_check:
+        import oracle
+
+        y64, a = oracle.scan(x_host, dtype, op, with_absum=True)
+        ratio, j = oracle.float_error_ratio(y.cpu().numpy(), y64, a)
+        entry["max_error_ratio"] = ratio
+        entry["error_ratio_argmax"] = j
+    del xd, y
+    torch.cuda.empty_cache()
+    return entry
+
+
+def bench_copy(n, steps, warmup):
+    import torch
+
+    a = torch.empty(n, dtype=torch.int32, device="cuda").fill_(1)
+    b = torch.empty_like(a)
+    ms, per = time_steps(lambda: b.copy_(a), steps, warmup)
+    e = rate_entry(2 * 4 * n, n, ms, per)
+    del a, b
+    torch.cuda.empty_cache()
+    return e
+
+
+def bench_segmented(binding, workloads, steps, warmup):
+    """4096 arrays, log-uniform lengths in [1, 2^20]: one persistent
+    segmented launch against 4096 plain launches on one stream."""
+    import numpy as np
+    import torch
+
+    off = workloads.segment_offsets(4096, 1 << 20, workloads.seed_for(3))
+    n = int(off[-1])
+    out = {}
+    for dtype in ("int32", "float32"):
+        if dtype == "int32":
+            x = workloads.uniform_int(n, -1000, 1000, workloads.seed_for(3, 1))
+        else:
+            x = workloads.uniform01_f32(n, workloads.seed_for(3, 2))
+        xd = to_device(x, dtype)
+        od = torch.from_numpy(off).to("cuda")
+        y = torch.empty_like(xd)
+        ms_seg, per = time_steps(lambda: binding.segmented(xd, od, "add", out=y), steps, warmup)
+        seg_y = y.clone()
+        views = [(xd[int(off[s]):int(off[s + 1])], y[int(off[s]):int(off[s + 1])]) for s in range(4096)]
+
+        def plain_all():
+            for xs, ys in views:
+                if xs.shape[0]:
+                    binding.inclusive(xs, "add", out=ys)
+
+        ms_plain, _ = time_steps(plain_all, max(2, steps // 5), 1)
+        binding.lscan_check(torch.cuda.current_stream().cuda_stream)
+        same = bool(torch.equal(seg_y, y)) if dtype == "int32" else None
+        nbytes = n * 8
+        e = rate_entry(nbytes, n, ms_seg, per)
+        e.update({"n": n, "segments": 4096, "plain_4096_launches_ms": round(ms_plain, 4),
+                  "speedup_vs_plain_launches": round(ms_plain / ms_seg, 2)})
+        if same is not None:
+            e["bit_equal_to_plain_launches"] = same
+        out[f"segmented_4096_{dtype}_add"] = e
+        del xd, y, seg_y, views, od
+        torch.cuda.empty_cache()
+    return out
+
+
+def bench_latency(binding, workloads, steps):
+    """N = 2^20 int32 add: launch-bound; device time per launch and the
+    host time of one call + synchronize."""
+    import torch
+
+    x = workloads.uniform_int(1 << 20, -1000, 1000, workloads.seed_for(0))
+    xd = to_device(x, "int32")
+    y = torch.empty_like(xd)
+    ms, per = time_steps(lambda: binding.inclusive(xd, "add", out=y), max(steps, 50), 5)
+    host = []
+    for _ in range(max(steps, 50)):
+        t0 = time.perf_counter()
+        binding.inclusive(xd, "add", out=y)
+        torch.cuda.synchronize()
+        host.append((time.perf_counter() - t0) * 1e3)
+    e = rate_entry(8 * (1 << 20), 1 << 20, ms, per)
+    e.update({"host_call_sync_ms_p50": round(pct(host, 50), 4), "host_call_sync_ms_p99": round(pct(host, 99), 4)})
+    return e
+
+
+def cpu_baseline(x_host, budget_s: float):
+    """The sequential oracle (one core) on the same array, repeated for about
+    budget_s seconds; median rate."""
+    import oracle
+
+    oracle.build(force=False)
+    times = []
+    t_start = time.perf_counter()
+    while True:
+        t0 = time.perf_counter_ns()
+        oracle.scan(x_host, "int32", "add")
+        times.append((time.perf_counter_ns() - t0) * 1e-9)
+        if len(times) >= 2 and time.perf_counter() - t_start >= budget_s:
+            break
+    t = statistics.median(times)
+    n = x_host.shape[0]
+    return {"value": round(2 * 4 * n / t / 1e9, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
+            "sample": f"the full int32 add N=2^28 array, {len(times)} sequential passes (median "
+                      f"{t:.3f} s each, {sum(times):.1f} s total) on one host core",
+            "gelem_s": round(n / t / 1e9, 3)}
+
+
+def main(argv=None) -> int:
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--only", default="", help="'1a' runs only the headline scan and a same-size copy")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    args = ap.parse_args(argv)
+
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the scan is not sharded "
+              "across GPUs in this build", file=sys.stderr)
+        return 2
+    if "WORLD_SIZE" in os.environ and int(os.environ["WORLD_SIZE"]) > 1:
+        print("bench.py runs on one GPU only", file=sys.stderr)
+        return 2
+
+    import torch
+
+    from paper_1604_04815_amd import binding, workloads
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 2
+    binding.load()
+    torch.cuda.init()
+    dev = torch.cuda.get_device_properties(0)
+    log(f"device {dev.name}, {dev.multi_processor_count} CUs")
+
+    n = 1 << 28
+    x = workloads.uniform_int(n, -1024, 1024, workloads.seed_for(1))
+    log("headline: int32 add N=2^28")
+    head = bench_plain(binding, x, "int32", "add", False, args.steps, args.warmup)
+    log(f"  {head['gbs']} GB/s, {head['ms']} ms/step, grid {head['grid']} x {head['block_threads']}")
+    copy = bench_copy(n, args.steps, args.warmup)
+    log(f"  device copy of the same size: {copy['gbs']} GB/s")
+
+    configs = {"copy_int32_2p28": copy}
+    if args.only != "1a":
+        log("int64 add N=2^27")
+        configs["int64_add_2p27"] = bench_plain(
+            binding, workloads.int64_half_open(1 << 27, -(2 ** 31), 2 ** 31, workloads.seed_for(1, 1)),
+            "int64", "add", False, args.steps, args.warmup)
+        log("int32 max N=2^28")
+        configs["int32_max_2p28"] = bench_plain(
+            binding, workloads.full_range_int32(1 << 28, workloads.seed_for(1, 2)),
+            "int32", "max", False, args.steps, args.warmup)
+        xf = workloads.signed_lognormal_f32(1 << 27, workloads.seed_for(2))
+        for comp in (False, True):
+            log(f"float32 add N=2^27 compensated={comp}")
+            configs[f"float32_add_2p27{'_compensated' if comp else ''}"] = bench_plain(
+                binding, xf, "float32", "add", comp, args.steps, args.warmup, oracle_check=True)
+        del xf
+        xb = workloads.bf16_unit(1 << 27, workloads.seed_for(2, 1))
+        for comp in (False, True):
+            log(f"bf16 -> float32 add N=2^27 compensated={comp}")
+            configs[f"bf16_add_2p27{'_compensated' if comp else ''}"] = bench_plain(
+                binding, xb, "bfloat16", "add", comp, args.steps, args.warmup, oracle_check=True)
+        del xb
+        log("segmented: 4096 arrays")
+        configs.update(bench_segmented(binding, workloads, args.steps, args.warmup))
+        log("latency: int32 add N=2^20")
+        configs["int32_add_2p20_latency"] = bench_latency(binding, workloads, args.steps)
+        try:
+            xd = to_device(x, "int32")
+            yd = torch.empty_like(xd)
+            ms, _ = time_steps(lambda: torch.cumsum(xd, 0, dtype=torch.int32, out=yd), 5, 1)
+            configs["torch_cumsum_int32_2p28_context"] = rate_entry(8 * n, n, ms)
+            del xd, yd
+        except Exception as exc:  # noqa: BLE001 - context only
+            log(f"torch.cumsum context skipped: {exc}")
+
+    cpu = None
+    if not args.no_cpu:
+        log(f"CPU oracle baseline (~{args.cpu_seconds:.0f} s)")
+        cpu = cpu_baseline(x, args.cpu_seconds)
+        cpu["cores_available"] = len(os.sched_getaffinity(0))
+
+    achieved = head["bytes"] / (head["ms"] * 1e-3) / 1e9
+    traffic = read_traffic()
+    record = {
+        "metric": "scan GB/s (2N*bytes), % HBM peak; batched p50/p99 latency vs plain launches",
+        "value": round(achieved, 1),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(head["ms"], 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": "inclusive scan, add, int32, N=2^28, x uniform in [-1024, 1024] (seeded)",
+                   "n": n, "bytes_per_step": head["bytes"], "grid": head["grid"],
+                   "block_threads": head["block_threads"], "tile_elems": head["tile_elems"],
+                   "parallelism": "single GPU"},
+        "gelem_per_s": head["gelem_s"],
+        "frac_hbm_peak": round(achieved / HBM_PEAK_GBS, 4),
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "algorithmic_bytes_per_launch": head["bytes"]},
+        "cpu_baseline": cpu,
+        "step_ms_p50": head.get("ms_p50"),
+        "step_ms_p99": head.get("ms_p99"),
+        "configs": configs,
+    }
+    print(json.dumps(record), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

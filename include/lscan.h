@@ -124,6 +124,14 @@ lscan_status lscan_segmented(const void *x, void *y, int64_t n_total,
  *                     (so K = vectors_per_lane * 16 / sizeof(input))
  *   groups_per_cu     resident workgroups per compute unit; B = this times
  *                     the CU count, capped by the occupancy limit and by M
+ * The persistent grid needs all B workgroups resident at once (paper,
+ * Section 5.1).  Before the first launch of a (kernel, groups_per_cu) pair
+ * on a device, the library runs that kernel once in a test mode in which
+ * every workgroup only waits (at most 20 ms) for all B to arrive; if they do
+ * not, it lowers groups_per_cu and tests again, and it caches the answer.
+ * The test synchronizes the stream, so the first call of a shape must not be
+ * made while the stream is being captured into a graph
+ * (LSCAN_ERR_UNSUPPORTED).
  */
 typedef struct {
     int32_t block_threads;
@@ -167,6 +175,8 @@ typedef struct {
     int32_t block_threads; /* T */
     int32_t slot_words;    /* 64-bit flag words per data block */
     int32_t vector_path;   /* 1 if the 16-byte path was used */
+    int32_t groups_per_cu; /* workgroups per CU of the launch */
+    int32_t occupancy;     /* workgroups per CU the occupancy query allows */
 } lscan_launch_info;
 lscan_status lscan_last_launch(lscan_launch_info *out);
 

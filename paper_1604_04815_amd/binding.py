@@ -43,7 +43,8 @@ class Params(ctypes.Structure):
 class LaunchInfo(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("num_blocks", ctypes.c_int64), ("tile_elems", ctypes.c_int64),
                 ("grid", ctypes.c_int32), ("block_threads", ctypes.c_int32),
-                ("slot_words", ctypes.c_int32), ("vector_path", ctypes.c_int32)]
+                ("slot_words", ctypes.c_int32), ("vector_path", ctypes.c_int32),
+                ("groups_per_cu", ctypes.c_int32), ("occupancy", ctypes.c_int32)]
 
 
 _lib = None

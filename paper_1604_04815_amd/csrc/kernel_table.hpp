@@ -16,10 +16,13 @@ struct ScanArgs {
     const int64_t* offsets;   // segmented: S + 1 offsets (device), else null
     int64_t num_segments;     // S
     uint64_t* slots;          // M * slot_words flag words (epoch tag | data)
-    uint32_t* ctrl;           // [0] last epoch tag, [1] exit counter, [2] timeout flag
+    uint32_t* ctrl;           // [0] last epoch tag, [1] exit counter, [2] timeout flag,
+                              // [4] residency arrivals, [5] residency failure, [6] residency exits
     uint64_t spin_limit;      // wall-clock ticks one wait may last
     int32_t exclusive;        // 1: exclusive scan
     int32_t vec_ok;           // 1: x and y allow full-width vector access
+    int32_t residency_check;  // 1: only test that all workgroups are resident at once, then exit
+    int32_t pad_;
 };
 
 using LaunchFn = hipError_t (*)(const ScanArgs&, int grid, hipStream_t);
@@ -46,9 +49,9 @@ enum OpCode : int {
 };
 
 // Compiled tile shapes (T, vectors per lane).
-constexpr int kNumShapes = 5;
-constexpr int kShapeThreads[kNumShapes] = {256, 512, 512, 256, 1024};
-constexpr int kShapeVectors[kNumShapes] = {8, 8, 4, 16, 4};
+constexpr int kNumShapes = 10;
+constexpr int kShapeThreads[kNumShapes] = {256, 512, 512, 256, 1024, 1024, 512, 256, 256, 1024};
+constexpr int kShapeVectors[kNumShapes] = {8, 8, 4, 16, 4, 2, 2, 4, 2, 1};
 
 // table[segmented][opcode][shape]
 using KernelTable = KernelEntry[2][kNumOpCodes][kNumShapes];

@@ -45,10 +45,18 @@ thread_local lscan_launch_info t_last_launch = {};
 // the grid is not making progress (e.g. not all workgroups are resident).
 constexpr double kSpinLimitSeconds = 2.0;
 
+// A co-residency test waits this long for the whole grid to arrive.
+constexpr double kResidencyWaitSeconds = 0.02;
+
 struct DeviceInfo {
     int cu_count = 0;
     uint64_t spin_limit = 0;
+    uint64_t residency_limit = 0;
     int occupancy[2][kNumOpCodes][kNumShapes];
+    // groups per CU proven resident together (0: none yet) and the smallest
+    // count that failed the test (0: none failed)
+    int resident_ok[2][kNumOpCodes][kNumShapes];
+    int resident_fail[2][kNumOpCodes][kNumShapes];
 };
 
 struct Workspace {
@@ -79,11 +87,29 @@ lscan_status device_error(hipError_t e)
     return LSCAN_ERR_DEVICE;
 }
 
+// Defaults measured on MI355X (gfx950) with N = 2^27..2^28 arrays: shape
+// index into kShapeThreads/kShapeVectors and workgroups per CU (capped later
+// by the occupancy limit and the co-residency test).
 void init_params_locked()
 {
     if (g_params_init) return;
-    for (int s = 0; s < 2; ++s)
-        for (int o = 0; o < kNumOpCodes; ++o) g_params[s][o] = Params{1, 2};  // T=512, 8 vectors, 2 groups/CU
+    const Params t256x8{0, 5}, t256x16{3, 3}, t1024x4{4, 1}, comp_bf16{3, 2};
+    for (int o = kI32Add; o <= kI32Min; ++o) g_params[0][o] = t256x8;
+    for (int o = kI64Add; o <= kI64Min; ++o) g_params[0][o] = t256x16;
+    g_params[0][kF32Add] = t256x8;
+    g_params[0][kF32AddComp] = t1024x4;
+    g_params[0][kF32Max] = t256x8;
+    g_params[0][kF32Min] = t256x8;
+    g_params[0][kBF16Add] = t256x16;
+    g_params[0][kBF16AddComp] = comp_bf16;
+    g_params[0][kBF16Max] = t256x16;
+    g_params[0][kBF16Min] = t256x16;
+    // segmented kernels: the per-tile head search adds latency, so fewer
+    // groups per CU measured best
+    for (int o = 0; o < kNumOpCodes; ++o) {
+        g_params[1][o] = g_params[0][o];
+        if (g_params[1][o].groups_per_cu > 3) g_params[1][o].groups_per_cu = 3;
+    }
     g_params_init = true;
 }
 
@@ -143,9 +169,14 @@ lscan_status device_info_locked(int dev, DeviceInfo** out)
         e = hipDeviceGetAttribute(&wall_khz, hipDeviceAttributeWallClockRate, dev);
         if (e != hipSuccess || wall_khz <= 0) wall_khz = 100000;  // 100 MHz constant clock
         info.spin_limit = uint64_t(double(wall_khz) * 1000.0 * kSpinLimitSeconds);
-        for (auto& a : info.occupancy)
-            for (auto& b : a)
-                for (int& c : b) c = -1;
+        info.residency_limit = uint64_t(double(wall_khz) * 1000.0 * kResidencyWaitSeconds);
+        for (int s = 0; s < 2; ++s)
+            for (int o = 0; o < kNumOpCodes; ++o)
+                for (int h = 0; h < kNumShapes; ++h) {
+                    info.occupancy[s][o][h] = -1;
+                    info.resident_ok[s][o][h] = 0;
+                    info.resident_fail[s][o][h] = 0;
+                }
         it = g_dev.emplace(dev, info).first;
     }
     *out = &it->second;
@@ -166,13 +197,13 @@ lscan_status workspace_locked(int dev, hipStream_t stream, size_t words, Workspa
             if (e != hipSuccess) return device_error(e);
         }
         if (ws.words < words) {
+            const size_t alloc = std::max<size_t>(words, std::max<size_t>(ws.words * 2, size_t(1) << 14));
             if (ws.slots) {
                 e = hipFree(ws.slots);
                 if (e != hipSuccess) return device_error(e);
                 ws.slots = nullptr;
                 ws.words = 0;
             }
-            const size_t alloc = std::max<size_t>(words, std::max<size_t>(ws.words * 2, size_t(1) << 14));
             e = hipMalloc(reinterpret_cast<void**>(&ws.slots), alloc * sizeof(uint64_t));
             if (e != hipSuccess) {
                 (void)hipGetLastError();
@@ -201,6 +232,58 @@ lscan_status workspace_locked(int dev, hipStream_t stream, size_t words, Workspa
         if (need_reset) ws.launches = 0;
     }
     *out = &ws;
+    return LSCAN_OK;
+}
+
+// Launch the kernel in its co-residency test mode with `groups` workgroups
+// per CU and report whether they were all resident at once.
+lscan_status test_residency_locked(const KernelEntry& k, int cu_count, int groups, uint64_t limit,
+                                   Workspace* ws, hipStream_t stream, bool* ok)
+{
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(stream, &cap) == hipSuccess && cap != hipStreamCaptureStatusNone)
+        return LSCAN_ERR_UNSUPPORTED;  // run one eager call of this shape before capturing
+    hipError_t e = hipMemsetAsync(ws->ctrl + 4, 0, 3 * sizeof(uint32_t), stream);
+    if (e != hipSuccess) return device_error(e);
+    ScanArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.ctrl = ws->ctrl;
+    a.slots = ws->slots;
+    a.spin_limit = limit;
+    a.residency_check = 1;
+    e = k.launch(a, groups * cu_count, stream);
+    if (e != hipSuccess) return device_error(e);
+    uint32_t failed = 1;
+    e = hipMemcpyAsync(&failed, ws->ctrl + 5, sizeof(failed), hipMemcpyDeviceToHost, stream);
+    if (e != hipSuccess) return device_error(e);
+    e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return device_error(e);
+    *ok = (failed == 0);
+    return LSCAN_OK;
+}
+
+// Largest groups-per-CU count <= want whose grid is known (or now tested)
+// to be resident at once.
+lscan_status resident_groups_locked(DeviceInfo* info, int sg, int oc, int shape, const KernelEntry& k,
+                                    int want, Workspace* ws, hipStream_t stream, int* out)
+{
+    int& good = info->resident_ok[sg][oc][shape];
+    int& bad = info->resident_fail[sg][oc][shape];
+    int g = want;
+    if (bad > 0 && g >= bad) g = bad - 1;
+    while (g > good) {
+        bool ok = false;
+        lscan_status st = test_residency_locked(k, info->cu_count, g, info->residency_limit, ws, stream, &ok);
+        if (st != LSCAN_OK) return st;
+        if (ok) {
+            good = g;
+        } else {
+            bad = g;
+            --g;
+        }
+    }
+    if (g < 1) return LSCAN_ERR_DEVICE;  // not even one workgroup per CU is resident
+    *out = g;
     return LSCAN_OK;
 }
 
@@ -253,12 +336,21 @@ lscan_status run_scan(bool segmented, const void* x, void* y, int64_t n, const i
 
     const int64_t L = k.tile_elems;
     const int64_t M = (n + L - 1) / L;
-    const int64_t groups = std::min<int64_t>(prm.groups_per_cu, occ);
-    const int64_t B = std::max<int64_t>(1, std::min<int64_t>(M, groups * info->cu_count));
 
     Workspace* ws = nullptr;
     st = workspace_locked(dev, stream, size_t(M) * size_t(k.slot_words), &ws);
     if (st != LSCAN_OK) return st;
+
+    // The grid must fit on the device at once: cap by the occupancy limit,
+    // then by what the co-residency test has shown (a grid no larger than M
+    // needs only the groups that M blocks fill).
+    int want = std::min<int>(prm.groups_per_cu, occ);
+    const int64_t need = (M + info->cu_count - 1) / info->cu_count;
+    if (need < want) want = int(need);
+    int groups = 0;
+    st = resident_groups_locked(info, sg, oc, prm.shape, k, want, ws, stream, &groups);
+    if (st != LSCAN_OK) return st;
+    const int64_t B = std::max<int64_t>(1, std::min<int64_t>(M, int64_t(groups) * info->cu_count));
 
     const int vec_bytes = k.in_bytes * k.elems_per_vec;
     ScanArgs a;
@@ -274,6 +366,8 @@ lscan_status run_scan(bool segmented, const void* x, void* y, int64_t n, const i
     a.exclusive = exclusive ? 1 : 0;
     a.vec_ok = (reinterpret_cast<uintptr_t>(x) % uintptr_t(vec_bytes) == 0 &&
                 reinterpret_cast<uintptr_t>(y) % 16 == 0) ? 1 : 0;
+    a.residency_check = 0;
+    a.pad_ = 0;
 
     e = k.launch(a, int(B), stream);
     if (e != hipSuccess) return device_error(e);
@@ -286,6 +380,8 @@ lscan_status run_scan(bool segmented, const void* x, void* y, int64_t n, const i
     t_last_launch.block_threads = k.block_threads;
     t_last_launch.slot_words = k.slot_words;
     t_last_launch.vector_path = a.vec_ok;
+    t_last_launch.groups_per_cu = groups;
+    t_last_launch.occupancy = occ;
     return LSCAN_OK;
 }
 

@@ -175,6 +175,38 @@ __device__ __forceinline__ int64_t lower_bound_i64(const int64_t* off, int64_t l
     return lo;
 }
 
+// Co-residency test run by the host once per (kernel, grid): every
+// workgroup counts itself in and waits, for at most `limit` ticks, until all
+// gridDim.x have arrived.  Any workgroup that stops waiting before that sets
+// the failure word, so the host learns whether the grid fits on the device
+// at once -- the condition the persistent scan needs to make progress.  All
+// waves of the workgroup stay alive (at the barrier) until the wait ends, so
+// the test occupies exactly what a real launch occupies.  The last workgroup
+// out clears the counters.
+__device__ __forceinline__ void check_residency(uint32_t* ctrl, uint64_t limit)
+{
+    const uint32_t grid = gridDim.x;
+    if (threadIdx.x == 0) {
+        uint32_t seen = __hip_atomic_fetch_add(ctrl + 4, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1u;
+        if (seen < grid) {
+            const uint64_t t0 = wall_clock64();
+            do {
+                __builtin_amdgcn_s_sleep(2);
+                seen = __hip_atomic_load(ctrl + 4, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            } while (seen < grid && wall_clock64() - t0 < limit);
+        }
+        if (seen < grid) __hip_atomic_store(ctrl + 5, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const uint32_t out = __hip_atomic_fetch_add(ctrl + 6, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (out == grid - 1u) {
+            __hip_atomic_store(ctrl + 4, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(ctrl + 6, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
 template <class BaseOp, bool SEG>
 struct ScanOpOf {
     using type = BaseOp;
@@ -201,6 +233,11 @@ __global__ void __launch_bounds__(T) scan_kernel(ScanArgs a)
     __shared__ V s_wave_total[2][NWAVE];
     __shared__ V s_block_prefix[2];
     __shared__ int s_abort[2];
+
+    if (a.residency_check) {
+        check_residency(a.ctrl, a.spin_limit);
+        return;
+    }
 
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
@@ -406,7 +443,12 @@ void fill_row(KernelTable& t, int opcode)
     row[2] = make_entry<BaseOp, SEG, 2>();
     row[3] = make_entry<BaseOp, SEG, 3>();
     row[4] = make_entry<BaseOp, SEG, 4>();
-    static_assert(kNumShapes == 5, "one entry per compiled shape");
+    row[5] = make_entry<BaseOp, SEG, 5>();
+    row[6] = make_entry<BaseOp, SEG, 6>();
+    row[7] = make_entry<BaseOp, SEG, 7>();
+    row[8] = make_entry<BaseOp, SEG, 8>();
+    row[9] = make_entry<BaseOp, SEG, 9>();
+    static_assert(kNumShapes == 10, "one entry per compiled shape");
 }
 
 }  // namespace lscan

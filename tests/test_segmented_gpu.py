@@ -69,7 +69,7 @@ def test_empty_and_boundary_segments(gpu_lib):
             compare(got, x, dtype, op, excl, offsets=off, what=f"boundary {dtype}/{op}/excl={excl}")
 
 
-@pytest.mark.parametrize("shape", range(5))
+@pytest.mark.parametrize("shape", range(10))
 def test_segmented_every_shape(gpu_lib, shape):
     from paper_1604_04815_amd import workloads as w
     t, r = gpu_lib.lscan_tile_shapes()[shape]

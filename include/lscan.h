@@ -117,6 +117,30 @@ lscan_status lscan_segmented(const void *x, void *y, int64_t n_total,
                              void *stream);
 
 /*
+ * lscan_batched -- the scan of Section 1 applied independently to each of
+ * `count` arrays in ONE persistent launch (batching for serving).  Each array
+ * occupies whole data blocks of its own, so the block method of Section 4
+ * runs unchanged inside an array and the prefix hand-off between blocks uses
+ * the segmented operator, restarting at the first block of every array.
+ *   arrays  HOST pointer to `count` descriptors; each x / y is a DEVICE
+ *           pointer with the element-alignment and in-place rules above
+ *           (16-byte alignment selects the vector path per array); arrays
+ *           must not overlap each other (not checked); n == 0 is allowed
+ *   flags   LSCAN_F_EXCLUSIVE, LSCAN_F_COMPENSATED as above
+ * The descriptor table is copied to the device before the launch; the host
+ * table may be reused as soon as the call returns.
+ */
+typedef struct {
+    const void *x;
+    void *y;
+    int64_t n;
+} lscan_array;
+
+lscan_status lscan_batched(const lscan_array *arrays, int64_t count,
+                           lscan_dtype dt, lscan_op op, uint32_t flags,
+                           void *stream);
+
+/*
  * Launch parameters (the paper's T, K and B of Section 5.1, chosen by
  * measurement here):
  *   block_threads     T: threads per workgroup (multiple of 64)
@@ -145,12 +169,17 @@ typedef struct {
 int32_t lscan_num_tile_shapes(void);
 lscan_status lscan_tile_shape(int32_t idx, lscan_params *out);
 
-/* Default parameters for (dt, op, flags) with segmented != 0 selecting the
- * segmented kernel; set replaces them (e.g. from an autotuner). */
+/* Kernel kinds for lscan_get_params / lscan_set_params. */
+#define LSCAN_KIND_PLAIN 0
+#define LSCAN_KIND_SEGMENTED 1
+#define LSCAN_KIND_BATCHED 2
+
+/* Default parameters for (dt, op, flags & LSCAN_F_COMPENSATED) and a kernel
+ * kind; set replaces them (e.g. from an autotuner). */
 lscan_status lscan_get_params(lscan_dtype dt, lscan_op op, uint32_t flags,
-                              int32_t segmented, lscan_params *out);
+                              int32_t kind, lscan_params *out);
 lscan_status lscan_set_params(lscan_dtype dt, lscan_op op, uint32_t flags,
-                              int32_t segmented, const lscan_params *p);
+                              int32_t kind, const lscan_params *p);
 
 /* As lscan_inclusive / lscan_exclusive / lscan_segmented with explicit
  * parameters (p == NULL: the defaults).  exclusive selects the form for the
@@ -165,6 +194,41 @@ lscan_status lscan_segmented_with_params(const void *x, void *y,
                                          int64_t num_segments, lscan_dtype dt,
                                          lscan_op op, uint32_t flags,
                                          const lscan_params *p, void *stream);
+
+lscan_status lscan_batched_with_params(const lscan_array *arrays,
+                                       int64_t count, lscan_dtype dt,
+                                       lscan_op op, uint32_t flags,
+                                       const lscan_params *p, void *stream);
+
+/*
+ * Graph-captured launches.  lscan_graph_create_* prepares one segmented or
+ * batched launch (workspace, co-residency test, descriptor upload, all on a
+ * private stream, synchronously) and captures it into a hipGraph that owns
+ * its own flag workspace; lscan_graph_launch replays it on `stream`.  The
+ * device pointers are fixed at creation: the caller changes the DATA in x /
+ * offsets between replays, not the pointers.  Replays of one graph must be
+ * ordered on one stream (they share the graph's flags); the flag epoch lives
+ * in device memory and is advanced by the kernel itself, so replays need no
+ * reset.  lscan_graph_check synchronizes `stream` and reports a timed-out
+ * replay; lscan_graph_destroy synchronizes the device and frees the graph.
+ */
+typedef struct lscan_graph lscan_graph;
+lscan_status lscan_graph_create_segmented(const void *x, void *y,
+                                          int64_t n_total,
+                                          const int64_t *offsets,
+                                          int64_t num_segments,
+                                          lscan_dtype dt, lscan_op op,
+                                          uint32_t flags,
+                                          const lscan_params *p,
+                                          lscan_graph **out);
+lscan_status lscan_graph_create_batched(const lscan_array *arrays,
+                                        int64_t count, lscan_dtype dt,
+                                        lscan_op op, uint32_t flags,
+                                        const lscan_params *p,
+                                        lscan_graph **out);
+lscan_status lscan_graph_launch(lscan_graph *g, void *stream);
+lscan_status lscan_graph_check(lscan_graph *g, void *stream);
+lscan_status lscan_graph_destroy(lscan_graph *g);
 
 /* Shape of the last launch made by the calling thread. */
 typedef struct {

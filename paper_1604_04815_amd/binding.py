@@ -40,6 +40,10 @@ class Params(ctypes.Structure):
                 ("groups_per_cu", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
+class Array(ctypes.Structure):
+    _fields_ = [("x", ctypes.c_void_p), ("y", ctypes.c_void_p), ("n", ctypes.c_int64)]
+
+
 class LaunchInfo(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("num_blocks", ctypes.c_int64), ("tile_elems", ctypes.c_int64),
                 ("grid", ctypes.c_int32), ("block_threads", ctypes.c_int32),
@@ -62,6 +66,16 @@ SIGNATURES = {
     "lscan_scan_with_params": ([_vp, _vp, _i64, _i32, _i32, _u32, _i32, ctypes.POINTER(Params), _vp], _i32),
     "lscan_segmented_with_params": ([_vp, _vp, _i64, _vp, _i64, _i32, _i32, _u32,
                                      ctypes.POINTER(Params), _vp], _i32),
+    "lscan_batched": ([ctypes.POINTER(Array), _i64, _i32, _i32, _u32, _vp], _i32),
+    "lscan_batched_with_params": ([ctypes.POINTER(Array), _i64, _i32, _i32, _u32, ctypes.POINTER(Params), _vp],
+                                  _i32),
+    "lscan_graph_create_segmented": ([_vp, _vp, _i64, _vp, _i64, _i32, _i32, _u32, ctypes.POINTER(Params),
+                                      ctypes.POINTER(_vp)], _i32),
+    "lscan_graph_create_batched": ([ctypes.POINTER(Array), _i64, _i32, _i32, _u32, ctypes.POINTER(Params),
+                                    ctypes.POINTER(_vp)], _i32),
+    "lscan_graph_launch": ([_vp, _vp], _i32),
+    "lscan_graph_check": ([_vp, _vp], _i32),
+    "lscan_graph_destroy": ([_vp], _i32),
     "lscan_last_launch": ([ctypes.POINTER(LaunchInfo)], _i32),
     "lscan_check": ([_vp], _i32),
     "lscan_release_workspaces": ([], _i32),
@@ -137,6 +151,66 @@ def lscan_segmented_with_params(x, y, n_total, offsets, num_segments, dt, op, fl
                                                      p, stream), "lscan_segmented_with_params")
 
 
+def _array_table(arrays):
+    tab = (Array * max(1, len(arrays)))()
+    for i, (x, y, n) in enumerate(arrays):
+        tab[i].x, tab[i].y, tab[i].n = x, y, n
+    return tab
+
+
+def lscan_batched(arrays, dt: int, op: int, flags: int = 0, stream: int = 0,
+                  params: Params | None = None) -> int:
+    """arrays: list of (x_ptr, y_ptr, n)."""
+    tab = _array_table(arrays)
+    if params is None:
+        st = load().lscan_batched(tab, len(arrays), dt, op, flags, stream)
+    else:
+        st = load().lscan_batched_with_params(tab, len(arrays), dt, op, flags, ctypes.byref(params), stream)
+    return _check(st, "lscan_batched")
+
+
+class Graph:
+    """A captured segmented or batched launch (lscan_graph_*)."""
+
+    def __init__(self, handle):
+        self.handle = handle
+
+    def launch(self, stream=None):
+        _check(load().lscan_graph_launch(self.handle, _stream(stream)), "lscan_graph_launch")
+
+    def check(self, stream=None):
+        _check(load().lscan_graph_check(self.handle, _stream(stream)), "lscan_graph_check")
+
+    def destroy(self):
+        if self.handle:
+            _check(load().lscan_graph_destroy(self.handle), "lscan_graph_destroy")
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:  # noqa: BLE001 - interpreter shutdown
+            pass
+
+
+def lscan_graph_create_segmented(x, y, n_total, offsets, num_segments, dt, op, flags=0,
+                                 params: Params | None = None) -> Graph:
+    h = ctypes.c_void_p()
+    p = ctypes.byref(params) if params is not None else None
+    _check(load().lscan_graph_create_segmented(x, y, n_total, offsets, num_segments, dt, op, flags, p,
+                                               ctypes.byref(h)), "lscan_graph_create_segmented")
+    return Graph(h.value)
+
+
+def lscan_graph_create_batched(arrays, dt, op, flags=0, params: Params | None = None) -> Graph:
+    h = ctypes.c_void_p()
+    tab = _array_table(arrays)
+    p = ctypes.byref(params) if params is not None else None
+    _check(load().lscan_graph_create_batched(tab, len(arrays), dt, op, flags, p, ctypes.byref(h)),
+           "lscan_graph_create_batched")
+    return Graph(h.value)
+
+
 def lscan_tile_shapes() -> list[tuple[int, int]]:
     lib = load()
     out = []
@@ -147,14 +221,17 @@ def lscan_tile_shapes() -> list[tuple[int, int]]:
     return out
 
 
-def lscan_get_params(dt, op, flags=0, segmented=False) -> Params:
+KIND_PLAIN, KIND_SEGMENTED, KIND_BATCHED = 0, 1, 2
+
+
+def lscan_get_params(dt, op, flags=0, kind=KIND_PLAIN) -> Params:
     p = Params()
-    _check(load().lscan_get_params(dt, op, flags, int(segmented), ctypes.byref(p)), "lscan_get_params")
+    _check(load().lscan_get_params(dt, op, flags, int(kind), ctypes.byref(p)), "lscan_get_params")
     return p
 
 
-def lscan_set_params(dt, op, flags, segmented, params: Params) -> None:
-    _check(load().lscan_set_params(dt, op, flags, int(segmented), ctypes.byref(params)), "lscan_set_params")
+def lscan_set_params(dt, op, flags, kind, params: Params) -> None:
+    _check(load().lscan_set_params(dt, op, flags, int(kind), ctypes.byref(params)), "lscan_set_params")
 
 
 def lscan_last_launch() -> LaunchInfo:
@@ -262,3 +339,24 @@ def segmented(x, offsets, op="add", exclusive=False, compensated=False, out=None
         lscan_segmented_with_params(x.data_ptr(), y.data_ptr(), x.shape[0], offsets.data_ptr(), nseg,
                                     dtype_code(x), OPS[op], flags, params, _stream(stream))
     return y
+
+
+def batched(xs, op="add", exclusive=False, compensated=False, outs=None, stream=None,
+            params: Params | None = None):
+    """Scan each tensor of ``xs`` (1-D device tensors of one dtype) in one
+    launch; returns the list of outputs."""
+    if not xs:
+        return []
+    dt = dtype_code(xs[0])
+    ys = []
+    table = []
+    for k, x in enumerate(xs):
+        _flat(x, "x")
+        if dtype_code(x) != dt:
+            raise TypeError("all arrays of a batch share one dtype")
+        y = _out_for(x, outs[k] if outs is not None else None)
+        ys.append(y)
+        table.append((x.data_ptr(), y.data_ptr(), x.shape[0]))
+    flags = (F_COMPENSATED if compensated else 0) | (F_EXCLUSIVE if exclusive else 0)
+    lscan_batched(table, dt, OPS[op], flags, _stream(stream), params)
+    return ys

@@ -7,6 +7,20 @@
 
 namespace lscan {
 
+// One array of a batched launch (device-side descriptor).  Array r owns data
+// blocks [first_block, first_block + ceil(n / L)); the table ends with a
+// sentinel whose first_block is the total block count M.
+struct BatchArray {
+    const void* x;
+    void* y;
+    int64_t n;
+    int64_t first_block;
+};
+
+// Kernel flavours: one array; one array cut into segments by offsets (heads
+// inside blocks); many arrays, each starting on a block boundary.
+enum ScanMode : int { kModePlain = 0, kModeSegmented = 1, kModeBatched = 2 };
+
 // Arguments of one persistent scan launch.
 struct ScanArgs {
     const void* x;            // input, n elements
@@ -15,6 +29,8 @@ struct ScanArgs {
     int64_t num_blocks;       // M = ceil(N / L)
     const int64_t* offsets;   // segmented: S + 1 offsets (device), else null
     int64_t num_segments;     // S
+    const BatchArray* arrays; // batched: num_arrays + 1 descriptors (device), else null
+    int64_t num_arrays;
     uint64_t* slots;          // M * slot_words flag words (epoch tag | data)
     uint32_t* ctrl;           // [0] last epoch tag, [1] exit counter, [2] timeout flag,
                               // [4] residency arrivals, [5] residency failure, [6] residency exits
@@ -53,8 +69,8 @@ constexpr int kNumShapes = 10;
 constexpr int kShapeThreads[kNumShapes] = {256, 512, 512, 256, 1024, 1024, 512, 256, 256, 1024};
 constexpr int kShapeVectors[kNumShapes] = {8, 8, 4, 16, 4, 2, 2, 4, 2, 1};
 
-// table[segmented][opcode][shape]
-using KernelTable = KernelEntry[2][kNumOpCodes][kNumShapes];
+// table[mode][opcode][shape]
+using KernelTable = KernelEntry[3][kNumOpCodes][kNumShapes];
 
 void register_i32_kernels(KernelTable& t);
 void register_i64_kernels(KernelTable& t);
@@ -64,5 +80,9 @@ void register_i32_seg_kernels(KernelTable& t);
 void register_i64_seg_kernels(KernelTable& t);
 void register_f32_seg_kernels(KernelTable& t);
 void register_bf16_seg_kernels(KernelTable& t);
+void register_i32_batch_kernels(KernelTable& t);
+void register_i64_batch_kernels(KernelTable& t);
+void register_f32_batch_kernels(KernelTable& t);
+void register_bf16_batch_kernels(KernelTable& t);
 
 }  // namespace lscan

@@ -6,10 +6,10 @@ namespace lscan {
 
 void register_bf16_kernels(KernelTable& t)
 {
-    fill_row<AddBF16, false>(t, kBF16Add);
-    fill_row<AddBF16Comp, false>(t, kBF16AddComp);
-    fill_row<MaxBF16, false>(t, kBF16Max);
-    fill_row<MinBF16, false>(t, kBF16Min);
+    fill_row<AddBF16, kModePlain>(t, kBF16Add);
+    fill_row<AddBF16Comp, kModePlain>(t, kBF16AddComp);
+    fill_row<MaxBF16, kModePlain>(t, kBF16Max);
+    fill_row<MinBF16, kModePlain>(t, kBF16Min);
 }
 
 }  // namespace lscan

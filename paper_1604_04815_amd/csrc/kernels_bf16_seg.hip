@@ -6,10 +6,10 @@ namespace lscan {
 
 void register_bf16_seg_kernels(KernelTable& t)
 {
-    fill_row<AddBF16, true>(t, kBF16Add);
-    fill_row<AddBF16Comp, true>(t, kBF16AddComp);
-    fill_row<MaxBF16, true>(t, kBF16Max);
-    fill_row<MinBF16, true>(t, kBF16Min);
+    fill_row<AddBF16, kModeSegmented>(t, kBF16Add);
+    fill_row<AddBF16Comp, kModeSegmented>(t, kBF16AddComp);
+    fill_row<MaxBF16, kModeSegmented>(t, kBF16Max);
+    fill_row<MinBF16, kModeSegmented>(t, kBF16Min);
 }
 
 }  // namespace lscan

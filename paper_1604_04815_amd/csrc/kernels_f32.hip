@@ -6,10 +6,10 @@ namespace lscan {
 
 void register_f32_kernels(KernelTable& t)
 {
-    fill_row<AddF32, false>(t, kF32Add);
-    fill_row<AddF32Comp, false>(t, kF32AddComp);
-    fill_row<MaxF32, false>(t, kF32Max);
-    fill_row<MinF32, false>(t, kF32Min);
+    fill_row<AddF32, kModePlain>(t, kF32Add);
+    fill_row<AddF32Comp, kModePlain>(t, kF32AddComp);
+    fill_row<MaxF32, kModePlain>(t, kF32Max);
+    fill_row<MinF32, kModePlain>(t, kF32Min);
 }
 
 }  // namespace lscan

@@ -6,10 +6,10 @@ namespace lscan {
 
 void register_f32_seg_kernels(KernelTable& t)
 {
-    fill_row<AddF32, true>(t, kF32Add);
-    fill_row<AddF32Comp, true>(t, kF32AddComp);
-    fill_row<MaxF32, true>(t, kF32Max);
-    fill_row<MinF32, true>(t, kF32Min);
+    fill_row<AddF32, kModeSegmented>(t, kF32Add);
+    fill_row<AddF32Comp, kModeSegmented>(t, kF32AddComp);
+    fill_row<MaxF32, kModeSegmented>(t, kF32Max);
+    fill_row<MinF32, kModeSegmented>(t, kF32Min);
 }
 
 }  // namespace lscan

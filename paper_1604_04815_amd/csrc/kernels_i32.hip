@@ -6,9 +6,9 @@ namespace lscan {
 
 void register_i32_kernels(KernelTable& t)
 {
-    fill_row<AddI32, false>(t, kI32Add);
-    fill_row<MaxI32, false>(t, kI32Max);
-    fill_row<MinI32, false>(t, kI32Min);
+    fill_row<AddI32, kModePlain>(t, kI32Add);
+    fill_row<MaxI32, kModePlain>(t, kI32Max);
+    fill_row<MinI32, kModePlain>(t, kI32Min);
 }
 
 }  // namespace lscan

@@ -6,9 +6,9 @@ namespace lscan {
 
 void register_i32_seg_kernels(KernelTable& t)
 {
-    fill_row<AddI32, true>(t, kI32Add);
-    fill_row<MaxI32, true>(t, kI32Max);
-    fill_row<MinI32, true>(t, kI32Min);
+    fill_row<AddI32, kModeSegmented>(t, kI32Add);
+    fill_row<MaxI32, kModeSegmented>(t, kI32Max);
+    fill_row<MinI32, kModeSegmented>(t, kI32Min);
 }
 
 }  // namespace lscan

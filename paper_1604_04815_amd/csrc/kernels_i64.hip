@@ -6,9 +6,9 @@ namespace lscan {
 
 void register_i64_kernels(KernelTable& t)
 {
-    fill_row<AddI64, false>(t, kI64Add);
-    fill_row<MaxI64, false>(t, kI64Max);
-    fill_row<MinI64, false>(t, kI64Min);
+    fill_row<AddI64, kModePlain>(t, kI64Add);
+    fill_row<MaxI64, kModePlain>(t, kI64Max);
+    fill_row<MinI64, kModePlain>(t, kI64Min);
 }
 
 }  // namespace lscan

@@ -6,9 +6,9 @@ namespace lscan {
 
 void register_i64_seg_kernels(KernelTable& t)
 {
-    fill_row<AddI64, true>(t, kI64Add);
-    fill_row<MaxI64, true>(t, kI64Max);
-    fill_row<MinI64, true>(t, kI64Min);
+    fill_row<AddI64, kModeSegmented>(t, kI64Add);
+    fill_row<MaxI64, kModeSegmented>(t, kI64Max);
+    fill_row<MinI64, kModeSegmented>(t, kI64Min);
 }
 
 }  // namespace lscan

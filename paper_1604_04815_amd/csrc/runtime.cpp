@@ -1,6 +1,7 @@
 // runtime.cpp -- host side of the C ABI declared in include/lscan.h:
 // argument validation, kernel selection, grid sizing against the occupancy
-// limit, and the per-(device, stream) flag workspaces.
+// limit and a co-residency test, the per-(device, stream) flag workspaces,
+// batched descriptors and graph-captured launches.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -8,6 +9,7 @@
 #include <cstring>
 #include <map>
 #include <mutex>
+#include <new>
 #include <utility>
 
 #include "kernel_table.hpp"
@@ -30,6 +32,10 @@ void init_table()
     register_i64_seg_kernels(g_table);
     register_f32_seg_kernels(g_table);
     register_bf16_seg_kernels(g_table);
+    register_i32_batch_kernels(g_table);
+    register_i64_batch_kernels(g_table);
+    register_f32_batch_kernels(g_table);
+    register_bf16_batch_kernels(g_table);
 }
 
 const KernelTable& table()
@@ -48,22 +54,35 @@ constexpr double kSpinLimitSeconds = 2.0;
 // A co-residency test waits this long for the whole grid to arrive.
 constexpr double kResidencyWaitSeconds = 0.02;
 
+// Tags are 32-bit and 0 marks a never-written slot: reset a workspace well
+// before its tag counter could wrap.
+constexpr uint64_t kMaxLaunchesPerEpochRun = 0xfffffff0ull;
+
+constexpr int kNumModes = 3;
+
 struct DeviceInfo {
     int cu_count = 0;
     uint64_t spin_limit = 0;
     uint64_t residency_limit = 0;
-    int occupancy[2][kNumOpCodes][kNumShapes];
+    int occupancy[kNumModes][kNumOpCodes][kNumShapes];
     // groups per CU proven resident together (0: none yet) and the smallest
     // count that failed the test (0: none failed)
-    int resident_ok[2][kNumOpCodes][kNumShapes];
-    int resident_fail[2][kNumOpCodes][kNumShapes];
+    int resident_ok[kNumModes][kNumOpCodes][kNumShapes];
+    int resident_fail[kNumModes][kNumOpCodes][kNumShapes];
 };
 
+// Flag slots, control words and (batched launches) array descriptors of one
+// launch sequence.  Launches that share a workspace must be stream-ordered.
 struct Workspace {
     uint64_t* slots = nullptr;
     size_t words = 0;
-    uint32_t* ctrl = nullptr;   // [0] last tag, [1] exit counter, [2] timeout flag
+    uint32_t* ctrl = nullptr;   // [0] last tag, [1] exit counter, [2] timeout flag, [4..6] residency test
     uint64_t launches = 0;
+    BatchArray* desc = nullptr;        // device copy of the descriptor table
+    size_t desc_cap = 0;
+    BatchArray* desc_host = nullptr;   // pinned staging copy
+    hipEvent_t desc_copied = nullptr;  // recorded after each upload from desc_host
+    bool desc_pending = false;
 };
 
 struct Params {
@@ -74,17 +93,19 @@ struct Params {
 std::mutex g_mu;
 std::map<int, DeviceInfo> g_dev;
 std::map<std::pair<int, hipStream_t>, Workspace> g_ws;
-Params g_params[2][kNumOpCodes];
+Params g_params[kNumModes][kNumOpCodes];
 bool g_params_init = false;
-
-// Tags are 32-bit and 0 marks a never-written slot: reset a workspace well
-// before its tag counter could wrap.
-constexpr uint64_t kMaxLaunchesPerEpochRun = 0xfffffff0ull;
 
 lscan_status device_error(hipError_t e)
 {
     t_last_hip_error = int32_t(e);
     return LSCAN_ERR_DEVICE;
+}
+
+bool capturing(hipStream_t stream)
+{
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    return hipStreamIsCapturing(stream, &cap) == hipSuccess && cap != hipStreamCaptureStatusNone;
 }
 
 // Defaults measured on MI355X (gfx950) with N = 2^27..2^28 arrays: shape
@@ -94,21 +115,22 @@ void init_params_locked()
 {
     if (g_params_init) return;
     const Params t256x8{0, 5}, t256x16{3, 3}, t1024x4{4, 1}, comp_bf16{3, 2};
-    for (int o = kI32Add; o <= kI32Min; ++o) g_params[0][o] = t256x8;
-    for (int o = kI64Add; o <= kI64Min; ++o) g_params[0][o] = t256x16;
-    g_params[0][kF32Add] = t256x8;
-    g_params[0][kF32AddComp] = t1024x4;
-    g_params[0][kF32Max] = t256x8;
-    g_params[0][kF32Min] = t256x8;
-    g_params[0][kBF16Add] = t256x16;
-    g_params[0][kBF16AddComp] = comp_bf16;
-    g_params[0][kBF16Max] = t256x16;
-    g_params[0][kBF16Min] = t256x16;
-    // segmented kernels: the per-tile head search adds latency, so fewer
-    // groups per CU measured best
+    for (int o = kI32Add; o <= kI32Min; ++o) g_params[kModePlain][o] = t256x8;
+    for (int o = kI64Add; o <= kI64Min; ++o) g_params[kModePlain][o] = t256x16;
+    g_params[kModePlain][kF32Add] = t256x8;
+    g_params[kModePlain][kF32AddComp] = t1024x4;
+    g_params[kModePlain][kF32Max] = t256x8;
+    g_params[kModePlain][kF32Min] = t256x8;
+    g_params[kModePlain][kBF16Add] = t256x16;
+    g_params[kModePlain][kBF16AddComp] = comp_bf16;
+    g_params[kModePlain][kBF16Max] = t256x16;
+    g_params[kModePlain][kBF16Min] = t256x16;
     for (int o = 0; o < kNumOpCodes; ++o) {
-        g_params[1][o] = g_params[0][o];
-        if (g_params[1][o].groups_per_cu > 3) g_params[1][o].groups_per_cu = 3;
+        // segmented kernels: the per-tile head search adds latency, so fewer
+        // groups per CU measured best
+        g_params[kModeSegmented][o] = g_params[kModePlain][o];
+        if (g_params[kModeSegmented][o].groups_per_cu > 3) g_params[kModeSegmented][o].groups_per_cu = 3;
+        g_params[kModeBatched][o] = g_params[kModePlain][o];
     }
     g_params_init = true;
 }
@@ -137,15 +159,10 @@ int shape_index(int threads, int vectors)
     return -1;
 }
 
-lscan_status check_common(const void* x, const void* y, int64_t n, int dt, int op, uint32_t flags,
-                          uint32_t allowed_flags, int* opcode)
+// x / y of one array: element alignment, and no overlap other than in place.
+lscan_status check_array(const void* x, const void* y, int64_t n, int dt)
 {
-    if (flags & ~allowed_flags) return LSCAN_ERR_INVALID_ARG;
-    const int oc = opcode_of(dt, op, flags);
-    if (oc == -1) return LSCAN_ERR_INVALID_ARG;
-    if (oc == -2) return LSCAN_ERR_UNSUPPORTED;
     if (n < 0) return LSCAN_ERR_INVALID_ARG;
-    *opcode = oc;
     if (n == 0) return LSCAN_OK;
     if (!x || !y) return LSCAN_ERR_INVALID_ARG;
     const uintptr_t xa = reinterpret_cast<uintptr_t>(x), ya = reinterpret_cast<uintptr_t>(y);
@@ -155,6 +172,77 @@ lscan_status check_common(const void* x, const void* y, int64_t n, int dt, int o
     const uintptr_t xe = xa + uintptr_t(n) * uintptr_t(ib), ye = ya + uintptr_t(n) * uintptr_t(ob);
     const bool overlap = xa < ye && ya < xe;
     if (overlap && !(xa == ya && ib == ob)) return LSCAN_ERR_INVALID_ARG;
+    return LSCAN_OK;
+}
+
+lscan_status check_params(const lscan_params* p)
+{
+    if (!p) return LSCAN_OK;
+    if ((p->block_threads != 0 || p->vectors_per_lane != 0) &&
+        shape_index(p->block_threads, p->vectors_per_lane) < 0)
+        return LSCAN_ERR_UNSUPPORTED;
+    if (p->groups_per_cu < 0) return LSCAN_ERR_INVALID_ARG;
+    return LSCAN_OK;
+}
+
+// One validated call.
+struct Request {
+    int mode = kModePlain;
+    int oc = 0;
+    const void* x = nullptr;
+    void* y = nullptr;
+    int64_t n = 0;                       // plain/segmented: elements
+    const int64_t* offsets = nullptr;
+    int64_t num_segments = 0;
+    const lscan_array* arrays = nullptr; // batched (host table)
+    int64_t num_arrays = 0;
+    bool exclusive = false;
+    const lscan_params* p = nullptr;
+    bool empty = false;                  // nothing to do
+};
+
+lscan_status make_request(int mode, const void* x, void* y, int64_t n, const int64_t* offsets, int64_t num_segments,
+                          const lscan_array* arrays, int64_t num_arrays, int dt, int op, uint32_t flags,
+                          bool exclusive, const lscan_params* p, Request* r)
+{
+    const uint32_t allowed = (mode == kModePlain) ? LSCAN_F_COMPENSATED : (LSCAN_F_COMPENSATED | LSCAN_F_EXCLUSIVE);
+    if (flags & ~allowed) return LSCAN_ERR_INVALID_ARG;
+    const int oc = opcode_of(dt, op, flags);
+    if (oc == -1) return LSCAN_ERR_INVALID_ARG;
+    if (oc == -2) return LSCAN_ERR_UNSUPPORTED;
+    lscan_status st = check_params(p);
+    if (st != LSCAN_OK) return st;
+    r->mode = mode;
+    r->oc = oc;
+    r->exclusive = exclusive;
+    r->p = p;
+    if (mode == kModeBatched) {
+        if (num_arrays < 0 || (num_arrays > 0 && !arrays)) return LSCAN_ERR_INVALID_ARG;
+        int64_t total = 0;
+        for (int64_t i = 0; i < num_arrays; ++i) {
+            st = check_array(arrays[i].x, arrays[i].y, arrays[i].n, dt);
+            if (st != LSCAN_OK) return st;
+            total += arrays[i].n;
+        }
+        r->arrays = arrays;
+        r->num_arrays = num_arrays;
+        r->empty = (total == 0);
+        return LSCAN_OK;
+    }
+    st = check_array(x, y, n, dt);
+    if (st != LSCAN_OK) return st;
+    if (mode == kModeSegmented) {
+        if (num_segments < 0) return LSCAN_ERR_INVALID_ARG;
+        if (num_segments == 0 && n != 0) return LSCAN_ERR_INVALID_ARG;
+        if (num_segments > 0 && !offsets) return LSCAN_ERR_INVALID_ARG;
+        if (reinterpret_cast<uintptr_t>(offsets) % 8) return LSCAN_ERR_INVALID_ARG;
+    }
+    r->x = x;
+    r->y = y;
+    r->n = n;
+    r->offsets = offsets;
+    r->num_segments = num_segments;
+    r->empty = (n == 0);
     return LSCAN_OK;
 }
 
@@ -170,7 +258,7 @@ lscan_status device_info_locked(int dev, DeviceInfo** out)
         if (e != hipSuccess || wall_khz <= 0) wall_khz = 100000;  // 100 MHz constant clock
         info.spin_limit = uint64_t(double(wall_khz) * 1000.0 * kSpinLimitSeconds);
         info.residency_limit = uint64_t(double(wall_khz) * 1000.0 * kResidencyWaitSeconds);
-        for (int s = 0; s < 2; ++s)
+        for (int s = 0; s < kNumModes; ++s)
             for (int o = 0; o < kNumOpCodes; ++o)
                 for (int h = 0; h < kNumShapes; ++h) {
                     info.occupancy[s][o][h] = -1;
@@ -183,54 +271,95 @@ lscan_status device_info_locked(int dev, DeviceInfo** out)
     return LSCAN_OK;
 }
 
-lscan_status workspace_locked(int dev, hipStream_t stream, size_t words, Workspace** out)
+void free_workspace(Workspace& ws)
 {
-    Workspace& ws = g_ws[std::make_pair(dev, stream)];
+    if (ws.slots) (void)hipFree(ws.slots);
+    if (ws.ctrl) (void)hipFree(ws.ctrl);
+    if (ws.desc) (void)hipFree(ws.desc);
+    if (ws.desc_host) (void)hipHostFree(ws.desc_host);
+    if (ws.desc_copied) (void)hipEventDestroy(ws.desc_copied);
+    ws = Workspace();
+}
+
+// Make ws hold at least `words` flag words and `desc_entries` descriptors.
+lscan_status ensure_workspace(Workspace& ws, hipStream_t stream, size_t words, size_t desc_entries)
+{
     hipError_t e;
     const bool need_reset = ws.launches >= kMaxLaunchesPerEpochRun;
-    if (ws.words < words || !ws.ctrl || need_reset) {
-        hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
-        if (hipStreamIsCapturing(stream, &cap) == hipSuccess && cap != hipStreamCaptureStatusNone)
-            return LSCAN_ERR_UNSUPPORTED;  // size the workspace with an eager call before capturing
-        if (ws.slots || ws.ctrl) {
-            e = hipStreamSynchronize(stream);
-            if (e != hipSuccess) return device_error(e);
-        }
-        if (ws.words < words) {
-            const size_t alloc = std::max<size_t>(words, std::max<size_t>(ws.words * 2, size_t(1) << 14));
-            if (ws.slots) {
-                e = hipFree(ws.slots);
-                if (e != hipSuccess) return device_error(e);
-                ws.slots = nullptr;
-                ws.words = 0;
-            }
-            e = hipMalloc(reinterpret_cast<void**>(&ws.slots), alloc * sizeof(uint64_t));
-            if (e != hipSuccess) {
-                (void)hipGetLastError();
-                return LSCAN_ERR_NO_MEMORY;
-            }
-            ws.words = alloc;
-            e = hipMemsetAsync(ws.slots, 0, alloc * sizeof(uint64_t), stream);
-            if (e != hipSuccess) return device_error(e);
-        } else if (need_reset) {
-            e = hipMemsetAsync(ws.slots, 0, ws.words * sizeof(uint64_t), stream);
-            if (e != hipSuccess) return device_error(e);
-        }
-        if (!ws.ctrl) {
-            e = hipMalloc(reinterpret_cast<void**>(&ws.ctrl), 64);
-            if (e != hipSuccess) {
-                (void)hipGetLastError();
-                return LSCAN_ERR_NO_MEMORY;
-            }
-            e = hipMemsetAsync(ws.ctrl, 0, 64, stream);
-            if (e != hipSuccess) return device_error(e);
-        } else if (need_reset) {
-            // keep the timeout flag (word 2); restart the tag and exit counter
-            e = hipMemsetAsync(ws.ctrl, 0, 2 * sizeof(uint32_t), stream);
-            if (e != hipSuccess) return device_error(e);
-        }
-        if (need_reset) ws.launches = 0;
+    const bool grow_slots = ws.words < words || !ws.ctrl;
+    const bool grow_desc = ws.desc_cap < desc_entries;
+    if (!grow_slots && !grow_desc && !need_reset) return LSCAN_OK;
+    if (capturing(stream)) return LSCAN_ERR_UNSUPPORTED;  // size the workspace with an eager call first
+    if (ws.slots || ws.ctrl || ws.desc) {
+        e = hipStreamSynchronize(stream);
+        if (e != hipSuccess) return device_error(e);
     }
+    if (ws.words < words) {
+        const size_t alloc = std::max<size_t>(words, std::max<size_t>(ws.words * 2, size_t(1) << 14));
+        if (ws.slots) {
+            e = hipFree(ws.slots);
+            if (e != hipSuccess) return device_error(e);
+            ws.slots = nullptr;
+            ws.words = 0;
+        }
+        e = hipMalloc(reinterpret_cast<void**>(&ws.slots), alloc * sizeof(uint64_t));
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return LSCAN_ERR_NO_MEMORY;
+        }
+        ws.words = alloc;
+        e = hipMemsetAsync(ws.slots, 0, alloc * sizeof(uint64_t), stream);
+        if (e != hipSuccess) return device_error(e);
+    } else if (need_reset) {
+        e = hipMemsetAsync(ws.slots, 0, ws.words * sizeof(uint64_t), stream);
+        if (e != hipSuccess) return device_error(e);
+    }
+    if (!ws.ctrl) {
+        e = hipMalloc(reinterpret_cast<void**>(&ws.ctrl), 64);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return LSCAN_ERR_NO_MEMORY;
+        }
+        e = hipMemsetAsync(ws.ctrl, 0, 64, stream);
+        if (e != hipSuccess) return device_error(e);
+    } else if (need_reset) {
+        // keep the timeout flag (word 2); restart the tag and the exit counter
+        e = hipMemsetAsync(ws.ctrl, 0, 2 * sizeof(uint32_t), stream);
+        if (e != hipSuccess) return device_error(e);
+    }
+    if (need_reset) ws.launches = 0;
+    if (grow_desc) {
+        const size_t cap = std::max<size_t>(desc_entries, std::max<size_t>(ws.desc_cap * 2, 256));
+        if (ws.desc) (void)hipFree(ws.desc);
+        if (ws.desc_host) (void)hipHostFree(ws.desc_host);
+        ws.desc = nullptr;
+        ws.desc_host = nullptr;
+        ws.desc_cap = 0;
+        ws.desc_pending = false;
+        e = hipMalloc(reinterpret_cast<void**>(&ws.desc), cap * sizeof(BatchArray));
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return LSCAN_ERR_NO_MEMORY;
+        }
+        e = hipHostMalloc(reinterpret_cast<void**>(&ws.desc_host), cap * sizeof(BatchArray), hipHostMallocDefault);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return LSCAN_ERR_NO_MEMORY;
+        }
+        if (!ws.desc_copied) {
+            e = hipEventCreateWithFlags(&ws.desc_copied, hipEventDisableTiming);
+            if (e != hipSuccess) return device_error(e);
+        }
+        ws.desc_cap = cap;
+    }
+    return LSCAN_OK;
+}
+
+lscan_status workspace_locked(int dev, hipStream_t stream, size_t words, size_t desc_entries, Workspace** out)
+{
+    Workspace& ws = g_ws[std::make_pair(dev, stream)];
+    lscan_status st = ensure_workspace(ws, stream, words, desc_entries);
+    if (st != LSCAN_OK) return st;
     *out = &ws;
     return LSCAN_OK;
 }
@@ -240,9 +369,7 @@ lscan_status workspace_locked(int dev, hipStream_t stream, size_t words, Workspa
 lscan_status test_residency_locked(const KernelEntry& k, int cu_count, int groups, uint64_t limit,
                                    Workspace* ws, hipStream_t stream, bool* ok)
 {
-    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
-    if (hipStreamIsCapturing(stream, &cap) == hipSuccess && cap != hipStreamCaptureStatusNone)
-        return LSCAN_ERR_UNSUPPORTED;  // run one eager call of this shape before capturing
+    if (capturing(stream)) return LSCAN_ERR_UNSUPPORTED;  // run one eager call of this shape first
     hipError_t e = hipMemsetAsync(ws->ctrl + 4, 0, 3 * sizeof(uint32_t), stream);
     if (e != hipSuccess) return device_error(e);
     ScanArgs a;
@@ -264,11 +391,11 @@ lscan_status test_residency_locked(const KernelEntry& k, int cu_count, int group
 
 // Largest groups-per-CU count <= want whose grid is known (or now tested)
 // to be resident at once.
-lscan_status resident_groups_locked(DeviceInfo* info, int sg, int oc, int shape, const KernelEntry& k,
+lscan_status resident_groups_locked(DeviceInfo* info, int mode, int oc, int shape, const KernelEntry& k,
                                     int want, Workspace* ws, hipStream_t stream, int* out)
 {
-    int& good = info->resident_ok[sg][oc][shape];
-    int& bad = info->resident_fail[sg][oc][shape];
+    int& good = info->resident_ok[mode][oc][shape];
+    int& bad = info->resident_fail[mode][oc][shape];
     int g = want;
     if (bad > 0 && g >= bad) g = bad - 1;
     while (g > good) {
@@ -287,58 +414,56 @@ lscan_status resident_groups_locked(DeviceInfo* info, int sg, int oc, int shape,
     return LSCAN_OK;
 }
 
-lscan_status run_scan(bool segmented, const void* x, void* y, int64_t n, const int64_t* offsets,
-                      int64_t num_segments, int dt, int op, uint32_t flags, bool exclusive,
-                      const lscan_params* p, void* stream_ptr)
+// Everything needed to enqueue one launch.
+struct Plan {
+    const KernelEntry* k = nullptr;
+    ScanArgs a;
+    int grid = 0;
+    int groups = 0;
+    int occupancy = 0;
+};
+
+// Choose the kernel and grid, size the workspace, run the co-residency test
+// if this shape is new, upload batched descriptors, and fill the kernel
+// arguments.  Called with g_mu held.  ws_fixed is a workspace owned by a
+// graph, or null for the per-stream one.
+lscan_status plan_locked(const Request& r, int dev, Workspace* ws_fixed, hipStream_t stream, Plan* plan,
+                         Workspace** ws_used)
 {
-    int oc = 0;
-    const uint32_t allowed = segmented ? (LSCAN_F_COMPENSATED | LSCAN_F_EXCLUSIVE) : LSCAN_F_COMPENSATED;
-    lscan_status st = check_common(x, y, n, dt, op, flags, allowed, &oc);
-    if (st != LSCAN_OK) return st;
-    if (segmented) {
-        if (num_segments < 0) return LSCAN_ERR_INVALID_ARG;
-        if (num_segments == 0 && n != 0) return LSCAN_ERR_INVALID_ARG;
-        if (num_segments > 0 && !offsets) return LSCAN_ERR_INVALID_ARG;
-        if (reinterpret_cast<uintptr_t>(offsets) % 8) return LSCAN_ERR_INVALID_ARG;
-    }
-    if (p && (p->block_threads != 0 || p->vectors_per_lane != 0) &&
-        shape_index(p->block_threads, p->vectors_per_lane) < 0)
-        return LSCAN_ERR_UNSUPPORTED;
-    if (p && p->groups_per_cu < 0) return LSCAN_ERR_INVALID_ARG;
-    if (n == 0) return LSCAN_OK;
-
-    const int sg = segmented ? 1 : 0;
-    hipStream_t stream = static_cast<hipStream_t>(stream_ptr);
-    const KernelTable& tab = table();
-
-    std::lock_guard<std::mutex> lock(g_mu);
     init_params_locked();
-    Params prm = g_params[sg][oc];
-    if (p && (p->block_threads != 0 || p->vectors_per_lane != 0))
-        prm.shape = shape_index(p->block_threads, p->vectors_per_lane);
-    if (p && p->groups_per_cu > 0) prm.groups_per_cu = p->groups_per_cu;
-    const KernelEntry& k = tab[sg][oc][prm.shape];
+    Params prm = g_params[r.mode][r.oc];
+    if (r.p && (r.p->block_threads != 0 || r.p->vectors_per_lane != 0))
+        prm.shape = shape_index(r.p->block_threads, r.p->vectors_per_lane);
+    if (r.p && r.p->groups_per_cu > 0) prm.groups_per_cu = r.p->groups_per_cu;
+    const KernelEntry& k = table()[r.mode][r.oc][prm.shape];
 
-    int dev = 0;
-    hipError_t e = hipGetDevice(&dev);
-    if (e != hipSuccess) return device_error(e);
     DeviceInfo* info = nullptr;
-    st = device_info_locked(dev, &info);
+    lscan_status st = device_info_locked(dev, &info);
     if (st != LSCAN_OK) return st;
-    int& occ = info->occupancy[sg][oc][prm.shape];
+    int& occ = info->occupancy[r.mode][r.oc][prm.shape];
     if (occ < 0) {
         int v = 0;
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, k.func, k.block_threads, 0);
+        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, k.func, k.block_threads, 0);
         if (e != hipSuccess) return device_error(e);
         occ = v;
     }
     if (occ <= 0) return LSCAN_ERR_UNSUPPORTED;
 
     const int64_t L = k.tile_elems;
-    const int64_t M = (n + L - 1) / L;
+    int64_t M = 0;
+    if (r.mode == kModeBatched) {
+        for (int64_t i = 0; i < r.num_arrays; ++i) M += (r.arrays[i].n + L - 1) / L;
+    } else {
+        M = (r.n + L - 1) / L;
+    }
+    const size_t desc_entries = (r.mode == kModeBatched) ? size_t(r.num_arrays) + 1 : 0;
 
-    Workspace* ws = nullptr;
-    st = workspace_locked(dev, stream, size_t(M) * size_t(k.slot_words), &ws);
+    Workspace* ws = ws_fixed;
+    if (ws) {
+        st = ensure_workspace(*ws, stream, size_t(M) * size_t(k.slot_words), desc_entries);
+    } else {
+        st = workspace_locked(dev, stream, size_t(M) * size_t(k.slot_words), desc_entries, &ws);
+    }
     if (st != LSCAN_OK) return st;
 
     // The grid must fit on the device at once: cap by the occupancy limit,
@@ -348,32 +473,67 @@ lscan_status run_scan(bool segmented, const void* x, void* y, int64_t n, const i
     const int64_t need = (M + info->cu_count - 1) / info->cu_count;
     if (need < want) want = int(need);
     int groups = 0;
-    st = resident_groups_locked(info, sg, oc, prm.shape, k, want, ws, stream, &groups);
+    st = resident_groups_locked(info, r.mode, r.oc, prm.shape, k, want, ws, stream, &groups);
     if (st != LSCAN_OK) return st;
     const int64_t B = std::max<int64_t>(1, std::min<int64_t>(M, int64_t(groups) * info->cu_count));
 
-    const int vec_bytes = k.in_bytes * k.elems_per_vec;
-    ScanArgs a;
-    a.x = x;
-    a.y = y;
-    a.n = n;
+    ScanArgs& a = plan->a;
+    std::memset(&a, 0, sizeof(a));
+    if (r.mode == kModeBatched) {
+        if (capturing(stream)) return LSCAN_ERR_UNSUPPORTED;  // descriptors are uploaded eagerly
+        hipError_t e;
+        if (ws->desc_pending) {  // the previous upload must have left the staging buffer
+            e = hipEventSynchronize(ws->desc_copied);
+            if (e != hipSuccess) return device_error(e);
+            ws->desc_pending = false;
+        }
+        int64_t first = 0;
+        for (int64_t i = 0; i < r.num_arrays; ++i) {
+            ws->desc_host[i].x = r.arrays[i].x;
+            ws->desc_host[i].y = r.arrays[i].y;
+            ws->desc_host[i].n = r.arrays[i].n;
+            ws->desc_host[i].first_block = first;
+            first += (r.arrays[i].n + L - 1) / L;
+        }
+        ws->desc_host[r.num_arrays] = BatchArray{nullptr, nullptr, 0, first};
+        e = hipMemcpyAsync(ws->desc, ws->desc_host, desc_entries * sizeof(BatchArray), hipMemcpyHostToDevice,
+                           stream);
+        if (e != hipSuccess) return device_error(e);
+        e = hipEventRecord(ws->desc_copied, stream);
+        if (e != hipSuccess) return device_error(e);
+        ws->desc_pending = true;
+        a.arrays = ws->desc;
+        a.num_arrays = r.num_arrays;
+        a.vec_ok = 1;  // decided per array in the kernel
+    } else {
+        const int vec_bytes = k.in_bytes * k.elems_per_vec;
+        a.x = r.x;
+        a.y = r.y;
+        a.n = r.n;
+        a.offsets = r.offsets;
+        a.num_segments = r.num_segments;
+        a.vec_ok = (reinterpret_cast<uintptr_t>(r.x) % uintptr_t(vec_bytes) == 0 &&
+                    reinterpret_cast<uintptr_t>(r.y) % 16 == 0) ? 1 : 0;
+    }
     a.num_blocks = M;
-    a.offsets = offsets;
-    a.num_segments = num_segments;
     a.slots = ws->slots;
     a.ctrl = ws->ctrl;
     a.spin_limit = info->spin_limit;
-    a.exclusive = exclusive ? 1 : 0;
-    a.vec_ok = (reinterpret_cast<uintptr_t>(x) % uintptr_t(vec_bytes) == 0 &&
-                reinterpret_cast<uintptr_t>(y) % 16 == 0) ? 1 : 0;
+    a.exclusive = r.exclusive ? 1 : 0;
     a.residency_check = 0;
-    a.pad_ = 0;
 
-    e = k.launch(a, int(B), stream);
-    if (e != hipSuccess) return device_error(e);
-    ws->launches++;
+    plan->k = &k;
+    plan->grid = int(B);
+    plan->groups = groups;
+    plan->occupancy = occ;
+    if (ws_used) *ws_used = ws;
 
-    t_last_launch.n = n;
+    int64_t total = r.n;
+    if (r.mode == kModeBatched) {
+        total = 0;
+        for (int64_t i = 0; i < r.num_arrays; ++i) total += r.arrays[i].n;
+    }
+    t_last_launch.n = total;
     t_last_launch.num_blocks = M;
     t_last_launch.tile_elems = L;
     t_last_launch.grid = int32_t(B);
@@ -385,44 +545,213 @@ lscan_status run_scan(bool segmented, const void* x, void* y, int64_t n, const i
     return LSCAN_OK;
 }
 
+lscan_status run(const Request& r, void* stream_ptr)
+{
+    if (r.empty) return LSCAN_OK;
+    hipStream_t stream = static_cast<hipStream_t>(stream_ptr);
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return device_error(e);
+    std::lock_guard<std::mutex> lock(g_mu);
+    Plan plan;
+    Workspace* ws = nullptr;
+    lscan_status st = plan_locked(r, dev, nullptr, stream, &plan, &ws);
+    if (st != LSCAN_OK) return st;
+    e = plan.k->launch(plan.a, plan.grid, stream);
+    if (e != hipSuccess) return device_error(e);
+    ws->launches++;
+    return LSCAN_OK;
+}
+
 }  // namespace
 }  // namespace lscan
 
 using namespace lscan;
+
+// A captured launch with its own workspace (so graph replays never share
+// flags with eager launches).
+struct lscan_graph {
+    int dev = 0;
+    hipStream_t prep = nullptr;
+    Workspace ws;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+lscan_status graph_create(const Request& r, lscan_graph** out)
+{
+    if (!out) return LSCAN_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (r.empty) return LSCAN_ERR_INVALID_ARG;  // nothing to capture
+    lscan_graph* g = new (std::nothrow) lscan_graph();
+    if (!g) return LSCAN_ERR_NO_MEMORY;
+    auto fail = [&](lscan_status st) {
+        if (g->exec) (void)hipGraphExecDestroy(g->exec);
+        if (g->graph) (void)hipGraphDestroy(g->graph);
+        if (g->prep) (void)hipStreamSynchronize(g->prep);
+        free_workspace(g->ws);
+        if (g->prep) (void)hipStreamDestroy(g->prep);
+        delete g;
+        return st;
+    };
+    hipError_t e = hipGetDevice(&g->dev);
+    if (e != hipSuccess) return fail(device_error(e));
+    e = hipStreamCreateWithFlags(&g->prep, hipStreamNonBlocking);
+    if (e != hipSuccess) return fail(device_error(e));
+    Plan plan;
+    {
+        std::lock_guard<std::mutex> lock(g_mu);
+        lscan_status st = plan_locked(r, g->dev, &g->ws, g->prep, &plan, nullptr);
+        if (st != LSCAN_OK) return fail(st);
+    }
+    e = hipStreamSynchronize(g->prep);  // workspace zeroed, descriptors uploaded, residency known
+    if (e != hipSuccess) return fail(device_error(e));
+    e = hipStreamBeginCapture(g->prep, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return fail(device_error(e));
+    e = plan.k->launch(plan.a, plan.grid, g->prep);
+    hipGraph_t graph = nullptr;
+    hipError_t e2 = hipStreamEndCapture(g->prep, &graph);
+    g->graph = graph;
+    if (e != hipSuccess) return fail(device_error(e));
+    if (e2 != hipSuccess) return fail(device_error(e2));
+    e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) return fail(device_error(e));
+    *out = g;
+    return LSCAN_OK;
+}
+
+}  // namespace
 
 extern "C" {
 
 lscan_status lscan_inclusive(const void* x, void* y, int64_t n, lscan_dtype dt, lscan_op op, uint32_t flags,
                              void* stream)
 {
-    return run_scan(false, x, y, n, nullptr, 0, dt, op, flags, false, nullptr, stream);
+    Request r;
+    lscan_status st = make_request(kModePlain, x, y, n, nullptr, 0, nullptr, 0, dt, op, flags, false, nullptr, &r);
+    return st != LSCAN_OK ? st : run(r, stream);
 }
 
 lscan_status lscan_exclusive(const void* x, void* y, int64_t n, lscan_dtype dt, lscan_op op, uint32_t flags,
                              void* stream)
 {
-    return run_scan(false, x, y, n, nullptr, 0, dt, op, flags, true, nullptr, stream);
+    Request r;
+    lscan_status st = make_request(kModePlain, x, y, n, nullptr, 0, nullptr, 0, dt, op, flags, true, nullptr, &r);
+    return st != LSCAN_OK ? st : run(r, stream);
 }
 
 lscan_status lscan_segmented(const void* x, void* y, int64_t n_total, const int64_t* offsets,
                              int64_t num_segments, lscan_dtype dt, lscan_op op, uint32_t flags, void* stream)
 {
-    return run_scan(true, x, y, n_total, offsets, num_segments, dt, op, flags,
-                    (flags & LSCAN_F_EXCLUSIVE) != 0, nullptr, stream);
+    Request r;
+    lscan_status st = make_request(kModeSegmented, x, y, n_total, offsets, num_segments, nullptr, 0, dt, op, flags,
+                                   (flags & LSCAN_F_EXCLUSIVE) != 0, nullptr, &r);
+    return st != LSCAN_OK ? st : run(r, stream);
+}
+
+lscan_status lscan_batched(const lscan_array* arrays, int64_t count, lscan_dtype dt, lscan_op op, uint32_t flags,
+                           void* stream)
+{
+    Request r;
+    lscan_status st = make_request(kModeBatched, nullptr, nullptr, 0, nullptr, 0, arrays, count, dt, op, flags,
+                                   (flags & LSCAN_F_EXCLUSIVE) != 0, nullptr, &r);
+    return st != LSCAN_OK ? st : run(r, stream);
 }
 
 lscan_status lscan_scan_with_params(const void* x, void* y, int64_t n, lscan_dtype dt, lscan_op op,
                                     uint32_t flags, int32_t exclusive, const lscan_params* p, void* stream)
 {
-    return run_scan(false, x, y, n, nullptr, 0, dt, op, flags, exclusive != 0, p, stream);
+    Request r;
+    lscan_status st = make_request(kModePlain, x, y, n, nullptr, 0, nullptr, 0, dt, op, flags, exclusive != 0, p, &r);
+    return st != LSCAN_OK ? st : run(r, stream);
 }
 
 lscan_status lscan_segmented_with_params(const void* x, void* y, int64_t n_total, const int64_t* offsets,
                                          int64_t num_segments, lscan_dtype dt, lscan_op op, uint32_t flags,
                                          const lscan_params* p, void* stream)
 {
-    return run_scan(true, x, y, n_total, offsets, num_segments, dt, op, flags,
-                    (flags & LSCAN_F_EXCLUSIVE) != 0, p, stream);
+    Request r;
+    lscan_status st = make_request(kModeSegmented, x, y, n_total, offsets, num_segments, nullptr, 0, dt, op, flags,
+                                   (flags & LSCAN_F_EXCLUSIVE) != 0, p, &r);
+    return st != LSCAN_OK ? st : run(r, stream);
+}
+
+lscan_status lscan_batched_with_params(const lscan_array* arrays, int64_t count, lscan_dtype dt, lscan_op op,
+                                       uint32_t flags, const lscan_params* p, void* stream)
+{
+    Request r;
+    lscan_status st = make_request(kModeBatched, nullptr, nullptr, 0, nullptr, 0, arrays, count, dt, op, flags,
+                                   (flags & LSCAN_F_EXCLUSIVE) != 0, p, &r);
+    return st != LSCAN_OK ? st : run(r, stream);
+}
+
+lscan_status lscan_graph_create_segmented(const void* x, void* y, int64_t n_total, const int64_t* offsets,
+                                          int64_t num_segments, lscan_dtype dt, lscan_op op, uint32_t flags,
+                                          const lscan_params* p, lscan_graph** out)
+{
+    Request r;
+    lscan_status st = make_request(kModeSegmented, x, y, n_total, offsets, num_segments, nullptr, 0, dt, op, flags,
+                                   (flags & LSCAN_F_EXCLUSIVE) != 0, p, &r);
+    return st != LSCAN_OK ? st : graph_create(r, out);
+}
+
+lscan_status lscan_graph_create_batched(const lscan_array* arrays, int64_t count, lscan_dtype dt, lscan_op op,
+                                        uint32_t flags, const lscan_params* p, lscan_graph** out)
+{
+    Request r;
+    lscan_status st = make_request(kModeBatched, nullptr, nullptr, 0, nullptr, 0, arrays, count, dt, op, flags,
+                                   (flags & LSCAN_F_EXCLUSIVE) != 0, p, &r);
+    return st != LSCAN_OK ? st : graph_create(r, out);
+}
+
+lscan_status lscan_graph_launch(lscan_graph* g, void* stream_ptr)
+{
+    if (!g || !g->exec) return LSCAN_ERR_INVALID_ARG;
+    hipStream_t stream = static_cast<hipStream_t>(stream_ptr);
+    hipError_t e;
+    if (g->ws.launches >= kMaxLaunchesPerEpochRun) {
+        if (capturing(stream)) return LSCAN_ERR_UNSUPPORTED;
+        e = hipMemsetAsync(g->ws.slots, 0, g->ws.words * sizeof(uint64_t), stream);
+        if (e != hipSuccess) return device_error(e);
+        e = hipMemsetAsync(g->ws.ctrl, 0, 2 * sizeof(uint32_t), stream);
+        if (e != hipSuccess) return device_error(e);
+        g->ws.launches = 0;
+    }
+    e = hipGraphLaunch(g->exec, stream);
+    if (e != hipSuccess) return device_error(e);
+    g->ws.launches++;
+    return LSCAN_OK;
+}
+
+lscan_status lscan_graph_check(lscan_graph* g, void* stream_ptr)
+{
+    if (!g) return LSCAN_ERR_INVALID_ARG;
+    hipError_t e = hipStreamSynchronize(static_cast<hipStream_t>(stream_ptr));
+    if (e != hipSuccess) return device_error(e);
+    uint32_t flag = 0;
+    e = hipMemcpy(&flag, g->ws.ctrl + 2, sizeof(flag), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return device_error(e);
+    if (flag) {
+        const uint32_t zero = 0;
+        e = hipMemcpy(g->ws.ctrl + 2, &zero, sizeof(zero), hipMemcpyHostToDevice);
+        if (e != hipSuccess) return device_error(e);
+        return LSCAN_ERR_TIMEOUT;
+    }
+    return LSCAN_OK;
+}
+
+lscan_status lscan_graph_destroy(lscan_graph* g)
+{
+    if (!g) return LSCAN_ERR_INVALID_ARG;
+    hipError_t e = hipDeviceSynchronize();  // no replay may still use the workspace
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    free_workspace(g->ws);
+    if (g->prep) (void)hipStreamDestroy(g->prep);
+    delete g;
+    return e == hipSuccess ? LSCAN_OK : device_error(e);
 }
 
 int32_t lscan_num_tile_shapes(void) { return kNumShapes; }
@@ -437,15 +766,15 @@ lscan_status lscan_tile_shape(int32_t idx, lscan_params* out)
     return LSCAN_OK;
 }
 
-lscan_status lscan_get_params(lscan_dtype dt, lscan_op op, uint32_t flags, int32_t segmented, lscan_params* out)
+lscan_status lscan_get_params(lscan_dtype dt, lscan_op op, uint32_t flags, int32_t kind, lscan_params* out)
 {
-    if (!out) return LSCAN_ERR_INVALID_ARG;
-    const int oc = opcode_of(dt, op, flags);
+    if (!out || kind < 0 || kind >= kNumModes) return LSCAN_ERR_INVALID_ARG;
+    const int oc = opcode_of(dt, op, flags & LSCAN_F_COMPENSATED);
     if (oc == -1) return LSCAN_ERR_INVALID_ARG;
     if (oc == -2) return LSCAN_ERR_UNSUPPORTED;
     std::lock_guard<std::mutex> lock(g_mu);
     init_params_locked();
-    const Params& p = g_params[segmented ? 1 : 0][oc];
+    const Params& p = g_params[kind][oc];
     out->block_threads = kShapeThreads[p.shape];
     out->vectors_per_lane = kShapeVectors[p.shape];
     out->groups_per_cu = p.groups_per_cu;
@@ -453,10 +782,10 @@ lscan_status lscan_get_params(lscan_dtype dt, lscan_op op, uint32_t flags, int32
     return LSCAN_OK;
 }
 
-lscan_status lscan_set_params(lscan_dtype dt, lscan_op op, uint32_t flags, int32_t segmented, const lscan_params* p)
+lscan_status lscan_set_params(lscan_dtype dt, lscan_op op, uint32_t flags, int32_t kind, const lscan_params* p)
 {
-    if (!p) return LSCAN_ERR_INVALID_ARG;
-    const int oc = opcode_of(dt, op, flags);
+    if (!p || kind < 0 || kind >= kNumModes) return LSCAN_ERR_INVALID_ARG;
+    const int oc = opcode_of(dt, op, flags & LSCAN_F_COMPENSATED);
     if (oc == -1) return LSCAN_ERR_INVALID_ARG;
     if (oc == -2) return LSCAN_ERR_UNSUPPORTED;
     const int s = shape_index(p->block_threads, p->vectors_per_lane);
@@ -464,7 +793,7 @@ lscan_status lscan_set_params(lscan_dtype dt, lscan_op op, uint32_t flags, int32
     if (p->groups_per_cu <= 0) return LSCAN_ERR_INVALID_ARG;
     std::lock_guard<std::mutex> lock(g_mu);
     init_params_locked();
-    g_params[segmented ? 1 : 0][oc] = Params{s, p->groups_per_cu};
+    g_params[kind][oc] = Params{s, p->groups_per_cu};
     return LSCAN_OK;
 }
 
@@ -512,8 +841,7 @@ lscan_status lscan_release_workspaces(void)
     std::lock_guard<std::mutex> lock(g_mu);
     for (auto it = g_ws.begin(); it != g_ws.end();) {
         if (it->first.first == dev) {
-            if (it->second.slots) (void)hipFree(it->second.slots);
-            if (it->second.ctrl) (void)hipFree(it->second.ctrl);
+            free_workspace(it->second);
             it = g_ws.erase(it);
         } else {
             ++it;

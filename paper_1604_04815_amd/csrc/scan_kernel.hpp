@@ -207,57 +207,98 @@ __device__ __forceinline__ void check_residency(uint32_t* ctrl, uint64_t limit)
     }
 }
 
-template <class BaseOp, bool SEG>
-struct ScanOpOf {
-    using type = BaseOp;
+// Operators of each kernel flavour: ElemOp scans the elements of a block,
+// BlkOp combines block aggregates and prefixes.  Segmented scans carry head
+// flags at both levels; batched scans only at block level, because every
+// array starts on a block boundary.
+template <class BaseOp, int MODE>
+struct ModeOps {
+    using ElemOp = BaseOp;
+    using BlkOp = BaseOp;
 };
 template <class BaseOp>
-struct ScanOpOf<BaseOp, true> {
-    using type = Seg<BaseOp>;
+struct ModeOps<BaseOp, kModeSegmented> {
+    using ElemOp = Seg<BaseOp>;
+    using BlkOp = Seg<BaseOp>;
+};
+template <class BaseOp>
+struct ModeOps<BaseOp, kModeBatched> {
+    using ElemOp = BaseOp;
+    using BlkOp = Seg<BaseOp>;
 };
 
-template <class BaseOp, int T, int R, bool SEG>
+template <class BaseOp, int T, int R, int MODE>
 __global__ void __launch_bounds__(T) scan_kernel(ScanArgs a)
 {
-    using SOp = typename ScanOpOf<BaseOp, SEG>::type;
-    using V = typename SOp::V;
+    using EOp = typename ModeOps<BaseOp, MODE>::ElemOp;
+    using BOp = typename ModeOps<BaseOp, MODE>::BlkOp;
+    using V = typename EOp::V;    // element-level scan value
+    using VB = typename BOp::V;   // block-level value (aggregates, prefixes)
     using In = typename BaseOp::In;
     using Out = typename BaseOp::Out;
     constexpr int E = BaseOp::E;
     constexpr int NWAVE = T / 64;
-    constexpr int W = sizeof(V) / 4;
+    constexpr int W = sizeof(VB) / 4;
     constexpr int ROW = 64 * E;                  // elements per wave-row
     constexpr int64_t L = int64_t(T) * R * E;    // elements per data block
+    constexpr int kVecBytes = int(sizeof(In)) * E;
     static_assert(T % 64 == 0 && NWAVE <= 16, "wave64 workgroups of up to 1024 threads");
-
-    __shared__ V s_wave_total[2][NWAVE];
-    __shared__ V s_block_prefix[2];
-    __shared__ int s_abort[2];
 
     if (a.residency_check) {
         check_residency(a.ctrl, a.spin_limit);
         return;
     }
 
+    __shared__ V s_wave_total[2][NWAVE];
+    __shared__ VB s_block_prefix[2];
+    __shared__ int s_abort[2];
+
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    const In* x = static_cast<const In*>(a.x);
-    Out* y = static_cast<Out*>(a.y);
     const int64_t B = gridDim.x;
     const uint32_t tag = __hip_atomic_load(a.ctrl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1u;
 
-    V carry = SOp::identity();  // wave 0: P(i - B), the prefix through this group's previous block
+    VB carry = BOp::identity();  // wave 0: P(i - B), the prefix through this group's previous block
     int parity = 0;
     for (int64_t i = blockIdx.x; i < a.num_blocks; i += B, parity ^= 1) {
-        const int64_t tile0 = i * L;
+        // -- which array and which part of it this block covers
+        const In* x;
+        Out* y;
+        int64_t n, tile0;
+        bool vec_ok;
+        uint32_t block_head = 0;
+        if constexpr (MODE == kModeBatched) {
+            int64_t lo = 0, hi = a.num_arrays;  // last r with first_block <= i
+            while (hi - lo > 1) {
+                const int64_t mid = (lo + hi) >> 1;
+                if (a.arrays[mid].first_block <= i)
+                    lo = mid;
+                else
+                    hi = mid;
+            }
+            const BatchArray d = a.arrays[lo];
+            x = static_cast<const In*>(d.x);
+            y = static_cast<Out*>(d.y);
+            n = d.n;
+            tile0 = (i - d.first_block) * L;
+            block_head = (tile0 == 0) ? 1u : 0u;
+            vec_ok = (reinterpret_cast<uintptr_t>(d.x) % uintptr_t(kVecBytes) == 0) &&
+                     (reinterpret_cast<uintptr_t>(d.y) % 16 == 0);
+        } else {
+            x = static_cast<const In*>(a.x);
+            y = static_cast<Out*>(a.y);
+            n = a.n;
+            tile0 = i * L;
+            vec_ok = a.vec_ok != 0;
+        }
         const int64_t lane0 = tile0 + int64_t(wave) * (R * ROW) + int64_t(lane) * E;
-        const bool full = a.vec_ok && (tile0 + L <= a.n);
+        const bool full = vec_ok && (tile0 + L <= n);
 
         // -- segment heads inside this lane's vectors (segmented scans only)
         uint32_t head[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) head[r] = 0;
-        if constexpr (SEG) {
+        if constexpr (MODE == kModeSegmented) {
             const int64_t S = a.num_segments;
             const int64_t s_lo = lower_bound_i64(a.offsets, 0, S, tile0);
             const int64_t s_hi = lower_bound_i64(a.offsets, s_lo, S, tile0 + L);
@@ -287,8 +328,8 @@ __global__ void __launch_bounds__(T) scan_kernel(ScanArgs a)
             for (int r = 0; r < R; ++r)
 #pragma unroll
                 for (int k = 0; k < E; ++k) {
-                    if constexpr (SEG)
-                        e[r][k] = SOp::make(BaseOp::lift(raw[r][k]), (head[r] >> k) & 1u);
+                    if constexpr (MODE == kModeSegmented)
+                        e[r][k] = EOp::make(BaseOp::lift(raw[r][k]), (head[r] >> k) & 1u);
                     else
                         e[r][k] = BaseOp::lift(raw[r][k]);
                 }
@@ -298,13 +339,13 @@ __global__ void __launch_bounds__(T) scan_kernel(ScanArgs a)
 #pragma unroll
                 for (int k = 0; k < E; ++k) {
                     const int64_t p = lane0 + int64_t(r) * ROW + k;
-                    if (p < a.n) {
-                        if constexpr (SEG)
-                            e[r][k] = SOp::make(BaseOp::lift(x[p]), (head[r] >> k) & 1u);
+                    if (p < n) {
+                        if constexpr (MODE == kModeSegmented)
+                            e[r][k] = EOp::make(BaseOp::lift(x[p]), (head[r] >> k) & 1u);
                         else
                             e[r][k] = BaseOp::lift(x[p]);
                     } else {
-                        e[r][k] = SOp::identity();
+                        e[r][k] = EOp::identity();
                     }
                 }
         }
@@ -313,21 +354,21 @@ __global__ void __launch_bounds__(T) scan_kernel(ScanArgs a)
 #pragma unroll
         for (int r = 0; r < R; ++r)
 #pragma unroll
-            for (int k = 1; k < E; ++k) e[r][k] = SOp::combine(e[r][k - 1], e[r][k]);
+            for (int k = 1; k < E; ++k) e[r][k] = EOp::combine(e[r][k - 1], e[r][k]);
 
         V lane_prefix[R];  // exclusive cross-lane prefix within the row
         V row_total[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            const V s = wave_inclusive_scan<SOp>(e[r][E - 1]);
+            const V s = wave_inclusive_scan<EOp>(e[r][E - 1]);
             row_total[r] = read_lane(s, 63);
-            lane_prefix[r] = wave_shift_right<SOp>(s);
+            lane_prefix[r] = wave_shift_right<EOp>(s);
         }
         V row_prefix[R];  // rows chained in order (wave-uniform)
-        row_prefix[0] = SOp::identity();
+        row_prefix[0] = EOp::identity();
 #pragma unroll
-        for (int r = 1; r < R; ++r) row_prefix[r] = SOp::combine(row_prefix[r - 1], row_total[r - 1]);
-        const V wave_total = SOp::combine(row_prefix[R - 1], row_total[R - 1]);
+        for (int r = 1; r < R; ++r) row_prefix[r] = EOp::combine(row_prefix[r - 1], row_total[r - 1]);
+        const V wave_total = EOp::combine(row_prefix[R - 1], row_total[R - 1]);
 
         // -- 3. intra-block local scan through LDS
         if (lane == 0) s_wave_total[parity][wave] = wave_total;
@@ -335,16 +376,21 @@ __global__ void __launch_bounds__(T) scan_kernel(ScanArgs a)
 
         // -- 4. inter-block communication (wave 0)
         if (wave == 0) {
-            V agg = s_wave_total[parity][0];
+            V agg_e = s_wave_total[parity][0];
 #pragma unroll
-            for (int w = 1; w < NWAVE; ++w) agg = SOp::combine(agg, s_wave_total[parity][w]);
+            for (int w = 1; w < NWAVE; ++w) agg_e = EOp::combine(agg_e, s_wave_total[parity][w]);
+            VB agg;
+            if constexpr (MODE == kModeBatched)
+                agg = BOp::make(agg_e, block_head);
+            else
+                agg = agg_e;
             publish_slot(a.slots + i * W, agg, tag, lane);
 
             const int64_t cnt = (i < B - 1) ? i : (B - 1);
             bool ok = true;
-            const V win = window_fold<SOp>(a.slots, i - cnt, cnt, tag, a.spin_limit, lane, ok);
-            const V prefix = SOp::combine(carry, win);  // P(i - 1)
-            carry = SOp::combine(prefix, agg);          // P(i)
+            const VB win = window_fold<BOp>(a.slots, i - cnt, cnt, tag, a.spin_limit, lane, ok);
+            const VB prefix = BOp::combine(carry, win);  // P(i - 1)
+            carry = BOp::combine(prefix, agg);           // P(i)
             const bool abort = __ballot(!ok) != 0;
             if (lane == 0) {
                 s_block_prefix[parity] = prefix;
@@ -356,18 +402,24 @@ __global__ void __launch_bounds__(T) scan_kernel(ScanArgs a)
         if (s_abort[parity]) break;
 
         // -- 5. intra-block global scan and one coalesced store per vector
-        V prefix = s_block_prefix[parity];
-        for (int w = 0; w < wave; ++w) prefix = SOp::combine(prefix, s_wave_total[parity][w]);
+        V prefix;
+        if constexpr (MODE == kModeBatched) {
+            // the first block of an array starts from the identity
+            prefix = block_head ? EOp::identity() : s_block_prefix[parity].v;
+        } else {
+            prefix = s_block_prefix[parity];
+        }
+        for (int w = 0; w < wave; ++w) prefix = EOp::combine(prefix, s_wave_total[parity][w]);
 
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            const V lp = SOp::combine(SOp::combine(prefix, row_prefix[r]), lane_prefix[r]);
+            const V lp = EOp::combine(EOp::combine(prefix, row_prefix[r]), lane_prefix[r]);
             Out out[E];
             if (!a.exclusive) {
 #pragma unroll
                 for (int k = 0; k < E; ++k) {
-                    const V v = SOp::combine(lp, e[r][k]);
-                    if constexpr (SEG)
+                    const V v = EOp::combine(lp, e[r][k]);
+                    if constexpr (MODE == kModeSegmented)
                         out[k] = BaseOp::lower(v.v);
                     else
                         out[k] = BaseOp::lower(v);
@@ -375,8 +427,8 @@ __global__ void __launch_bounds__(T) scan_kernel(ScanArgs a)
             } else {
 #pragma unroll
                 for (int k = 0; k < E; ++k) {
-                    const V v = (k == 0) ? lp : SOp::combine(lp, e[r][k - 1]);
-                    if constexpr (SEG)
+                    const V v = (k == 0) ? lp : EOp::combine(lp, e[r][k - 1]);
+                    if constexpr (MODE == kModeSegmented)
                         out[k] = ((head[r] >> k) & 1u) ? BaseOp::lower(BaseOp::identity()) : BaseOp::lower(v.v);
                     else
                         out[k] = BaseOp::lower(v);
@@ -388,7 +440,7 @@ __global__ void __launch_bounds__(T) scan_kernel(ScanArgs a)
             } else {
 #pragma unroll
                 for (int k = 0; k < E; ++k)
-                    if (p + k < a.n) y[p + k] = out[k];
+                    if (p + k < n) y[p + k] = out[k];
             }
         }
     }
@@ -407,47 +459,47 @@ __global__ void __launch_bounds__(T) scan_kernel(ScanArgs a)
 // ---------------------------------------------------------------------------
 // Registration helpers used by the instantiation units.
 // ---------------------------------------------------------------------------
-template <class BaseOp, bool SEG, int T, int R>
+template <class BaseOp, int MODE, int T, int R>
 hipError_t launch_scan(const ScanArgs& a, int grid, hipStream_t stream)
 {
     (void)hipGetLastError();  // a stale error from earlier work must not be read as this launch's
-    hipLaunchKernelGGL((scan_kernel<BaseOp, T, R, SEG>), dim3(grid), dim3(T), 0, stream, a);
+    hipLaunchKernelGGL((scan_kernel<BaseOp, T, R, MODE>), dim3(grid), dim3(T), 0, stream, a);
     return hipGetLastError();
 }
 
-template <class BaseOp, bool SEG, int S>
+template <class BaseOp, int MODE, int S>
 KernelEntry make_entry()
 {
     constexpr int T = kShapeThreads[S];
     constexpr int R = kShapeVectors[S];
-    using SOp = typename ScanOpOf<BaseOp, SEG>::type;
+    using BOp = typename ModeOps<BaseOp, MODE>::BlkOp;
     KernelEntry k;
-    k.func = reinterpret_cast<const void*>(&scan_kernel<BaseOp, T, R, SEG>);
-    k.launch = &launch_scan<BaseOp, SEG, T, R>;
+    k.func = reinterpret_cast<const void*>(&scan_kernel<BaseOp, T, R, MODE>);
+    k.launch = &launch_scan<BaseOp, MODE, T, R>;
     k.block_threads = T;
     k.vectors_per_lane = R;
     k.elems_per_vec = BaseOp::E;
-    k.slot_words = int(sizeof(typename SOp::V) / 4);
+    k.slot_words = int(sizeof(typename BOp::V) / 4);
     k.in_bytes = int(sizeof(typename BaseOp::In));
     k.out_bytes = int(sizeof(typename BaseOp::Out));
     k.tile_elems = int64_t(T) * R * BaseOp::E;
     return k;
 }
 
-template <class BaseOp, bool SEG>
+template <class BaseOp, int MODE>
 void fill_row(KernelTable& t, int opcode)
 {
-    KernelEntry* row = t[SEG ? 1 : 0][opcode];
-    row[0] = make_entry<BaseOp, SEG, 0>();
-    row[1] = make_entry<BaseOp, SEG, 1>();
-    row[2] = make_entry<BaseOp, SEG, 2>();
-    row[3] = make_entry<BaseOp, SEG, 3>();
-    row[4] = make_entry<BaseOp, SEG, 4>();
-    row[5] = make_entry<BaseOp, SEG, 5>();
-    row[6] = make_entry<BaseOp, SEG, 6>();
-    row[7] = make_entry<BaseOp, SEG, 7>();
-    row[8] = make_entry<BaseOp, SEG, 8>();
-    row[9] = make_entry<BaseOp, SEG, 9>();
+    KernelEntry* row = t[MODE][opcode];
+    row[0] = make_entry<BaseOp, MODE, 0>();
+    row[1] = make_entry<BaseOp, MODE, 1>();
+    row[2] = make_entry<BaseOp, MODE, 2>();
+    row[3] = make_entry<BaseOp, MODE, 3>();
+    row[4] = make_entry<BaseOp, MODE, 4>();
+    row[5] = make_entry<BaseOp, MODE, 5>();
+    row[6] = make_entry<BaseOp, MODE, 6>();
+    row[7] = make_entry<BaseOp, MODE, 7>();
+    row[8] = make_entry<BaseOp, MODE, 8>();
+    row[9] = make_entry<BaseOp, MODE, 9>();
     static_assert(kNumShapes == 10, "one entry per compiled shape");
 }
 

@@ -121,3 +121,55 @@ def test_raising_wrappers(lib):
     with pytest.raises(binding.LscanError) as ei:
         binding.lscan_inclusive(FAKE_X, FAKE_Y, -5, binding.I32, binding.ADD)
     assert ei.value.status == binding.ERR_INVALID_ARG
+
+
+def _table(entries):
+    tab = (binding.Array * max(1, len(entries)))()
+    for i, (x, y, n) in enumerate(entries):
+        tab[i].x, tab[i].y, tab[i].n = x, y, n
+    return tab
+
+
+@pytest.mark.parametrize("entries,count,status", [
+    ([], 0, binding.OK),                                         # nothing to do
+    ([(None, None, 0), (None, None, 0)], 2, binding.OK),         # all empty
+    ([(FAKE_X, FAKE_Y, 8)], -1, binding.ERR_INVALID_ARG),        # negative count
+    ([(FAKE_X, FAKE_Y, -3)], 1, binding.ERR_INVALID_ARG),        # negative length
+    ([(FAKE_X, None, 8)], 1, binding.ERR_INVALID_ARG),           # null y
+    ([(FAKE_X + 2, FAKE_Y, 8)], 1, binding.ERR_INVALID_ARG),     # misaligned x
+    ([(FAKE_X, FAKE_X + 8, 8)], 1, binding.ERR_INVALID_ARG),     # partial overlap
+    ([(FAKE_X, FAKE_Y, 8), (FAKE_X, FAKE_Y + 4, -1)], 2, binding.ERR_INVALID_ARG),
+])
+def test_batched_validation(lib, entries, count, status):
+    tab = _table(entries)
+    assert lib.lscan_batched(tab, count, binding.I32, binding.ADD, 0, None) == status
+
+
+def test_batched_null_table(lib):
+    assert lib.lscan_batched(None, 3, binding.I32, binding.ADD, 0, None) == binding.ERR_INVALID_ARG
+    assert lib.lscan_batched(None, 0, binding.I32, binding.ADD, 0, None) == binding.OK
+
+
+def test_graph_validation(lib):
+    h = ctypes.c_void_p()
+    # nothing to capture
+    st = lib.lscan_graph_create_segmented(None, None, 0, None, 0, binding.I32, binding.ADD, 0, None,
+                                          ctypes.byref(h))
+    assert st == binding.ERR_INVALID_ARG
+    st = lib.lscan_graph_create_batched(_table([]), 0, binding.I32, binding.ADD, 0, None, ctypes.byref(h))
+    assert st == binding.ERR_INVALID_ARG
+    # bad arguments are rejected before any device work
+    st = lib.lscan_graph_create_segmented(FAKE_X, FAKE_Y, 8, FAKE_X, -1, binding.I32, binding.ADD, 0, None,
+                                          ctypes.byref(h))
+    assert st == binding.ERR_INVALID_ARG
+    assert lib.lscan_graph_launch(None, None) == binding.ERR_INVALID_ARG
+    assert lib.lscan_graph_destroy(None) == binding.ERR_INVALID_ARG
+
+
+def test_params_kinds(lib):
+    p = binding.Params()
+    for kind in (binding.KIND_PLAIN, binding.KIND_SEGMENTED, binding.KIND_BATCHED):
+        assert lib.lscan_get_params(binding.F32, binding.ADD, binding.F_COMPENSATED, kind, ctypes.byref(p)) == 0
+    assert lib.lscan_get_params(binding.F32, binding.ADD, 0, 3, ctypes.byref(p)) == binding.ERR_INVALID_ARG
+    assert lib.lscan_get_params(binding.I32, binding.MAX, binding.F_COMPENSATED, 0,
+                                ctypes.byref(p)) == binding.ERR_UNSUPPORTED

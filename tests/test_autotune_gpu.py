@@ -1,0 +1,40 @@
+"""The autotuner on the device: it times candidates, installs the winner as
+the default, and scans with the winner stay exact."""
+import torch
+import pytest
+
+from gpu_util import compare, make_input, to_device, to_host
+
+pytestmark = pytest.mark.gpu
+
+
+def test_tune_apply_and_scan(gpu_lib, tmp_path):
+    from paper_1604_04815_amd import autotune
+    x_host = make_input("int32", "add", 6_000_001, seed=12)
+    x = to_device(x_host, "int32")
+    before = gpu_lib.lscan_get_params(gpu_lib.I32, gpu_lib.ADD)
+    e = autotune.tune(x, "add", shapes=[(256, 8), (512, 4), (1024, 2)], groups=(1, 2, 4), reps=3, warmup=1)
+    assert e.tried >= 3 and e.gbs > 0
+    cache = autotune.Cache(str(tmp_path / "t.json"))
+    cache.put(e)
+    cache.save()
+    assert autotune.apply_cache(str(tmp_path / "t.json")) == 1
+    now = gpu_lib.lscan_get_params(gpu_lib.I32, gpu_lib.ADD)
+    assert (now.block_threads, now.vectors_per_lane) == (e.block_threads, e.vectors_per_lane)
+    y = gpu_lib.inclusive(x, "add")
+    compare(to_host(y), x_host, "int32", "add", False, what="tuned default")
+    gpu_lib.lscan_set_params(gpu_lib.I32, gpu_lib.ADD, 0, gpu_lib.KIND_PLAIN, before)
+
+
+def test_tune_batched_and_segmented(gpu_lib):
+    from paper_1604_04815_amd import autotune, workloads as w
+    xs = [to_device(make_input("float32", "add", n, seed=n), "float32") for n in (1000, 200_000, 3_000_000)]
+    e = autotune.tune(None, "add", compensated=True, kind="batched", arrays=xs, shapes=[(256, 8), (1024, 4)],
+                      groups=(1, 2), reps=2, warmup=1)
+    assert e.kind == "batched" and e.compensated
+    off = w.segment_offsets(64, 1 << 14, seed=2)
+    xh = make_input("int32", "add", int(off[-1]), seed=3)
+    od = torch.from_numpy(off).to("cuda")
+    e = autotune.tune(to_device(xh, "int32"), "add", kind="segmented", offsets=od, shapes=[(256, 8), (512, 4)],
+                      groups=(1, 2), reps=2, warmup=1)
+    assert e.kind == "segmented"

@@ -1,0 +1,97 @@
+"""Parity of the many-array batched scan and of graph-captured launches with
+the CPU oracle."""
+import numpy as np
+import pytest
+import torch
+
+from gpu_util import compare, log, make_input, to_device, to_host
+
+pytestmark = pytest.mark.gpu
+
+CASES = [("int32", "add", False), ("int32", "min", False), ("int64", "add", False), ("int64", "max", False),
+         ("float32", "add", False), ("float32", "add", True), ("float32", "max", False),
+         ("bfloat16", "add", False), ("bfloat16", "add", True), ("bfloat16", "max", False)]
+
+
+def tile_len(gpu_lib, dtype):
+    t = {"int32": torch.int32, "int64": torch.int64, "float32": torch.float32, "bfloat16": torch.bfloat16}[dtype]
+    x = torch.zeros(1 << 16, dtype=t, device="cuda")
+    gpu_lib.batched([x])
+    return int(gpu_lib.lscan_last_launch().tile_elems)
+
+
+@pytest.mark.parametrize("dtype,op,comp", CASES, ids=[f"{d}-{o}{'-comp' if c else ''}" for d, o, c in CASES])
+def test_batched_mixed_sizes(gpu_lib, dtype, op, comp):
+    L = tile_len(gpu_lib, dtype)
+    rng = np.random.default_rng(11)
+    sizes = [0, 1, 2, 63, L - 1, L, L + 1, 3 * L + 5, 0, 1000, 100_000, 1_234_567]
+    sizes += [int(v) for v in np.floor(np.exp(rng.uniform(0, np.log(300_000), 40)))]
+    xs_host = [make_input(dtype, op, n, seed=100 + k) for k, n in enumerate(sizes)]
+    xs = [to_device(x, dtype) for x in xs_host]
+    log(f"[batched] {dtype} {op} comp={comp} arrays={len(xs)} L={L}")
+    for excl in (False, True):
+        ys = gpu_lib.batched(xs, op, exclusive=excl, compensated=comp)
+        gpu_lib.lscan_check(torch.cuda.current_stream().cuda_stream)
+        for k, (xh, y) in enumerate(zip(xs_host, ys)):
+            compare(to_host(y), xh, dtype, op, excl, comp, what=f"batched {dtype}/{op} array {k} n={xh.size}")
+
+
+def test_batched_equals_alone_for_exact_ops(gpu_lib):
+    xs_host = [make_input("int32", "add", n, seed=n) for n in (5, 70_000, 3_000_001, 123)]
+    xs = [to_device(x, "int32") for x in xs_host]
+    ys = gpu_lib.batched(xs, "add")
+    for x, y in zip(xs, ys):
+        assert torch.equal(y, gpu_lib.inclusive(x, "add"))
+
+
+def test_batched_in_place_and_unaligned(gpu_lib):
+    xs_host = [make_input("int32", "add", n, seed=n) for n in (10_001, 40_000, 7)]
+    xs = [to_device(x, "int32") for x in xs_host]
+    base = to_device(make_input("float32", "max", 50_001, seed=3), "float32")
+    gpu_lib.lscan_batched([(x.data_ptr(), x.data_ptr(), x.shape[0]) for x in xs], gpu_lib.I32, gpu_lib.ADD)
+    for xh, x in zip(xs_host, xs):
+        compare(to_host(x), xh, "int32", "add", False, what="batched in place")
+    xu = base[1:]
+    yu = torch.empty(50_001, dtype=torch.float32, device="cuda")[1:]
+    gpu_lib.batched([xu], "max", outs=[yu])
+    compare(to_host(yu), to_host(xu), "float32", "max", False, what="batched unaligned")
+
+
+def test_graph_segmented_replays(gpu_lib):
+    from paper_1604_04815_amd import workloads as w
+    off = w.segment_offsets(512, 1 << 14, seed=5)
+    n = int(off[-1])
+    xd = torch.empty(n, dtype=torch.int32, device="cuda")
+    yd = torch.empty_like(xd)
+    od = torch.from_numpy(off).to("cuda")
+    g = gpu_lib.lscan_graph_create_segmented(xd.data_ptr(), yd.data_ptr(), n, od.data_ptr(), off.size - 1,
+                                             gpu_lib.I32, gpu_lib.ADD)
+    for rep in range(5):
+        x = make_input("int32", "add", n, seed=700 + rep)
+        xd.copy_(torch.from_numpy(x))
+        g.launch()
+        g.check()
+        compare(to_host(yd), x, "int32", "add", False, offsets=off, what=f"graph replay {rep}")
+        # eager work in between replays, on the same stream
+        z = gpu_lib.inclusive(xd, "max")
+        torch.cuda.synchronize()
+        compare(to_host(z), x, "int32", "max", False, what=f"eager between replays {rep}")
+    g.destroy()
+
+
+def test_graph_batched_replays(gpu_lib):
+    sizes = [1, 4097, 100_000, 0, 65_536, 3]
+    xs = [torch.empty(n, dtype=torch.float32, device="cuda") for n in sizes]
+    ys = [torch.empty_like(x) for x in xs]
+    g = gpu_lib.lscan_graph_create_batched([(x.data_ptr(), y.data_ptr(), x.shape[0]) for x, y in zip(xs, ys)],
+                                           gpu_lib.F32, gpu_lib.ADD, gpu_lib.F_COMPENSATED)
+    for rep in range(4):
+        hosts = [make_input("float32", "add", n, seed=900 + 7 * rep + k) for k, n in enumerate(sizes)]
+        for x, h in zip(xs, hosts):
+            x.copy_(torch.from_numpy(h))
+        g.launch()
+        g.check()
+        for k, (h, y) in enumerate(zip(hosts, ys)):
+            compare(to_host(y), h, "float32", "add", False, True, what=f"graph batched replay {rep} array {k}")
+        torch.cumsum(xs[2], 0)  # unrelated eager work on the stream
+    g.destroy()

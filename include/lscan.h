@@ -230,6 +230,75 @@ lscan_status lscan_graph_launch(lscan_graph *g, void *stream);
 lscan_status lscan_graph_check(lscan_graph *g, void *stream);
 lscan_status lscan_graph_destroy(lscan_graph *g);
 
+/*
+ * Request server (continuous batching).  Requests are submitted one at a
+ * time and polled by ticket; a scheduler thread groups pending requests with
+ * the same (dtype, operator, flags) into one lscan_batched launch whenever
+ * one of num_streams stream slots is free, so requests that arrive while
+ * others run are launched as soon as a slot and budget allow, and batches on
+ * different streams run on the device at the same time.
+ *   Admission: a request holds n * (sizeof input + sizeof output) bytes of
+ *   the HBM budget from launch to completion.  submit returns
+ *   LSCAN_ERR_NO_MEMORY if one request exceeds the whole budget and
+ *   LSCAN_ERR_AGAIN if max_queue requests are already pending.  Requests are
+ *   launched oldest first: the oldest pending request fixes each batch's
+ *   key, later requests of that key join it in submit order while the budget
+ *   allows, and a request that does not fit waits (nothing of its key
+ *   overtakes it).
+ *   Ownership: x and y are device pointers owned by the caller and must stay
+ *   valid until lscan_poll / lscan_wait returns a final status.
+ *   Co-residency: every batch launches groups_per_cu workgroups per CU and
+ *   num_streams * groups_per_cu <= 3 is enforced, so the persistent grids of
+ *   all streams fit on the device together.
+ * lscan_poll returns LSCAN_PENDING (result partly filled) or the final
+ * status, and forgets a ticket once it has reported its final status;
+ * lscan_wait blocks until then.  lscan_server_destroy finishes every
+ * submitted request first.  All timestamps are steady-clock nanoseconds.
+ */
+typedef struct {
+    int32_t device;
+    int32_t num_streams;       /* concurrent batches (default 2) */
+    uint64_t hbm_budget_bytes; /* bytes of requests in flight (default 32 GiB) */
+    int32_t max_queue;         /* pending requests (default 65536) */
+    int32_t max_batch;         /* arrays per launch (default 4096) */
+    int32_t groups_per_cu;     /* workgroups per CU per batch (default 1) */
+    int32_t reserved;
+} lscan_server_config;
+
+typedef struct {
+    lscan_dtype dt;
+    lscan_op op;
+    uint32_t flags; /* LSCAN_F_EXCLUSIVE, LSCAN_F_COMPENSATED */
+    int32_t reserved;
+    int64_t n;
+    const void *x;  /* device */
+    void *y;        /* device */
+} lscan_request;
+
+typedef struct {
+    lscan_status status; /* LSCAN_PENDING, LSCAN_OK or an error */
+    int32_t batch_size;  /* requests in the launch that carried it */
+    uint64_t batch_id;
+    uint64_t t_submit_ns, t_admit_ns, t_launch_ns, t_done_ns;
+} lscan_result;
+
+typedef struct {
+    uint64_t submitted, completed, failed, batches;
+    uint64_t bytes_in_flight, peak_bytes_in_flight;
+    int64_t pending;
+} lscan_server_stats;
+
+typedef struct lscan_server lscan_server;
+lscan_status lscan_server_default_config(lscan_server_config *cfg);
+lscan_status lscan_server_create(const lscan_server_config *cfg,
+                                 lscan_server **out);
+lscan_status lscan_submit(lscan_server *s, const lscan_request *r,
+                          uint64_t *ticket);
+lscan_status lscan_poll(lscan_server *s, uint64_t ticket, lscan_result *out);
+lscan_status lscan_wait(lscan_server *s, uint64_t ticket, lscan_result *out);
+lscan_status lscan_server_get_stats(lscan_server *s, lscan_server_stats *out);
+lscan_status lscan_server_destroy(lscan_server *s);
+
 /* Shape of the last launch made by the calling thread. */
 typedef struct {
     int64_t n;             /* elements */

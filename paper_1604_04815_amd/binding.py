@@ -51,6 +51,30 @@ class LaunchInfo(ctypes.Structure):
                 ("groups_per_cu", ctypes.c_int32), ("occupancy", ctypes.c_int32)]
 
 
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("device", ctypes.c_int32), ("num_streams", ctypes.c_int32),
+                ("hbm_budget_bytes", ctypes.c_uint64), ("max_queue", ctypes.c_int32),
+                ("max_batch", ctypes.c_int32), ("groups_per_cu", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("dt", ctypes.c_int32), ("op", ctypes.c_int32), ("flags", ctypes.c_uint32),
+                ("reserved", ctypes.c_int32), ("n", ctypes.c_int64), ("x", ctypes.c_void_p),
+                ("y", ctypes.c_void_p)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("batch_size", ctypes.c_int32), ("batch_id", ctypes.c_uint64),
+                ("t_submit_ns", ctypes.c_uint64), ("t_admit_ns", ctypes.c_uint64),
+                ("t_launch_ns", ctypes.c_uint64), ("t_done_ns", ctypes.c_uint64)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64), ("failed", ctypes.c_uint64),
+                ("batches", ctypes.c_uint64), ("bytes_in_flight", ctypes.c_uint64),
+                ("peak_bytes_in_flight", ctypes.c_uint64), ("pending", ctypes.c_int64)]
+
+
 _lib = None
 
 # Every symbol declared in include/lscan.h, with its ctypes signature.
@@ -76,6 +100,13 @@ SIGNATURES = {
     "lscan_graph_launch": ([_vp, _vp], _i32),
     "lscan_graph_check": ([_vp, _vp], _i32),
     "lscan_graph_destroy": ([_vp], _i32),
+    "lscan_server_default_config": ([ctypes.POINTER(ServerConfig)], _i32),
+    "lscan_server_create": ([ctypes.POINTER(ServerConfig), ctypes.POINTER(_vp)], _i32),
+    "lscan_submit": ([_vp, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)], _i32),
+    "lscan_poll": ([_vp, ctypes.c_uint64, ctypes.POINTER(Result)], _i32),
+    "lscan_wait": ([_vp, ctypes.c_uint64, ctypes.POINTER(Result)], _i32),
+    "lscan_server_get_stats": ([_vp, ctypes.POINTER(ServerStats)], _i32),
+    "lscan_server_destroy": ([_vp], _i32),
     "lscan_last_launch": ([ctypes.POINTER(LaunchInfo)], _i32),
     "lscan_check": ([_vp], _i32),
     "lscan_release_workspaces": ([], _i32),
@@ -360,3 +391,65 @@ def batched(xs, op="add", exclusive=False, compensated=False, outs=None, stream=
     flags = (F_COMPENSATED if compensated else 0) | (F_EXCLUSIVE if exclusive else 0)
     lscan_batched(table, dt, OPS[op], flags, _stream(stream), params)
     return ys
+
+
+class Server:
+    """Request server (lscan_server_*): submit device arrays, poll tickets."""
+
+    def __init__(self, device=0, num_streams=2, hbm_budget_bytes=32 << 30, max_queue=1 << 16, max_batch=4096,
+                 groups_per_cu=1):
+        lib = load()
+        cfg = ServerConfig()
+        _check(lib.lscan_server_default_config(ctypes.byref(cfg)), "lscan_server_default_config")
+        cfg.device, cfg.num_streams, cfg.hbm_budget_bytes = device, num_streams, hbm_budget_bytes
+        cfg.max_queue, cfg.max_batch, cfg.groups_per_cu = max_queue, max_batch, groups_per_cu
+        h = ctypes.c_void_p()
+        _check(lib.lscan_server_create(ctypes.byref(cfg), ctypes.byref(h)), "lscan_server_create")
+        self.handle = h.value
+        self._req = Request()
+        self._ticket = ctypes.c_uint64()
+        self._res = Result()
+
+    def submit_raw(self, x_ptr, y_ptr, n, dt, op, flags=0) -> int:
+        """Returns a ticket (> 0) or a negative status (no exception)."""
+        r = self._req
+        r.dt, r.op, r.flags, r.n, r.x, r.y = dt, op, flags, n, x_ptr, y_ptr
+        st = load().lscan_submit(self.handle, ctypes.byref(r), ctypes.byref(self._ticket))
+        return int(self._ticket.value) if st == OK else st
+
+    def submit(self, x, y, op="add", exclusive=False, compensated=False) -> int:
+        _flat(x, "x")
+        _flat(y, "y")
+        flags = (F_COMPENSATED if compensated else 0) | (F_EXCLUSIVE if exclusive else 0)
+        t = self.submit_raw(x.data_ptr(), y.data_ptr(), x.shape[0], dtype_code(x), OPS[op], flags)
+        if t < 0:
+            raise LscanError(t, "lscan_submit")
+        return t
+
+    def poll(self, ticket: int):
+        """(status, Result copy); status is PENDING, OK or an error code."""
+        st = load().lscan_poll(self.handle, ticket, ctypes.byref(self._res))
+        res = Result()
+        ctypes.pointer(res)[0] = self._res
+        return st, res
+
+    def wait(self, ticket: int):
+        res = Result()
+        st = load().lscan_wait(self.handle, ticket, ctypes.byref(res))
+        return st, res
+
+    def stats(self) -> ServerStats:
+        s = ServerStats()
+        _check(load().lscan_server_get_stats(self.handle, ctypes.byref(s)), "lscan_server_get_stats")
+        return s
+
+    def close(self):
+        if self.handle:
+            _check(load().lscan_server_destroy(self.handle), "lscan_server_destroy")
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -14,6 +14,7 @@
 
 #include "kernel_table.hpp"
 #include "lscan.h"
+#include "runtime_internal.hpp"
 
 namespace lscan {
 namespace {
@@ -564,6 +565,18 @@ lscan_status run(const Request& r, void* stream_ptr)
 }
 
 }  // namespace
+
+lscan_status validate_request(const void* x, const void* y, int64_t n, int dt, int op, uint32_t flags)
+{
+    if (flags & ~(LSCAN_F_COMPENSATED | LSCAN_F_EXCLUSIVE)) return LSCAN_ERR_INVALID_ARG;
+    const int oc = opcode_of(dt, op, flags);
+    if (oc == -1) return LSCAN_ERR_INVALID_ARG;
+    if (oc == -2) return LSCAN_ERR_UNSUPPORTED;
+    return check_array(x, y, n, dt);
+}
+
+uint64_t request_bytes(int64_t n, int dt) { return uint64_t(n) * uint64_t(in_bytes_of(dt) + out_bytes_of(dt)); }
+
 }  // namespace lscan
 
 using namespace lscan;

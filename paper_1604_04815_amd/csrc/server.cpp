@@ -1,0 +1,387 @@
+// server.cpp -- request loop on top of the batched scan: submit / poll
+// tickets, admission against an HBM byte budget, continuous batching of
+// pending requests into one persistent launch per (dtype, operator, flags),
+// and several streams so that batches overlap on the device.
+//
+// Co-residency: every batch launches with `groups_per_cu` workgroups per CU
+// of the 256-thread x 8-vector batched kernels (one wave per SIMD per
+// workgroup), and num_streams * groups_per_cu <= 3, so at most three of
+// those waves share a SIMD.  Each of those kernels allocates at most 144
+// VGPRs per wave on gfx950 (the compensated ones; the others 96-104), and
+// 3 * 144 <= 512, so the grids of all streams always fit together.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <memory>
+#include <mutex>
+#include <new>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "lscan.h"
+#include "runtime_internal.hpp"
+#include "serve_policy.hpp"
+
+namespace {
+
+uint64_t now_ns()
+{
+    return uint64_t(std::chrono::duration_cast<std::chrono::nanoseconds>(
+                        std::chrono::steady_clock::now().time_since_epoch())
+                        .count());
+}
+
+constexpr int kServerThreads = 256;
+constexpr int kServerVectors = 8;
+constexpr int kMaxWorkgroupsPerCu = 3;  // summed over streams
+
+struct RequestState {
+    lscan_request req;
+    lscan_result res;
+    uint64_t bytes = 0;
+};
+
+struct StreamSlot {
+    hipStream_t stream = nullptr;
+    hipEvent_t done = nullptr;
+    bool busy = false;      // a batch was formed for this slot
+    bool launched = false;  // ... and its launch and completion event are enqueued
+    lscan::serve::Batch batch;
+    std::thread completer;
+};
+
+uint64_t batch_key(const lscan_request& r)
+{
+    return uint64_t(uint32_t(r.dt)) | (uint64_t(uint32_t(r.op)) << 8) | (uint64_t(r.flags) << 16);
+}
+
+}  // namespace
+
+struct lscan_server {
+    lscan_server_config cfg;
+    std::mutex mu;
+    std::condition_variable cv;        // scheduler: new work or a free slot
+    std::condition_variable done_cv;   // waiters: a request finished
+    std::unique_ptr<lscan::serve::Policy> policy;
+    std::unordered_map<uint64_t, RequestState> reqs;
+    uint64_t next_ticket = 1;
+    std::vector<std::unique_ptr<StreamSlot>> slots;
+    std::thread scheduler;
+    bool stopping = false;
+    lscan_server_stats stats;
+    std::condition_variable slot_cv;   // completers: a batch was launched on their slot
+};
+
+namespace {
+
+void fail_batch_locked(lscan_server* s, const lscan::serve::Batch& b, lscan_status st, uint64_t t)
+{
+    for (uint64_t t_id : b.tickets) {
+        auto it = s->reqs.find(t_id);
+        if (it == s->reqs.end()) continue;
+        it->second.res.status = st;
+        it->second.res.t_done_ns = t;
+        s->stats.failed++;
+    }
+    s->policy->release(b.bytes);
+}
+
+void scheduler_loop(lscan_server* s)
+{
+    (void)hipSetDevice(s->cfg.device);
+    lscan_params prm;
+    prm.block_threads = kServerThreads;
+    prm.vectors_per_lane = kServerVectors;
+    prm.groups_per_cu = s->cfg.groups_per_cu;
+    prm.reserved = 0;
+    std::vector<lscan_array> table;
+    std::unique_lock<std::mutex> lock(s->mu);
+    while (true) {
+        StreamSlot* free_slot = nullptr;
+        for (auto& sl : s->slots)
+            if (!sl->busy) {
+                free_slot = sl.get();
+                break;
+            }
+        if (free_slot && s->policy->pending() > 0) {
+            lscan::serve::Batch b = s->policy->next_batch();
+            if (!b.tickets.empty()) {
+                const uint64_t t = now_ns();
+                table.clear();
+                const lscan_request& head = s->reqs[b.tickets.front()].req;
+                const lscan_dtype dt = head.dt;
+                const lscan_op op = head.op;
+                const uint32_t flags = head.flags;
+                for (uint64_t id : b.tickets) {
+                    RequestState& rs = s->reqs[id];
+                    rs.res.t_admit_ns = t;
+                    rs.res.batch_id = s->stats.batches;
+                    rs.res.batch_size = int32_t(b.tickets.size());
+                    table.push_back(lscan_array{rs.req.x, rs.req.y, rs.req.n});
+                }
+                free_slot->busy = true;
+                free_slot->batch = b;
+                s->stats.batches++;
+                lock.unlock();
+                lscan_status st = lscan_batched_with_params(table.data(), int64_t(table.size()), dt, op, flags,
+                                                            &prm, free_slot->stream);
+                if (st == LSCAN_OK && hipEventRecord(free_slot->done, free_slot->stream) != hipSuccess)
+                    st = LSCAN_ERR_DEVICE;
+                const uint64_t t_launch = now_ns();
+                lock.lock();
+                for (uint64_t id : b.tickets) s->reqs[id].res.t_launch_ns = t_launch;
+                if (st != LSCAN_OK) {
+                    fail_batch_locked(s, b, st, t_launch);
+                    free_slot->busy = false;
+                    free_slot->batch = lscan::serve::Batch();
+                    s->done_cv.notify_all();
+                } else {
+                    free_slot->launched = true;
+                    s->slot_cv.notify_all();
+                }
+                continue;
+            }
+        }
+        if (s->stopping && s->policy->pending() == 0) break;
+        s->cv.wait(lock);
+    }
+}
+
+void completer_loop(lscan_server* s, StreamSlot* sl)
+{
+    (void)hipSetDevice(s->cfg.device);
+    std::unique_lock<std::mutex> lock(s->mu);
+    while (true) {
+        while (!sl->launched && !s->stopping) s->slot_cv.wait(lock);
+        if (!sl->launched) {
+            // stopping: leave once nothing more can be launched on this slot
+            if (!sl->busy && s->policy->pending() == 0) break;
+            s->slot_cv.wait(lock);
+            continue;
+        }
+        hipEvent_t ev = sl->done;
+        hipStream_t stream = sl->stream;
+        lock.unlock();
+        hipError_t e = hipEventSynchronize(ev);
+        lscan_status st = (e == hipSuccess) ? lscan_check(stream) : LSCAN_ERR_DEVICE;
+        const uint64_t t = now_ns();
+        lock.lock();
+        for (uint64_t id : sl->batch.tickets) {
+            auto it = s->reqs.find(id);
+            if (it == s->reqs.end()) continue;
+            it->second.res.status = st;
+            it->second.res.t_done_ns = t;
+            if (st == LSCAN_OK)
+                s->stats.completed++;
+            else
+                s->stats.failed++;
+        }
+        s->policy->release(sl->batch.bytes);
+        sl->batch = lscan::serve::Batch();
+        sl->launched = false;
+        sl->busy = false;
+        s->done_cv.notify_all();
+        s->cv.notify_all();
+    }
+}
+
+// One eager launch of every (dtype, operator, flags) on every server stream:
+// runs the co-residency test and sizes the workspaces before requests
+// arrive.
+lscan_status warm_up(lscan_server* s)
+{
+    lscan_params prm;
+    prm.block_threads = kServerThreads;
+    prm.vectors_per_lane = kServerVectors;
+    prm.groups_per_cu = s->cfg.groups_per_cu;
+    prm.reserved = 0;
+    void* buf = nullptr;
+    const size_t n = 4096;
+    if (hipMalloc(&buf, n * 16) != hipSuccess) return LSCAN_ERR_NO_MEMORY;
+    (void)hipMemset(buf, 0, n * 16);
+    lscan_status st = LSCAN_OK;
+    for (auto& sl : s->slots) {
+        for (int dt = LSCAN_I32; dt <= LSCAN_BF16 && st == LSCAN_OK; ++dt)
+            for (int op = LSCAN_ADD; op <= LSCAN_MIN && st == LSCAN_OK; ++op)
+                for (uint32_t comp = 0; comp <= 1 && st == LSCAN_OK; ++comp) {
+                    if (comp && !(op == LSCAN_ADD && (dt == LSCAN_F32 || dt == LSCAN_BF16))) continue;
+                    char* base = static_cast<char*>(buf);
+                    lscan_array a{base, base + n * 8, int64_t(n)};
+                    st = lscan_batched_with_params(&a, 1, lscan_dtype(dt), lscan_op(op),
+                                                   comp ? LSCAN_F_COMPENSATED : 0u, &prm, sl->stream);
+                }
+        if (st == LSCAN_OK) st = lscan_check(sl->stream);
+    }
+    (void)hipDeviceSynchronize();
+    (void)hipFree(buf);
+    return st;
+}
+
+}  // namespace
+
+extern "C" {
+
+lscan_status lscan_server_default_config(lscan_server_config* cfg)
+{
+    if (!cfg) return LSCAN_ERR_INVALID_ARG;
+    std::memset(cfg, 0, sizeof(*cfg));
+    cfg->device = 0;
+    cfg->num_streams = 2;
+    cfg->groups_per_cu = 1;
+    cfg->hbm_budget_bytes = uint64_t(32) << 30;
+    cfg->max_queue = 1 << 16;
+    cfg->max_batch = 4096;
+    return LSCAN_OK;
+}
+
+lscan_status lscan_server_create(const lscan_server_config* cfg, lscan_server** out)
+{
+    if (!cfg || !out) return LSCAN_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (cfg->num_streams < 1 || cfg->groups_per_cu < 1 ||
+        cfg->num_streams * cfg->groups_per_cu > kMaxWorkgroupsPerCu || cfg->hbm_budget_bytes == 0 ||
+        cfg->max_queue < 1 || cfg->max_batch < 1)
+        return LSCAN_ERR_INVALID_ARG;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || cfg->device < 0 || cfg->device >= count)
+        return LSCAN_ERR_INVALID_ARG;
+    if (hipSetDevice(cfg->device) != hipSuccess) return LSCAN_ERR_DEVICE;
+    lscan_server* s = new (std::nothrow) lscan_server();
+    if (!s) return LSCAN_ERR_NO_MEMORY;
+    s->cfg = *cfg;
+    std::memset(&s->stats, 0, sizeof(s->stats));
+    s->policy.reset(new lscan::serve::Policy(cfg->hbm_budget_bytes, size_t(cfg->max_queue), size_t(cfg->max_batch)));
+    for (int i = 0; i < cfg->num_streams; ++i) {
+        std::unique_ptr<StreamSlot> sl(new StreamSlot());
+        if (hipStreamCreateWithFlags(&sl->stream, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&sl->done, hipEventDisableTiming) != hipSuccess) {
+            for (auto& o : s->slots) {
+                (void)hipEventDestroy(o->done);
+                (void)hipStreamDestroy(o->stream);
+            }
+            delete s;
+            return LSCAN_ERR_DEVICE;
+        }
+        s->slots.push_back(std::move(sl));
+    }
+    lscan_status st = warm_up(s);
+    if (st != LSCAN_OK) {
+        for (auto& o : s->slots) {
+            (void)hipEventDestroy(o->done);
+            (void)hipStreamDestroy(o->stream);
+        }
+        delete s;
+        return st;
+    }
+    s->scheduler = std::thread(scheduler_loop, s);
+    for (auto& sl : s->slots) sl->completer = std::thread(completer_loop, s, sl.get());
+    *out = s;
+    return LSCAN_OK;
+}
+
+lscan_status lscan_submit(lscan_server* s, const lscan_request* r, uint64_t* ticket)
+{
+    if (!s || !r || !ticket) return LSCAN_ERR_INVALID_ARG;
+    lscan_status st = lscan::validate_request(r->x, r->y, r->n, r->dt, r->op, r->flags);
+    if (st != LSCAN_OK) return st;
+    const uint64_t t = now_ns();
+    std::lock_guard<std::mutex> lock(s->mu);
+    if (s->stopping) return LSCAN_ERR_INVALID_ARG;
+    RequestState rs;
+    rs.req = *r;
+    std::memset(&rs.res, 0, sizeof(rs.res));
+    rs.res.status = LSCAN_PENDING;
+    rs.res.t_submit_ns = t;
+    rs.bytes = lscan::request_bytes(r->n, r->dt);
+    const uint64_t id = s->next_ticket;
+    if (r->n == 0) {  // nothing to scan: done at once
+        rs.res.status = LSCAN_OK;
+        rs.res.t_admit_ns = rs.res.t_launch_ns = rs.res.t_done_ns = t;
+        s->reqs.emplace(id, rs);
+        s->next_ticket++;
+        s->stats.submitted++;
+        s->stats.completed++;
+        *ticket = id;
+        return LSCAN_OK;
+    }
+    const lscan::serve::Admit a = s->policy->submit(lscan::serve::PendingRequest{id, batch_key(*r), rs.bytes, t});
+    if (a == lscan::serve::Admit::kTooLarge) return LSCAN_ERR_NO_MEMORY;
+    if (a == lscan::serve::Admit::kQueueFull) return LSCAN_ERR_AGAIN;
+    s->reqs.emplace(id, rs);
+    s->next_ticket++;
+    s->stats.submitted++;
+    *ticket = id;
+    s->cv.notify_all();
+    return LSCAN_OK;
+}
+
+lscan_status lscan_poll(lscan_server* s, uint64_t ticket, lscan_result* out)
+{
+    if (!s || !out) return LSCAN_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lock(s->mu);
+    auto it = s->reqs.find(ticket);
+    if (it == s->reqs.end()) return LSCAN_ERR_NOT_FOUND;
+    *out = it->second.res;
+    if (out->status == LSCAN_PENDING) return LSCAN_PENDING;
+    const lscan_status st = out->status;
+    s->reqs.erase(it);
+    return st;
+}
+
+lscan_status lscan_wait(lscan_server* s, uint64_t ticket, lscan_result* out)
+{
+    if (!s || !out) return LSCAN_ERR_INVALID_ARG;
+    std::unique_lock<std::mutex> lock(s->mu);
+    while (true) {
+        auto it = s->reqs.find(ticket);
+        if (it == s->reqs.end()) return LSCAN_ERR_NOT_FOUND;
+        if (it->second.res.status != LSCAN_PENDING) {
+            *out = it->second.res;
+            const lscan_status st = out->status;
+            s->reqs.erase(it);
+            return st;
+        }
+        s->done_cv.wait(lock);
+    }
+}
+
+lscan_status lscan_server_get_stats(lscan_server* s, lscan_server_stats* out)
+{
+    if (!s || !out) return LSCAN_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lock(s->mu);
+    *out = s->stats;
+    out->pending = int64_t(s->policy->pending());
+    out->bytes_in_flight = s->policy->in_flight_bytes();
+    out->peak_bytes_in_flight = s->policy->peak_bytes();
+    return LSCAN_OK;
+}
+
+lscan_status lscan_server_destroy(lscan_server* s)
+{
+    if (!s) return LSCAN_ERR_INVALID_ARG;
+    {
+        std::lock_guard<std::mutex> lock(s->mu);
+        s->stopping = true;
+        s->cv.notify_all();
+        s->slot_cv.notify_all();
+    }
+    if (s->scheduler.joinable()) s->scheduler.join();
+    {
+        std::lock_guard<std::mutex> lock(s->mu);
+        s->slot_cv.notify_all();
+    }
+    for (auto& sl : s->slots)
+        if (sl->completer.joinable()) sl->completer.join();
+    for (auto& sl : s->slots) {
+        (void)hipStreamSynchronize(sl->stream);
+        (void)hipEventDestroy(sl->done);
+        (void)hipStreamDestroy(sl->stream);
+    }
+    delete s;
+    return LSCAN_OK;
+}
+
+}  // extern "C"

@@ -233,6 +233,114 @@ def bench_latency(binding, workloads, steps):
     return e
 
 
+def _serving_pools(workloads):
+    """Device-resident value pools (2^26 elements each) that request inputs
+    are sliced from; PCIe could not feed fresh inputs at the offered load."""
+    n = 1 << 26
+    return {
+        ("int32", "add"): to_device(workloads.uniform_int(n, -1000, 1000, workloads.seed_for(4, 1)), "int32"),
+        ("int32", "max"): to_device(workloads.full_range_int32(n, workloads.seed_for(4, 2)), "int32"),
+        ("int64", "add"): to_device(workloads.int64_half_open(n, -(2 ** 31), 2 ** 31, workloads.seed_for(4, 3)),
+                                    "int64"),
+        ("float32", "add"): to_device(workloads.signed_lognormal_f32(n, workloads.seed_for(4, 4)), "float32"),
+    }
+
+
+def _pool_slice(pools, req, rng):
+    key = (req["dtype"], "max" if (req["dtype"] == "int32" and req["op"] == "max") else "add")
+    pool = pools[key]
+    n = req["n"]
+    off = int(rng.integers(0, pool.shape[0] - n + 1)) & ~3  # 16-byte aligned slices
+    return pool[off:off + n]
+
+
+def bench_serving(binding, workloads, seconds: float, rate: float):
+    """Poisson trace through the request server, and the same trace as
+    serial plain launches (one launch + synchronize per request, FIFO)."""
+    import numpy as np
+    import torch
+
+    trace = workloads.request_trace(rate, seconds, workloads.seed_for(4))
+    pools = _serving_pools(workloads)
+    torch.cuda.synchronize()
+    size_of = {"int32": 4, "int64": 8, "float32": 4}
+    total_bytes = sum(2 * size_of[r["dtype"]] * r["n"] for r in trace)
+    rng = np.random.default_rng(workloads.seed_for(4, 9))
+    xs = [_pool_slice(pools, r, rng) for r in trace]
+    out = {"requests": len(trace), "seconds": seconds, "rate_hz": rate, "bytes": total_bytes}
+
+    def summarize(lat_ns, t_first, t_last):
+        lat = np.array(lat_ns, dtype=np.float64) / 1e3
+        span = (t_last - t_first) / 1e9
+        return {"p50_us": round(float(np.percentile(lat, 50)), 1), "p99_us": round(float(np.percentile(lat, 99)), 1),
+                "mean_us": round(float(lat.mean()), 1), "gbs": round(total_bytes / span / 1e9, 1),
+                "makespan_s": round(span, 3)}
+
+    # --- served
+    srv = binding.Server(num_streams=2, hbm_budget_bytes=32 << 30)
+    t0 = time.monotonic_ns() + 20_000_000
+    arrivals = [t0 + int(r["t"] * 1e9) for r in trace]
+    live = {}
+    lat, t_done_last = [], t0
+    checks = []
+    k = 0
+    ops = {"add": binding.ADD, "max": binding.MAX}
+    while k < len(trace) or live:
+        now = time.monotonic_ns()
+        while k < len(trace) and arrivals[k] <= now:
+            r, x = trace[k], xs[k]
+            y = torch.empty(r["n"], dtype=x.dtype, device="cuda")
+            tk = srv.submit_raw(x.data_ptr(), y.data_ptr(), r["n"], binding.dtype_code(x), ops[r["op"]])
+            if tk < 0:
+                raise RuntimeError(f"submit refused: {tk}")
+            live[tk] = (k, y)
+            k += 1
+        for tk in list(live):
+            st, res = srv.poll(tk)
+            if st == binding.PENDING:
+                continue
+            if st != binding.OK:
+                raise RuntimeError(f"request failed: {st}")
+            idx, y = live.pop(tk)
+            lat.append(res.t_done_ns - arrivals[idx])
+            t_done_last = max(t_done_last, res.t_done_ns)
+            if idx % 997 == 0:
+                checks.append((idx, y))
+    stats = srv.stats()
+    srv.close()
+    served = summarize(lat, arrivals[0], t_done_last)
+    served.update({"batches": int(stats.batches), "peak_bytes_in_flight": int(stats.peak_bytes_in_flight)})
+    same = True
+    for idx, y in checks:
+        alone = binding.inclusive(xs[idx], trace[idx]["op"])
+        if trace[idx]["dtype"] == "float32" and trace[idx]["op"] == "add":
+            same &= bool(torch.allclose(y, alone, rtol=1e-4, atol=1e-2))
+        else:
+            same &= bool(torch.equal(y, alone))
+    served["spot_checks_equal_alone"] = same
+    served["spot_checks"] = len(checks)
+    out["served"] = served
+
+    # --- serial plain launches on the same trace
+    torch.cuda.synchronize()
+    t0 = time.monotonic_ns() + 20_000_000
+    arrivals = [t0 + int(r["t"] * 1e9) for r in trace]
+    lat = []
+    for k, (r, x) in enumerate(zip(trace, xs)):
+        while time.monotonic_ns() < arrivals[k]:
+            pass
+        y = torch.empty(r["n"], dtype=x.dtype, device="cuda")
+        binding.inclusive(x, r["op"], out=y)
+        torch.cuda.synchronize()
+        lat.append(time.monotonic_ns() - arrivals[k])
+    out["serial_plain"] = summarize(lat, arrivals[0], time.monotonic_ns())
+    out["p99_speedup_vs_serial"] = round(out["serial_plain"]["p99_us"] / out["served"]["p99_us"], 2)
+    out["p50_speedup_vs_serial"] = round(out["serial_plain"]["p50_us"] / out["served"]["p50_us"], 2)
+    del pools, xs
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(x_host, budget_s: float):
     """The sequential oracle (one core) on the same array, repeated for about
     budget_s seconds; median rate."""
@@ -260,9 +368,15 @@ def main(argv=None) -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--only", default="", help="'1a' runs only the headline scan and a same-size copy")
+    ap.add_argument("--only", default="", help="'1a': only the headline scan and a same-size copy; 'serve': only the serving trace")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--serve-seconds", type=float, default=5.0,
+                    help="length of the Poisson request trace (the full trace is 60 s)")
+    ap.add_argument("--serve-rate", type=float, default=2000.0)
+    ap.add_argument("--serve-heavy-rate", type=float, default=20000.0,
+                    help="a second, heavier trace where requests queue and batching pays")
+    ap.add_argument("--serve-heavy-seconds", type=float, default=1.0)
     args = ap.parse_args(argv)
 
     if args.gpus != 1:
@@ -284,6 +398,12 @@ def main(argv=None) -> int:
     torch.cuda.init()
     dev = torch.cuda.get_device_properties(0)
     log(f"device {dev.name}, {dev.multi_processor_count} CUs")
+
+    if args.only == "serve":
+        sv = bench_serving(binding, workloads, args.serve_seconds, args.serve_rate)
+        hv = bench_serving(binding, workloads, args.serve_heavy_seconds, args.serve_heavy_rate)
+        print(json.dumps({"serving": sv, "serving_heavy": hv}), flush=True)
+        return 0
 
     n = 1 << 28
     x = workloads.uniform_int(n, -1024, 1024, workloads.seed_for(1))
@@ -317,6 +437,19 @@ def main(argv=None) -> int:
         del xb
         log("segmented: 4096 arrays")
         configs.update(bench_segmented(binding, workloads, args.steps, args.warmup))
+        if args.serve_seconds > 0:
+            log(f"serving: Poisson {args.serve_rate:.0f} req/s for {args.serve_seconds:.0f} s")
+            configs["serving"] = bench_serving(binding, workloads, args.serve_seconds, args.serve_rate)
+            sv = configs["serving"]
+            log(f"  served p50/p99 {sv['served']['p50_us']}/{sv['served']['p99_us']} us, serial "
+                f"{sv['serial_plain']['p50_us']}/{sv['serial_plain']['p99_us']} us")
+            if args.serve_heavy_seconds > 0:
+                log(f"serving: Poisson {args.serve_heavy_rate:.0f} req/s for {args.serve_heavy_seconds:.0f} s")
+                configs["serving_heavy"] = bench_serving(binding, workloads, args.serve_heavy_seconds,
+                                                         args.serve_heavy_rate)
+                hv = configs["serving_heavy"]
+                log(f"  served p50/p99 {hv['served']['p50_us']}/{hv['served']['p99_us']} us, serial "
+                    f"{hv['serial_plain']['p50_us']}/{hv['serial_plain']['p99_us']} us")
         log("latency: int32 add N=2^20")
         configs["int32_add_2p20_latency"] = bench_latency(binding, workloads, args.steps)
         try:

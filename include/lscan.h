@@ -247,9 +247,15 @@ lscan_status lscan_graph_destroy(lscan_graph *g);
  *   overtakes it).
  *   Ownership: x and y are device pointers owned by the caller and must stay
  *   valid until lscan_poll / lscan_wait returns a final status.
- *   Co-residency: every batch launches groups_per_cu workgroups per CU and
- *   num_streams * groups_per_cu <= 3 is enforced, so the persistent grids of
- *   all streams fit on the device together.
+ *   Co-residency: the batches of stream i launch g_i workgroups per CU and
+ *   the g_i sum to at most 3, so the persistent grids of all streams fit on
+ *   the device together; groups_per_cu > 0 gives every stream that many
+ *   (num_streams * groups_per_cu <= 3), groups_per_cu == 0 splits 3 among
+ *   the streams, larger shares first (2 + 1 for two streams).  A batch goes
+ *   to the free stream with the largest share.
+ *   Scheduling happens in the thread that makes it possible -- lscan_submit
+ *   or the completion of a batch -- so an arrival that finds a free stream
+ *   is launched before lscan_submit returns.
  * lscan_poll returns LSCAN_PENDING (result partly filled) or the final
  * status, and forgets a ticket once it has reported its final status;
  * lscan_wait blocks until then.  lscan_server_destroy finishes every
@@ -257,11 +263,11 @@ lscan_status lscan_graph_destroy(lscan_graph *g);
  */
 typedef struct {
     int32_t device;
-    int32_t num_streams;       /* concurrent batches (default 2) */
+    int32_t num_streams;       /* concurrent batches, 1..3 (default 2) */
     uint64_t hbm_budget_bytes; /* bytes of requests in flight (default 32 GiB) */
     int32_t max_queue;         /* pending requests (default 65536) */
     int32_t max_batch;         /* arrays per launch (default 4096) */
-    int32_t groups_per_cu;     /* workgroups per CU per batch (default 1) */
+    int32_t groups_per_cu;     /* per stream; 0 = split 3 (default 0) */
     int32_t reserved;
 } lscan_server_config;
 

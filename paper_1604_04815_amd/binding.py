@@ -397,7 +397,7 @@ class Server:
     """Request server (lscan_server_*): submit device arrays, poll tickets."""
 
     def __init__(self, device=0, num_streams=2, hbm_budget_bytes=32 << 30, max_queue=1 << 16, max_batch=4096,
-                 groups_per_cu=1):
+                 groups_per_cu=0):
         lib = load()
         cfg = ServerConfig()
         _check(lib.lscan_server_default_config(ctypes.byref(cfg)), "lscan_server_default_config")

@@ -39,6 +39,7 @@ struct ScanArgs {
     int32_t vec_ok;           // 1: x and y allow full-width vector access
     int32_t residency_check;  // 1: only test that all workgroups are resident at once, then exit
     int32_t pad_;
+    uint32_t* status_host;    // optional host-visible word that also receives the timeout flag
 };
 
 using LaunchFn = hipError_t (*)(const ScanArgs&, int grid, hipStream_t);

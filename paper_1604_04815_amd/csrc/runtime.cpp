@@ -200,6 +200,7 @@ struct Request {
     bool exclusive = false;
     const lscan_params* p = nullptr;
     bool empty = false;                  // nothing to do
+    uint32_t* status_host = nullptr;     // optional host-visible timeout word
 };
 
 lscan_status make_request(int mode, const void* x, void* y, int64_t n, const int64_t* offsets, int64_t num_segments,
@@ -522,6 +523,7 @@ lscan_status plan_locked(const Request& r, int dev, Workspace* ws_fixed, hipStre
     a.spin_limit = info->spin_limit;
     a.exclusive = r.exclusive ? 1 : 0;
     a.residency_check = 0;
+    a.status_host = r.status_host;
 
     plan->k = &k;
     plan->grid = int(B);
@@ -576,6 +578,27 @@ lscan_status validate_request(const void* x, const void* y, int64_t n, int dt, i
 }
 
 uint64_t request_bytes(int64_t n, int dt) { return uint64_t(n) * uint64_t(in_bytes_of(dt) + out_bytes_of(dt)); }
+
+int batched_kernel_vgprs(int dt, int op, uint32_t flags, int threads, int vectors)
+{
+    const int oc = opcode_of(dt, op, flags & LSCAN_F_COMPENSATED);
+    const int sh = shape_index(threads, vectors);
+    if (oc < 0 || sh < 0) return -1;
+    hipFuncAttributes attr;
+    if (hipFuncGetAttributes(&attr, table()[kModeBatched][oc][sh].func) != hipSuccess) return -1;
+    return attr.numRegs;
+}
+
+lscan_status launch_batched(const lscan_array* arrays, int64_t count, lscan_dtype dt, lscan_op op, uint32_t flags,
+                            const lscan_params* p, void* stream, uint32_t* status_host)
+{
+    Request r;
+    lscan_status st = make_request(kModeBatched, nullptr, nullptr, 0, nullptr, 0, arrays, count, dt, op, flags,
+                                   (flags & LSCAN_F_EXCLUSIVE) != 0, p, &r);
+    if (st != LSCAN_OK) return st;
+    r.status_host = status_host;
+    return run(r, stream);
+}
 
 }  // namespace lscan
 

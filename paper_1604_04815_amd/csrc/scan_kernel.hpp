@@ -395,7 +395,11 @@ __global__ void __launch_bounds__(T) scan_kernel(ScanArgs a)
             if (lane == 0) {
                 s_block_prefix[parity] = prefix;
                 s_abort[parity] = abort ? 1 : 0;
-                if (abort) __hip_atomic_store(a.ctrl + 2, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (abort) {
+                    __hip_atomic_store(a.ctrl + 2, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    if (a.status_host)
+                        __hip_atomic_store(a.status_host, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                }
             }
         }
         __syncthreads();

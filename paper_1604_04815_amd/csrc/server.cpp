@@ -3,14 +3,18 @@
 // pending requests into one persistent launch per (dtype, operator, flags),
 // and several streams so that batches overlap on the device.
 //
-// Co-residency: every batch launches with `groups_per_cu` workgroups per CU
-// of the 256-thread x 8-vector batched kernels (one wave per SIMD per
-// workgroup), and num_streams * groups_per_cu <= 3, so at most three of
-// those waves share a SIMD.  Each of those kernels allocates at most 144
-// VGPRs per wave on gfx950 (the compensated ones; the others 96-104), and
-// 3 * 144 <= 512, so the grids of all streams always fit together.
+// Co-residency: batches launch 256-thread workgroups (one wave per SIMD per
+// workgroup) of the batched kernels, 16 vectors per lane (8 for the
+// compensated pair, whose state is twice as wide), and the workgroups per CU
+// of all streams sum to at most 3, so at most three of those waves share a
+// SIMD.  At creation the server reads every such kernel's VGPR count from
+// the code object and refuses to start unless three waves of the largest
+// fit in one SIMD's 512 registers (on gfx950 they need at most 160 each),
+// so the grids of all streams are always resident together.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
@@ -35,8 +39,11 @@ uint64_t now_ns()
 }
 
 constexpr int kServerThreads = 256;
-constexpr int kServerVectors = 8;
 constexpr int kMaxWorkgroupsPerCu = 3;  // summed over streams
+constexpr int kSimdVgprs = 512;
+constexpr int kVgprGranule = 8;
+
+int server_vectors(uint32_t flags) { return (flags & LSCAN_F_COMPENSATED) ? 8 : 16; }
 
 struct RequestState {
     lscan_request req;
@@ -47,6 +54,9 @@ struct RequestState {
 struct StreamSlot {
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
+    int groups = 1;                  // workgroups per CU of this stream's launches
+    uint32_t* status = nullptr;      // host word the kernel raises on a timeout
+    uint32_t* status_dev = nullptr;  // its device-visible address
     bool busy = false;      // a batch was formed for this slot
     bool launched = false;  // ... and its launch and completion event are enqueued
     lscan::serve::Batch batch;
@@ -63,16 +73,14 @@ uint64_t batch_key(const lscan_request& r)
 struct lscan_server {
     lscan_server_config cfg;
     std::mutex mu;
-    std::condition_variable cv;        // scheduler: new work or a free slot
     std::condition_variable done_cv;   // waiters: a request finished
+    std::condition_variable slot_cv;   // completers: a batch was launched on their slot
     std::unique_ptr<lscan::serve::Policy> policy;
     std::unordered_map<uint64_t, RequestState> reqs;
     uint64_t next_ticket = 1;
     std::vector<std::unique_ptr<StreamSlot>> slots;
-    std::thread scheduler;
     bool stopping = false;
     lscan_server_stats stats;
-    std::condition_variable slot_cv;   // completers: a batch was launched on their slot
 };
 
 namespace {
@@ -89,64 +97,58 @@ void fail_batch_locked(lscan_server* s, const lscan::serve::Batch& b, lscan_stat
     s->policy->release(b.bytes);
 }
 
-void scheduler_loop(lscan_server* s)
+// Launch batches while a stream slot is free and the policy has work.  Runs
+// in whichever thread made progress possible (a submit or a completion), so
+// no thread hand-off sits between an arrival and its launch.  Called with
+// the lock held; drops it around each launch.
+void schedule_locked(lscan_server* s, std::unique_lock<std::mutex>& lock)
 {
-    (void)hipSetDevice(s->cfg.device);
-    lscan_params prm;
-    prm.block_threads = kServerThreads;
-    prm.vectors_per_lane = kServerVectors;
-    prm.groups_per_cu = s->cfg.groups_per_cu;
-    prm.reserved = 0;
     std::vector<lscan_array> table;
-    std::unique_lock<std::mutex> lock(s->mu);
-    while (true) {
-        StreamSlot* free_slot = nullptr;
+    while (s->policy->pending() > 0) {
+        StreamSlot* slot = nullptr;  // the free slot with the largest grid
         for (auto& sl : s->slots)
-            if (!sl->busy) {
-                free_slot = sl.get();
-                break;
-            }
-        if (free_slot && s->policy->pending() > 0) {
-            lscan::serve::Batch b = s->policy->next_batch();
-            if (!b.tickets.empty()) {
-                const uint64_t t = now_ns();
-                table.clear();
-                const lscan_request& head = s->reqs[b.tickets.front()].req;
-                const lscan_dtype dt = head.dt;
-                const lscan_op op = head.op;
-                const uint32_t flags = head.flags;
-                for (uint64_t id : b.tickets) {
-                    RequestState& rs = s->reqs[id];
-                    rs.res.t_admit_ns = t;
-                    rs.res.batch_id = s->stats.batches;
-                    rs.res.batch_size = int32_t(b.tickets.size());
-                    table.push_back(lscan_array{rs.req.x, rs.req.y, rs.req.n});
-                }
-                free_slot->busy = true;
-                free_slot->batch = b;
-                s->stats.batches++;
-                lock.unlock();
-                lscan_status st = lscan_batched_with_params(table.data(), int64_t(table.size()), dt, op, flags,
-                                                            &prm, free_slot->stream);
-                if (st == LSCAN_OK && hipEventRecord(free_slot->done, free_slot->stream) != hipSuccess)
-                    st = LSCAN_ERR_DEVICE;
-                const uint64_t t_launch = now_ns();
-                lock.lock();
-                for (uint64_t id : b.tickets) s->reqs[id].res.t_launch_ns = t_launch;
-                if (st != LSCAN_OK) {
-                    fail_batch_locked(s, b, st, t_launch);
-                    free_slot->busy = false;
-                    free_slot->batch = lscan::serve::Batch();
-                    s->done_cv.notify_all();
-                } else {
-                    free_slot->launched = true;
-                    s->slot_cv.notify_all();
-                }
-                continue;
-            }
+            if (!sl->busy && (!slot || sl->groups > slot->groups)) slot = sl.get();
+        if (!slot) return;
+        lscan::serve::Batch b = s->policy->next_batch();
+        if (b.tickets.empty()) return;
+        const uint64_t t = now_ns();
+        table.clear();
+        const lscan_request& head = s->reqs[b.tickets.front()].req;
+        const lscan_dtype dt = head.dt;
+        const lscan_op op = head.op;
+        const uint32_t flags = head.flags;
+        for (uint64_t id : b.tickets) {
+            RequestState& rs = s->reqs[id];
+            rs.res.t_admit_ns = t;
+            rs.res.batch_id = s->stats.batches;
+            rs.res.batch_size = int32_t(b.tickets.size());
+            table.push_back(lscan_array{rs.req.x, rs.req.y, rs.req.n});
         }
-        if (s->stopping && s->policy->pending() == 0) break;
-        s->cv.wait(lock);
+        slot->busy = true;
+        slot->batch = b;
+        *slot->status = 0;  // the slot's previous batch has completed
+        s->stats.batches++;
+        lscan_params prm;
+        prm.block_threads = kServerThreads;
+        prm.vectors_per_lane = server_vectors(flags);
+        prm.groups_per_cu = slot->groups;
+        prm.reserved = 0;
+        lock.unlock();
+        lscan_status st = lscan::launch_batched(table.data(), int64_t(table.size()), dt, op, flags, &prm,
+                                                slot->stream, slot->status_dev);
+        if (st == LSCAN_OK && hipEventRecord(slot->done, slot->stream) != hipSuccess) st = LSCAN_ERR_DEVICE;
+        const uint64_t t_launch = now_ns();
+        lock.lock();
+        for (uint64_t id : b.tickets) s->reqs[id].res.t_launch_ns = t_launch;
+        if (st != LSCAN_OK) {
+            fail_batch_locked(s, b, st, t_launch);
+            slot->busy = false;
+            slot->batch = lscan::serve::Batch();
+            s->done_cv.notify_all();
+        } else {
+            slot->launched = true;
+            s->slot_cv.notify_all();
+        }
     }
 }
 
@@ -155,18 +157,13 @@ void completer_loop(lscan_server* s, StreamSlot* sl)
     (void)hipSetDevice(s->cfg.device);
     std::unique_lock<std::mutex> lock(s->mu);
     while (true) {
-        while (!sl->launched && !s->stopping) s->slot_cv.wait(lock);
-        if (!sl->launched) {
-            // stopping: leave once nothing more can be launched on this slot
-            if (!sl->busy && s->policy->pending() == 0) break;
-            s->slot_cv.wait(lock);
-            continue;
-        }
+        while (!sl->launched && !(s->stopping && !sl->busy)) s->slot_cv.wait(lock);
+        if (!sl->launched) break;  // stopping and idle
         hipEvent_t ev = sl->done;
-        hipStream_t stream = sl->stream;
         lock.unlock();
-        hipError_t e = hipEventSynchronize(ev);
-        lscan_status st = (e == hipSuccess) ? lscan_check(stream) : LSCAN_ERR_DEVICE;
+        const hipError_t e = hipEventSynchronize(ev);
+        const uint32_t timed_out = __atomic_load_n(sl->status, __ATOMIC_ACQUIRE);
+        const lscan_status st = (e != hipSuccess) ? LSCAN_ERR_DEVICE : (timed_out ? LSCAN_ERR_TIMEOUT : LSCAN_OK);
         const uint64_t t = now_ns();
         lock.lock();
         for (uint64_t id : sl->batch.tickets) {
@@ -184,7 +181,7 @@ void completer_loop(lscan_server* s, StreamSlot* sl)
         sl->launched = false;
         sl->busy = false;
         s->done_cv.notify_all();
-        s->cv.notify_all();
+        schedule_locked(s, lock);  // the freed slot and bytes may admit waiting requests
     }
 }
 
@@ -193,21 +190,21 @@ void completer_loop(lscan_server* s, StreamSlot* sl)
 // arrive.
 lscan_status warm_up(lscan_server* s)
 {
-    lscan_params prm;
-    prm.block_threads = kServerThreads;
-    prm.vectors_per_lane = kServerVectors;
-    prm.groups_per_cu = s->cfg.groups_per_cu;
-    prm.reserved = 0;
     void* buf = nullptr;
     const size_t n = 4096;
     if (hipMalloc(&buf, n * 16) != hipSuccess) return LSCAN_ERR_NO_MEMORY;
     (void)hipMemset(buf, 0, n * 16);
     lscan_status st = LSCAN_OK;
     for (auto& sl : s->slots) {
+        lscan_params prm;
+        prm.block_threads = kServerThreads;
+        prm.groups_per_cu = sl->groups;
+        prm.reserved = 0;
         for (int dt = LSCAN_I32; dt <= LSCAN_BF16 && st == LSCAN_OK; ++dt)
             for (int op = LSCAN_ADD; op <= LSCAN_MIN && st == LSCAN_OK; ++op)
                 for (uint32_t comp = 0; comp <= 1 && st == LSCAN_OK; ++comp) {
                     if (comp && !(op == LSCAN_ADD && (dt == LSCAN_F32 || dt == LSCAN_BF16))) continue;
+                    prm.vectors_per_lane = server_vectors(comp ? LSCAN_F_COMPENSATED : 0u);
                     char* base = static_cast<char*>(buf);
                     lscan_array a{base, base + n * 8, int64_t(n)};
                     st = lscan_batched_with_params(&a, 1, lscan_dtype(dt), lscan_op(op),
@@ -220,6 +217,17 @@ lscan_status warm_up(lscan_server* s)
     return st;
 }
 
+void destroy_slots(lscan_server* s)
+{
+    for (auto& o : s->slots) {
+        if (o->stream) (void)hipStreamSynchronize(o->stream);
+        if (o->done) (void)hipEventDestroy(o->done);
+        if (o->stream) (void)hipStreamDestroy(o->stream);
+        if (o->status) (void)hipHostFree(o->status);
+    }
+    s->slots.clear();
+}
+
 }  // namespace
 
 extern "C" {
@@ -230,7 +238,7 @@ lscan_status lscan_server_default_config(lscan_server_config* cfg)
     std::memset(cfg, 0, sizeof(*cfg));
     cfg->device = 0;
     cfg->num_streams = 2;
-    cfg->groups_per_cu = 1;
+    cfg->groups_per_cu = 0;  // split the device: 2 + 1 workgroups per CU
     cfg->hbm_budget_bytes = uint64_t(32) << 30;
     cfg->max_queue = 1 << 16;
     cfg->max_batch = 4096;
@@ -241,7 +249,7 @@ lscan_status lscan_server_create(const lscan_server_config* cfg, lscan_server** 
 {
     if (!cfg || !out) return LSCAN_ERR_INVALID_ARG;
     *out = nullptr;
-    if (cfg->num_streams < 1 || cfg->groups_per_cu < 1 ||
+    if (cfg->num_streams < 1 || cfg->num_streams > kMaxWorkgroupsPerCu || cfg->groups_per_cu < 0 ||
         cfg->num_streams * cfg->groups_per_cu > kMaxWorkgroupsPerCu || cfg->hbm_budget_bytes == 0 ||
         cfg->max_queue < 1 || cfg->max_batch < 1)
         return LSCAN_ERR_INVALID_ARG;
@@ -256,27 +264,46 @@ lscan_status lscan_server_create(const lscan_server_config* cfg, lscan_server** 
     s->policy.reset(new lscan::serve::Policy(cfg->hbm_budget_bytes, size_t(cfg->max_queue), size_t(cfg->max_batch)));
     for (int i = 0; i < cfg->num_streams; ++i) {
         std::unique_ptr<StreamSlot> sl(new StreamSlot());
-        if (hipStreamCreateWithFlags(&sl->stream, hipStreamNonBlocking) != hipSuccess ||
-            hipEventCreateWithFlags(&sl->done, hipEventDisableTiming) != hipSuccess) {
-            for (auto& o : s->slots) {
-                (void)hipEventDestroy(o->done);
-                (void)hipStreamDestroy(o->stream);
-            }
+        // groups_per_cu == 0: share kMaxWorkgroupsPerCu among the streams,
+        // the larger shares first
+        sl->groups = cfg->groups_per_cu > 0
+                         ? cfg->groups_per_cu
+                         : kMaxWorkgroupsPerCu / cfg->num_streams + (i < kMaxWorkgroupsPerCu % cfg->num_streams);
+        bool ok = hipStreamCreateWithFlags(&sl->stream, hipStreamNonBlocking) == hipSuccess &&
+                  hipEventCreateWithFlags(&sl->done, hipEventDisableTiming) == hipSuccess &&
+                  hipHostMalloc(reinterpret_cast<void**>(&sl->status), sizeof(uint32_t),
+                                hipHostMallocMapped | hipHostMallocCoherent) == hipSuccess &&
+                  hipHostGetDevicePointer(reinterpret_cast<void**>(&sl->status_dev), sl->status, 0) == hipSuccess;
+        s->slots.push_back(std::move(sl));
+        if (!ok) {
+            destroy_slots(s);
             delete s;
             return LSCAN_ERR_DEVICE;
         }
-        s->slots.push_back(std::move(sl));
+        *s->slots.back()->status = 0;
+    }
+    // every kernel the server may run must fit three waves to a SIMD
+    int max_vgprs = 0;
+    for (int dt = LSCAN_I32; dt <= LSCAN_BF16; ++dt)
+        for (int op = LSCAN_ADD; op <= LSCAN_MIN; ++op)
+            for (uint32_t comp = 0; comp <= 1; ++comp) {
+                if (comp && !(op == LSCAN_ADD && (dt == LSCAN_F32 || dt == LSCAN_BF16))) continue;
+                const uint32_t f = comp ? LSCAN_F_COMPENSATED : 0u;
+                const int v = lscan::batched_kernel_vgprs(dt, op, f, kServerThreads, server_vectors(f));
+                max_vgprs = (v < 0) ? kSimdVgprs : std::max(max_vgprs, v);
+            }
+    const int alloc = (max_vgprs + kVgprGranule - 1) / kVgprGranule * kVgprGranule;
+    if (kMaxWorkgroupsPerCu * alloc > kSimdVgprs) {
+        destroy_slots(s);
+        delete s;
+        return LSCAN_ERR_UNSUPPORTED;
     }
     lscan_status st = warm_up(s);
     if (st != LSCAN_OK) {
-        for (auto& o : s->slots) {
-            (void)hipEventDestroy(o->done);
-            (void)hipStreamDestroy(o->stream);
-        }
+        destroy_slots(s);
         delete s;
         return st;
     }
-    s->scheduler = std::thread(scheduler_loop, s);
     for (auto& sl : s->slots) sl->completer = std::thread(completer_loop, s, sl.get());
     *out = s;
     return LSCAN_OK;
@@ -288,7 +315,7 @@ lscan_status lscan_submit(lscan_server* s, const lscan_request* r, uint64_t* tic
     lscan_status st = lscan::validate_request(r->x, r->y, r->n, r->dt, r->op, r->flags);
     if (st != LSCAN_OK) return st;
     const uint64_t t = now_ns();
-    std::lock_guard<std::mutex> lock(s->mu);
+    std::unique_lock<std::mutex> lock(s->mu);
     if (s->stopping) return LSCAN_ERR_INVALID_ARG;
     RequestState rs;
     rs.req = *r;
@@ -314,7 +341,7 @@ lscan_status lscan_submit(lscan_server* s, const lscan_request* r, uint64_t* tic
     s->next_ticket++;
     s->stats.submitted++;
     *ticket = id;
-    s->cv.notify_all();
+    schedule_locked(s, lock);
     return LSCAN_OK;
 }
 
@@ -363,23 +390,20 @@ lscan_status lscan_server_destroy(lscan_server* s)
 {
     if (!s) return LSCAN_ERR_INVALID_ARG;
     {
-        std::lock_guard<std::mutex> lock(s->mu);
-        s->stopping = true;
-        s->cv.notify_all();
-        s->slot_cv.notify_all();
-    }
-    if (s->scheduler.joinable()) s->scheduler.join();
-    {
-        std::lock_guard<std::mutex> lock(s->mu);
+        std::unique_lock<std::mutex> lock(s->mu);
+        s->stopping = true;  // refuse new submits; finish what was submitted
+        auto busy = [&] {
+            if (s->policy->pending() > 0) return true;
+            for (auto& sl : s->slots)
+                if (sl->busy) return true;
+            return false;
+        };
+        while (busy()) s->done_cv.wait(lock);
         s->slot_cv.notify_all();
     }
     for (auto& sl : s->slots)
         if (sl->completer.joinable()) sl->completer.join();
-    for (auto& sl : s->slots) {
-        (void)hipStreamSynchronize(sl->stream);
-        (void)hipEventDestroy(sl->done);
-        (void)hipStreamDestroy(sl->stream);
-    }
+    destroy_slots(s);
     delete s;
     return LSCAN_OK;
 }

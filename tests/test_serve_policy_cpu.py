@@ -29,10 +29,10 @@ def lib():
 def test_server_config_validation(lib):
     cfg = binding.ServerConfig()
     assert lib.lscan_server_default_config(ctypes.byref(cfg)) == binding.OK
-    assert cfg.num_streams == 2 and cfg.groups_per_cu == 1 and cfg.hbm_budget_bytes == 32 << 30
+    assert cfg.num_streams == 2 and cfg.groups_per_cu == 0 and cfg.hbm_budget_bytes == 32 << 30
     h = ctypes.c_void_p()
-    for field, value in (("num_streams", 0), ("groups_per_cu", 0), ("hbm_budget_bytes", 0), ("max_queue", 0),
-                         ("max_batch", 0), ("num_streams", 4)):
+    for field, value in (("num_streams", 0), ("groups_per_cu", -1), ("hbm_budget_bytes", 0), ("max_queue", 0),
+                         ("max_batch", 0), ("num_streams", 4), ("groups_per_cu", 2)):
         bad = binding.ServerConfig()
         lib.lscan_server_default_config(ctypes.byref(bad))
         setattr(bad, field, value)

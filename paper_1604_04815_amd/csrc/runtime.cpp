@@ -111,26 +111,25 @@ bool capturing(hipStream_t stream)
 
 // Defaults measured on MI355X (gfx950) with N = 2^27..2^28 arrays: shape
 // index into kShapeThreads/kShapeVectors and workgroups per CU (capped later
-// by the occupancy limit and the co-residency test).
+// by the occupancy limit and the co-residency test).  With the prefix of
+// each block resolved one round late, one large workgroup per CU (B = 256,
+// so a window of 255 aggregates) measured best for every type.
 void init_params_locked()
 {
     if (g_params_init) return;
-    const Params t256x8{0, 5}, t256x16{3, 3}, t1024x4{4, 1}, comp_bf16{3, 2};
-    for (int o = kI32Add; o <= kI32Min; ++o) g_params[kModePlain][o] = t256x8;
-    for (int o = kI64Add; o <= kI64Min; ++o) g_params[kModePlain][o] = t256x16;
-    g_params[kModePlain][kF32Add] = t256x8;
-    g_params[kModePlain][kF32AddComp] = t1024x4;
-    g_params[kModePlain][kF32Max] = t256x8;
-    g_params[kModePlain][kF32Min] = t256x8;
+    const Params t512x8{1, 1}, t1024x4{4, 1}, t256x16{3, 2};
+    for (int o = kI32Add; o <= kI32Min; ++o) g_params[kModePlain][o] = t512x8;
+    for (int o = kI64Add; o <= kI64Min; ++o) g_params[kModePlain][o] = t1024x4;
+    g_params[kModePlain][kF32Add] = t512x8;
+    g_params[kModePlain][kF32AddComp] = t512x8;
+    g_params[kModePlain][kF32Max] = t512x8;
+    g_params[kModePlain][kF32Min] = t512x8;
     g_params[kModePlain][kBF16Add] = t256x16;
-    g_params[kModePlain][kBF16AddComp] = comp_bf16;
+    g_params[kModePlain][kBF16AddComp] = t1024x4;
     g_params[kModePlain][kBF16Max] = t256x16;
     g_params[kModePlain][kBF16Min] = t256x16;
     for (int o = 0; o < kNumOpCodes; ++o) {
-        // segmented kernels: the per-tile head search adds latency, so fewer
-        // groups per CU measured best
-        g_params[kModeSegmented][o] = g_params[kModePlain][o];
-        if (g_params[kModeSegmented][o].groups_per_cu > 3) g_params[kModeSegmented][o].groups_per_cu = 3;
+        g_params[kModeSegmented][o] = t512x8;
         g_params[kModeBatched][o] = g_params[kModePlain][o];
     }
     g_params_init = true;

@@ -258,139 +258,101 @@ __global__ void __launch_bounds__(T) scan_kernel(ScanArgs a)
     const int64_t B = gridDim.x;
     const uint32_t tag = __hip_atomic_load(a.ctrl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1u;
 
-    VB carry = BOp::identity();  // wave 0: P(i - B), the prefix through this group's previous block
-    int parity = 0;
-    for (int64_t i = blockIdx.x; i < a.num_blocks; i += B, parity ^= 1) {
-        // -- which array and which part of it this block covers
-        const In* x;
-        Out* y;
-        int64_t n, tile0;
-        bool vec_ok;
-        uint32_t block_head = 0;
-        if constexpr (MODE == kModeBatched) {
-            int64_t lo = 0, hi = a.num_arrays;  // last r with first_block <= i
-            while (hi - lo > 1) {
-                const int64_t mid = (lo + hi) >> 1;
-                if (a.arrays[mid].first_block <= i)
-                    lo = mid;
-                else
-                    hi = mid;
-            }
-            const BatchArray d = a.arrays[lo];
-            x = static_cast<const In*>(d.x);
-            y = static_cast<Out*>(d.y);
-            n = d.n;
-            tile0 = (i - d.first_block) * L;
-            block_head = (tile0 == 0) ? 1u : 0u;
-            vec_ok = (reinterpret_cast<uintptr_t>(d.x) % uintptr_t(kVecBytes) == 0) &&
-                     (reinterpret_cast<uintptr_t>(d.y) % 16 == 0);
-        } else {
-            x = static_cast<const In*>(a.x);
-            y = static_cast<Out*>(a.y);
-            n = a.n;
-            tile0 = i * L;
-            vec_ok = a.vec_ok != 0;
-        }
-        const int64_t lane0 = tile0 + int64_t(wave) * (R * ROW) + int64_t(lane) * E;
-        const bool full = vec_ok && (tile0 + L <= n);
+    // The block scanned in the previous iteration waits, in registers, for
+    // its prefix: it is resolved (window fold) and stored one iteration
+    // later, while the loads of the next block are in flight, and by then
+    // the aggregates it needs were published a round earlier.
+    bool have_pend = false;
+    int64_t p_i = 0, p_n = 0, p_lane0 = 0;
+    Out* p_y = nullptr;
+    bool p_full = false;
+    uint32_t p_block_head = 0;
+    uint32_t p_head[R];
+    // block-local scan values (inclusive, or exclusive for exclusive scans);
+    // segmented scans keep the value and, per row, a bit per element telling
+    // whether a segment head lies at or before it inside the block
+    using PV = typename BaseOp::V;
+    PV pe[R][E];
+    uint32_t p_seen[R];
+    VB p_agg = BOp::identity();         // wave 0: the pending block's aggregate
+    VB carry = BOp::identity();         // wave 0: P(j - B) for the pending block j
 
-        // -- segment heads inside this lane's vectors (segmented scans only)
+    int parity = 0;
+    for (int64_t i = blockIdx.x;; i += B, parity ^= 1) {
+        const bool have_new = i < a.num_blocks;
+        if (!have_new && !have_pend) break;
+
+        // -- 1. where the new block lives, and its loads (issued first)
+        const In* x = nullptr;
+        Out* y = nullptr;
+        int64_t n = 0, tile0 = 0, lane0 = 0;
+        bool full = false;
+        uint32_t block_head = 0;
         uint32_t head[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) head[r] = 0;
-        if constexpr (MODE == kModeSegmented) {
-            const int64_t S = a.num_segments;
-            const int64_t s_lo = lower_bound_i64(a.offsets, 0, S, tile0);
-            const int64_t s_hi = lower_bound_i64(a.offsets, s_lo, S, tile0 + L);
-            if (s_lo < s_hi) {
-#pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    const int64_t p = lane0 + int64_t(r) * ROW;
-                    int64_t k = lower_bound_i64(a.offsets, s_lo, s_hi, p);
-                    uint32_t h = 0;
-                    for (; k < s_hi; ++k) {
-                        const int64_t o = a.offsets[k];
-                        if (o >= p + E) break;
-                        h |= 1u << uint32_t(o - p);
-                    }
-                    head[r] = h;
+        In raw[R][E];
+        if (have_new) {
+            bool vec_ok;
+            if constexpr (MODE == kModeBatched) {
+                int64_t lo = 0, hi = a.num_arrays;  // last array with first_block <= i
+                while (hi - lo > 1) {
+                    const int64_t mid = (lo + hi) >> 1;
+                    if (a.arrays[mid].first_block <= i)
+                        lo = mid;
+                    else
+                        hi = mid;
                 }
+                const BatchArray d = a.arrays[lo];
+                x = static_cast<const In*>(d.x);
+                y = static_cast<Out*>(d.y);
+                n = d.n;
+                tile0 = (i - d.first_block) * L;
+                block_head = (tile0 == 0) ? 1u : 0u;
+                vec_ok = (reinterpret_cast<uintptr_t>(d.x) % uintptr_t(kVecBytes) == 0) &&
+                         (reinterpret_cast<uintptr_t>(d.y) % 16 == 0);
+            } else {
+                x = static_cast<const In*>(a.x);
+                y = static_cast<Out*>(a.y);
+                n = a.n;
+                tile0 = i * L;
+                vec_ok = a.vec_ok != 0;
+            }
+            lane0 = tile0 + int64_t(wave) * (R * ROW) + int64_t(lane) * E;
+            full = vec_ok && (tile0 + L <= n);
+            if constexpr (MODE == kModeSegmented) {  // segment heads inside this lane's vectors
+                const int64_t S = a.num_segments;
+                const int64_t s_lo = lower_bound_i64(a.offsets, 0, S, tile0);
+                const int64_t s_hi = lower_bound_i64(a.offsets, s_lo, S, tile0 + L);
+                if (s_lo < s_hi) {
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        const int64_t p = lane0 + int64_t(r) * ROW;
+                        int64_t k = lower_bound_i64(a.offsets, s_lo, s_hi, p);
+                        uint32_t h = 0;
+                        for (; k < s_hi; ++k) {
+                            const int64_t o = a.offsets[k];
+                            if (o >= p + E) break;
+                            h |= 1u << uint32_t(o - p);
+                        }
+                        head[r] = h;
+                    }
+                }
+            }
+            if (full) {
+#pragma unroll
+                for (int r = 0; r < R; ++r) load_vector<In, E>(x + lane0 + int64_t(r) * ROW, raw[r]);
             }
         }
 
-        // -- 1. load (each x read exactly once) and lift to scan values
-        V e[R][E];
-        if (full) {
-            In raw[R][E];
-#pragma unroll
-            for (int r = 0; r < R; ++r) load_vector<In, E>(x + lane0 + int64_t(r) * ROW, raw[r]);
-#pragma unroll
-            for (int r = 0; r < R; ++r)
-#pragma unroll
-                for (int k = 0; k < E; ++k) {
-                    if constexpr (MODE == kModeSegmented)
-                        e[r][k] = EOp::make(BaseOp::lift(raw[r][k]), (head[r] >> k) & 1u);
-                    else
-                        e[r][k] = BaseOp::lift(raw[r][k]);
-                }
-        } else {
-#pragma unroll
-            for (int r = 0; r < R; ++r)
-#pragma unroll
-                for (int k = 0; k < E; ++k) {
-                    const int64_t p = lane0 + int64_t(r) * ROW + k;
-                    if (p < n) {
-                        if constexpr (MODE == kModeSegmented)
-                            e[r][k] = EOp::make(BaseOp::lift(x[p]), (head[r] >> k) & 1u);
-                        else
-                            e[r][k] = BaseOp::lift(x[p]);
-                    } else {
-                        e[r][k] = EOp::identity();
-                    }
-                }
-        }
-
-        // -- 2. intra-wave local scan: in-lane, then across lanes per row
-#pragma unroll
-        for (int r = 0; r < R; ++r)
-#pragma unroll
-            for (int k = 1; k < E; ++k) e[r][k] = EOp::combine(e[r][k - 1], e[r][k]);
-
-        V lane_prefix[R];  // exclusive cross-lane prefix within the row
-        V row_total[R];
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const V s = wave_inclusive_scan<EOp>(e[r][E - 1]);
-            row_total[r] = read_lane(s, 63);
-            lane_prefix[r] = wave_shift_right<EOp>(s);
-        }
-        V row_prefix[R];  // rows chained in order (wave-uniform)
-        row_prefix[0] = EOp::identity();
-#pragma unroll
-        for (int r = 1; r < R; ++r) row_prefix[r] = EOp::combine(row_prefix[r - 1], row_total[r - 1]);
-        const V wave_total = EOp::combine(row_prefix[R - 1], row_total[R - 1]);
-
-        // -- 3. intra-block local scan through LDS
-        if (lane == 0) s_wave_total[parity][wave] = wave_total;
-        __syncthreads();
-
-        // -- 4. inter-block communication (wave 0)
-        if (wave == 0) {
-            V agg_e = s_wave_total[parity][0];
-#pragma unroll
-            for (int w = 1; w < NWAVE; ++w) agg_e = EOp::combine(agg_e, s_wave_total[parity][w]);
-            VB agg;
-            if constexpr (MODE == kModeBatched)
-                agg = BOp::make(agg_e, block_head);
-            else
-                agg = agg_e;
-            publish_slot(a.slots + i * W, agg, tag, lane);
-
-            const int64_t cnt = (i < B - 1) ? i : (B - 1);
+        // -- 2. inter-block communication for the pending block (wave 0)
+        if (have_pend && wave == 0) {
+            const int64_t j = p_i;
+            const int64_t cnt = (j < B - 1) ? j : (B - 1);
             bool ok = true;
-            const VB win = window_fold<BOp>(a.slots, i - cnt, cnt, tag, a.spin_limit, lane, ok);
-            const VB prefix = BOp::combine(carry, win);  // P(i - 1)
-            carry = BOp::combine(prefix, agg);           // P(i)
+            const VB win = window_fold<BOp>(a.slots, j - cnt, cnt, tag, a.spin_limit, lane, ok);
+            const VB prefix = BOp::combine(carry, win);  // P(j - 1)
+            carry = BOp::combine(prefix, p_agg);         // P(j)
             const bool abort = __ballot(!ok) != 0;
             if (lane == 0) {
                 s_block_prefix[parity] = prefix;
@@ -402,49 +364,145 @@ __global__ void __launch_bounds__(T) scan_kernel(ScanArgs a)
                 }
             }
         }
-        __syncthreads();
-        if (s_abort[parity]) break;
 
-        // -- 5. intra-block global scan and one coalesced store per vector
-        V prefix;
-        if constexpr (MODE == kModeBatched) {
-            // the first block of an array starts from the identity
-            prefix = block_head ? EOp::identity() : s_block_prefix[parity].v;
-        } else {
-            prefix = s_block_prefix[parity];
-        }
-        for (int w = 0; w < wave; ++w) prefix = EOp::combine(prefix, s_wave_total[parity][w]);
-
+        // -- 3. intra-wave local scan of the new block: in-lane, then across lanes per row
+        V e[R][E];
+        V lane_prefix[R];
+        V row_prefix[R];
+        if (have_new) {
+            if (full) {
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const V lp = EOp::combine(EOp::combine(prefix, row_prefix[r]), lane_prefix[r]);
-            Out out[E];
-            if (!a.exclusive) {
+                for (int r = 0; r < R; ++r)
 #pragma unroll
-                for (int k = 0; k < E; ++k) {
-                    const V v = EOp::combine(lp, e[r][k]);
-                    if constexpr (MODE == kModeSegmented)
-                        out[k] = BaseOp::lower(v.v);
-                    else
-                        out[k] = BaseOp::lower(v);
-                }
+                    for (int k = 0; k < E; ++k) {
+                        if constexpr (MODE == kModeSegmented)
+                            e[r][k] = EOp::make(BaseOp::lift(raw[r][k]), (head[r] >> k) & 1u);
+                        else
+                            e[r][k] = BaseOp::lift(raw[r][k]);
+                    }
             } else {
 #pragma unroll
+                for (int r = 0; r < R; ++r)
+#pragma unroll
+                    for (int k = 0; k < E; ++k) {
+                        const int64_t p = lane0 + int64_t(r) * ROW + k;
+                        if (p < n) {
+                            if constexpr (MODE == kModeSegmented)
+                                e[r][k] = EOp::make(BaseOp::lift(x[p]), (head[r] >> k) & 1u);
+                            else
+                                e[r][k] = BaseOp::lift(x[p]);
+                        } else {
+                            e[r][k] = EOp::identity();
+                        }
+                    }
+            }
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+#pragma unroll
+                for (int k = 1; k < E; ++k) e[r][k] = EOp::combine(e[r][k - 1], e[r][k]);
+            V row_total[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const V sc = wave_inclusive_scan<EOp>(e[r][E - 1]);
+                row_total[r] = read_lane(sc, 63);
+                lane_prefix[r] = wave_shift_right<EOp>(sc);
+            }
+            row_prefix[0] = EOp::identity();
+#pragma unroll
+            for (int r = 1; r < R; ++r) row_prefix[r] = EOp::combine(row_prefix[r - 1], row_total[r - 1]);
+            // -- intra-block local scan: wave totals through LDS
+            if (lane == 0) s_wave_total[parity][wave] = EOp::combine(row_prefix[R - 1], row_total[R - 1]);
+        }
+
+        __syncthreads();  // wave totals of the new block and the pending block's prefix are visible
+        if (have_pend && s_abort[parity]) break;
+
+        // -- 4. the new block's aggregate (published by wave 0) and its block-local
+        //       scan: wave prefix, row prefix and lane prefix folded into each value,
+        //       so only the block prefix is left for the fix-up
+        V wave_prefix = EOp::identity();
+        VB agg = BOp::identity();
+        if (have_new) {
+            for (int w = 0; w < wave; ++w) wave_prefix = EOp::combine(wave_prefix, s_wave_total[parity][w]);
+            if (wave == 0) {
+                V agg_e = s_wave_total[parity][0];
+#pragma unroll
+                for (int w = 1; w < NWAVE; ++w) agg_e = EOp::combine(agg_e, s_wave_total[parity][w]);
+                if constexpr (MODE == kModeBatched)
+                    agg = BOp::make(agg_e, block_head);
+                else
+                    agg = agg_e;
+                publish_slot(a.slots + i * W, agg, tag, lane);
+            }
+        }
+
+        // -- 5. intra-block global scan and one coalesced store per vector, for the pending block
+        if (have_pend) {
+            V prefix;
+            if constexpr (MODE == kModeBatched)  // the first block of an array starts from the identity
+                prefix = p_block_head ? EOp::identity() : s_block_prefix[parity].v;
+            else
+                prefix = s_block_prefix[parity];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                Out out[E];
+#pragma unroll
                 for (int k = 0; k < E; ++k) {
-                    const V v = (k == 0) ? lp : EOp::combine(lp, e[r][k - 1]);
-                    if constexpr (MODE == kModeSegmented)
-                        out[k] = ((head[r] >> k) & 1u) ? BaseOp::lower(BaseOp::identity()) : BaseOp::lower(v.v);
-                    else
-                        out[k] = BaseOp::lower(v);
+                    if constexpr (MODE == kModeSegmented) {
+                        const PV v = ((p_seen[r] >> k) & 1u) ? pe[r][k] : BaseOp::combine(prefix.v, pe[r][k]);
+                        out[k] = (a.exclusive && ((p_head[r] >> k) & 1u)) ? BaseOp::lower(BaseOp::identity())
+                                                                          : BaseOp::lower(v);
+                    } else {
+                        out[k] = BaseOp::lower(EOp::combine(prefix, pe[r][k]));
+                    }
+                }
+                const int64_t p = p_lane0 + int64_t(r) * ROW;
+                if (p_full) {
+                    store_vector<Out, E>(p_y + p, out);
+                } else {
+#pragma unroll
+                    for (int k = 0; k < E; ++k)
+                        if (p + k < p_n) p_y[p + k] = out[k];
                 }
             }
-            const int64_t p = lane0 + int64_t(r) * ROW;
-            if (full) {
-                store_vector<Out, E>(y + p, out);
-            } else {
+        }
+
+        // -- 6. the new block becomes the pending one
+        have_pend = have_new;
+        if (have_new) {
+            p_i = i;
+            p_n = n;
+            p_lane0 = lane0;
+            p_y = y;
+            p_full = full;
+            p_block_head = block_head;
+            p_agg = agg;
 #pragma unroll
-                for (int k = 0; k < E; ++k)
-                    if (p + k < n) y[p + k] = out[k];
+            for (int r = 0; r < R; ++r) {
+                p_head[r] = head[r];
+                // local prefix of this lane's row: waves before, rows before, lanes before
+                const V lp = EOp::combine(EOp::combine(wave_prefix, row_prefix[r]), lane_prefix[r]);
+                V loc[E];
+                if (!a.exclusive) {
+#pragma unroll
+                    for (int k = 0; k < E; ++k) loc[k] = EOp::combine(lp, e[r][k]);
+                } else {
+#pragma unroll
+                    for (int k = E - 1; k > 0; --k) loc[k] = EOp::combine(lp, e[r][k - 1]);
+                    loc[0] = lp;
+                }
+                if constexpr (MODE == kModeSegmented) {
+                    uint32_t seen = 0;
+#pragma unroll
+                    for (int k = 0; k < E; ++k) {
+                        pe[r][k] = loc[k].v;
+                        seen |= (loc[k].f ? 1u : 0u) << k;
+                    }
+                    p_seen[r] = seen;
+                } else {
+#pragma unroll
+                    for (int k = 0; k < E; ++k) pe[r][k] = loc[k];
+                }
             }
         }
     }

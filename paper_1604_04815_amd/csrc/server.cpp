@@ -4,12 +4,12 @@
 // and several streams so that batches overlap on the device.
 //
 // Co-residency: batches launch 256-thread workgroups (one wave per SIMD per
-// workgroup) of the batched kernels, 16 vectors per lane (8 for the
+// workgroup) of the batched kernels, 4 vectors per lane (2 for the
 // compensated pair, whose state is twice as wide), and the workgroups per CU
 // of all streams sum to at most 3, so at most three of those waves share a
 // SIMD.  At creation the server reads every such kernel's VGPR count from
 // the code object and refuses to start unless three waves of the largest
-// fit in one SIMD's 512 registers (on gfx950 they need at most 160 each),
+// fit in one SIMD's 512 registers (on gfx950 they need at most 130 each),
 // so the grids of all streams are always resident together.
 #include <hip/hip_runtime.h>
 
@@ -43,7 +43,7 @@ constexpr int kMaxWorkgroupsPerCu = 3;  // summed over streams
 constexpr int kSimdVgprs = 512;
 constexpr int kVgprGranule = 8;
 
-int server_vectors(uint32_t flags) { return (flags & LSCAN_F_COMPENSATED) ? 8 : 16; }
+int server_vectors(uint32_t flags) { return (flags & LSCAN_F_COMPENSATED) ? 2 : 4; }
 
 struct RequestState {
     lscan_request req;

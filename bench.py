@@ -45,13 +45,18 @@ def log(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+DEVICE_SOURCES = ("scan_kernel.hpp", "scan_ops.hpp", "kernel_table.hpp")
+
+
 def kernel_source_hash() -> str:
+    """Hash of the device code (kernel templates, operators, argument layout
+    and instantiation units); host-only changes leave it unchanged."""
     h = hashlib.sha256()
-    files = sorted(glob.glob(os.path.join(ROOT, "paper_1604_04815_amd", "csrc", "*")))
+    csrc = os.path.join(ROOT, "paper_1604_04815_amd", "csrc")
+    files = [os.path.join(csrc, f) for f in DEVICE_SOURCES] + sorted(glob.glob(os.path.join(csrc, "kernels_*.hip")))
     for f in files:
-        if f.endswith((".hip", ".hpp", ".cpp", ".h")):
-            h.update(os.path.basename(f).encode())
-            h.update(open(f, "rb").read())
+        h.update(os.path.basename(f).encode())
+        h.update(open(f, "rb").read())
     return h.hexdigest()[:16]
 
 

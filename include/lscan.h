@@ -253,6 +253,11 @@ lscan_status lscan_graph_destroy(lscan_graph *g);
  *   (num_streams * groups_per_cu <= 3), groups_per_cu == 0 splits 3 among
  *   the streams, larger shares first (2 + 1 for two streams).  A batch goes
  *   to the free stream with the largest share.
+ *   Large requests: a request of at least solo_bytes is never grouped; when
+ *   it is the oldest it waits until no batch runs, then runs alone as a
+ *   plain full-device scan (lscan_inclusive / lscan_exclusive with the
+ *   default parameters), and nothing else launches until it completes.  The
+ *   largest requests set the tail latency, and they get the fastest kernel.
  *   Scheduling happens in the thread that makes it possible -- lscan_submit
  *   or the completion of a batch -- so an arrival that finds a free stream
  *   is launched before lscan_submit returns.
@@ -269,6 +274,7 @@ typedef struct {
     int32_t max_batch;         /* arrays per launch (default 4096) */
     int32_t groups_per_cu;     /* per stream; 0 = split 3 (default 0) */
     int32_t reserved;
+    uint64_t solo_bytes;       /* requests this large run alone (0 = 64 MiB) */
 } lscan_server_config;
 
 typedef struct {

@@ -54,7 +54,8 @@ class LaunchInfo(ctypes.Structure):
 class ServerConfig(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int32), ("num_streams", ctypes.c_int32),
                 ("hbm_budget_bytes", ctypes.c_uint64), ("max_queue", ctypes.c_int32),
-                ("max_batch", ctypes.c_int32), ("groups_per_cu", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("max_batch", ctypes.c_int32), ("groups_per_cu", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("solo_bytes", ctypes.c_uint64)]
 
 
 class Request(ctypes.Structure):
@@ -397,12 +398,13 @@ class Server:
     """Request server (lscan_server_*): submit device arrays, poll tickets."""
 
     def __init__(self, device=0, num_streams=2, hbm_budget_bytes=32 << 30, max_queue=1 << 16, max_batch=4096,
-                 groups_per_cu=0):
+                 groups_per_cu=0, solo_bytes=0):
         lib = load()
         cfg = ServerConfig()
         _check(lib.lscan_server_default_config(ctypes.byref(cfg)), "lscan_server_default_config")
         cfg.device, cfg.num_streams, cfg.hbm_budget_bytes = device, num_streams, hbm_budget_bytes
         cfg.max_queue, cfg.max_batch, cfg.groups_per_cu = max_queue, max_batch, groups_per_cu
+        cfg.solo_bytes = solo_bytes
         h = ctypes.c_void_p()
         _check(lib.lscan_server_create(ctypes.byref(cfg), ctypes.byref(h)), "lscan_server_create")
         self.handle = h.value

@@ -588,6 +588,17 @@ int batched_kernel_vgprs(int dt, int op, uint32_t flags, int threads, int vector
     return attr.numRegs;
 }
 
+lscan_status launch_single(const void* x, void* y, int64_t n, lscan_dtype dt, lscan_op op, uint32_t flags,
+                           void* stream, uint32_t* status_host)
+{
+    Request r;
+    lscan_status st = make_request(kModePlain, x, y, n, nullptr, 0, nullptr, 0, dt, op, flags & LSCAN_F_COMPENSATED,
+                                   (flags & LSCAN_F_EXCLUSIVE) != 0, nullptr, &r);
+    if (st != LSCAN_OK) return st;
+    r.status_host = status_host;
+    return run(r, stream);
+}
+
 lscan_status launch_batched(const lscan_array* arrays, int64_t count, lscan_dtype dt, lscan_op op, uint32_t flags,
                             const lscan_params* p, void* stream, uint32_t* status_host)
 {

@@ -18,6 +18,11 @@ uint64_t request_bytes(int64_t n, int dt);
 // tile shape, from the code object (-1 if unknown).
 int batched_kernel_vgprs(int dt, int op, uint32_t flags, int threads, int vectors);
 
+// lscan_inclusive / lscan_exclusive (flags & LSCAN_F_EXCLUSIVE) with the
+// default parameters, also raising *status_host on a timeout.
+lscan_status launch_single(const void* x, void* y, int64_t n, lscan_dtype dt, lscan_op op, uint32_t flags,
+                           void* stream, uint32_t* status_host);
+
 // lscan_batched_with_params that also raises *status_host (a device-visible
 // pointer to host memory, may be null) if a workgroup times out.
 lscan_status launch_batched(const lscan_array* arrays, int64_t count, lscan_dtype dt, lscan_op op, uint32_t flags,

@@ -15,7 +15,12 @@
 //     released, so a large request is never overtaken by later requests of
 //     its own key and never starves;
 //   * requests of other keys may be launched ahead of older ones only by
-//     forming their own batch when they become the oldest.
+//     forming their own batch when they become the oldest;
+//   * a request of at least solo_bytes is never grouped: when it is the
+//     oldest it forms a batch of its own, marked solo, which the server runs
+//     alone with the whole device (so the largest requests, which set the
+//     tail latency, get the full-device kernel); smaller requests of its key
+//     may still form batches while it waits behind older requests.
 #pragma once
 
 #include <cstdint>
@@ -38,15 +43,19 @@ struct PendingRequest {
 struct Batch {
     uint64_t key = 0;
     uint64_t bytes = 0;
+    bool solo = false;
     std::vector<uint64_t> tickets;
 };
 
 class Policy {
 public:
-    Policy(uint64_t budget_bytes, size_t max_queue, size_t max_batch)
-        : budget_(budget_bytes), max_queue_(max_queue), max_batch_(max_batch)
+    Policy(uint64_t budget_bytes, size_t max_queue, size_t max_batch, uint64_t solo_bytes = UINT64_MAX)
+        : budget_(budget_bytes), max_queue_(max_queue), max_batch_(max_batch), solo_(solo_bytes)
     {
     }
+
+    // The oldest pending request would run alone.
+    bool head_is_solo() const { return !pending_.empty() && pending_.front().bytes >= solo_; }
 
     Admit submit(const PendingRequest& r)
     {
@@ -63,12 +72,22 @@ public:
         if (pending_.empty()) return b;
         const uint64_t key = pending_.front().key;
         if (in_flight_ + pending_.front().bytes > budget_) return b;  // oldest first
+        if (pending_.front().bytes >= solo_) {
+            b.key = key;
+            b.bytes = pending_.front().bytes;
+            b.solo = true;
+            b.tickets.push_back(pending_.front().ticket);
+            pending_.pop_front();
+            in_flight_ += b.bytes;
+            if (in_flight_ > peak_) peak_ = in_flight_;
+            return b;
+        }
         std::deque<PendingRequest> keep;
         bool closed = false;
         while (!pending_.empty()) {
             PendingRequest r = pending_.front();
             pending_.pop_front();
-            if (!closed && r.key == key) {
+            if (!closed && r.key == key && r.bytes < solo_) {
                 if (b.tickets.size() < max_batch_ && in_flight_ + b.bytes + r.bytes <= budget_) {
                     b.tickets.push_back(r.ticket);
                     b.bytes += r.bytes;
@@ -96,6 +115,7 @@ private:
     uint64_t budget_;
     size_t max_queue_;
     size_t max_batch_;
+    uint64_t solo_;
     uint64_t in_flight_ = 0;
     uint64_t peak_ = 0;
     std::deque<PendingRequest> pending_;

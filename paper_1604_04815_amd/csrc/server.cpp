@@ -80,6 +80,7 @@ struct lscan_server {
     uint64_t next_ticket = 1;
     std::vector<std::unique_ptr<StreamSlot>> slots;
     bool stopping = false;
+    bool exclusive = false;  // a solo request owns the device
     lscan_server_stats stats;
 };
 
@@ -104,11 +105,15 @@ void fail_batch_locked(lscan_server* s, const lscan::serve::Batch& b, lscan_stat
 void schedule_locked(lscan_server* s, std::unique_lock<std::mutex>& lock)
 {
     std::vector<lscan_array> table;
-    while (s->policy->pending() > 0) {
+    while (s->policy->pending() > 0 && !s->exclusive) {
         StreamSlot* slot = nullptr;  // the free slot with the largest grid
-        for (auto& sl : s->slots)
+        bool any_busy = false;
+        for (auto& sl : s->slots) {
+            any_busy |= sl->busy;
             if (!sl->busy && (!slot || sl->groups > slot->groups)) slot = sl.get();
+        }
         if (!slot) return;
+        if (s->policy->head_is_solo() && any_busy) return;  // a large request waits for an idle device
         lscan::serve::Batch b = s->policy->next_batch();
         if (b.tickets.empty()) return;
         const uint64_t t = now_ns();
@@ -128,14 +133,17 @@ void schedule_locked(lscan_server* s, std::unique_lock<std::mutex>& lock)
         slot->batch = b;
         *slot->status = 0;  // the slot's previous batch has completed
         s->stats.batches++;
+        if (b.solo) s->exclusive = true;
         lscan_params prm;
         prm.block_threads = kServerThreads;
         prm.vectors_per_lane = server_vectors(flags);
         prm.groups_per_cu = slot->groups;
         prm.reserved = 0;
         lock.unlock();
-        lscan_status st = lscan::launch_batched(table.data(), int64_t(table.size()), dt, op, flags, &prm,
-                                                slot->stream, slot->status_dev);
+        lscan_status st = b.solo ? lscan::launch_single(table[0].x, table[0].y, table[0].n, dt, op, flags,
+                                                        slot->stream, slot->status_dev)
+                                 : lscan::launch_batched(table.data(), int64_t(table.size()), dt, op, flags, &prm,
+                                                         slot->stream, slot->status_dev);
         if (st == LSCAN_OK && hipEventRecord(slot->done, slot->stream) != hipSuccess) st = LSCAN_ERR_DEVICE;
         const uint64_t t_launch = now_ns();
         lock.lock();
@@ -144,6 +152,7 @@ void schedule_locked(lscan_server* s, std::unique_lock<std::mutex>& lock)
             fail_batch_locked(s, b, st, t_launch);
             slot->busy = false;
             slot->batch = lscan::serve::Batch();
+            if (b.solo) s->exclusive = false;
             s->done_cv.notify_all();
         } else {
             slot->launched = true;
@@ -177,6 +186,7 @@ void completer_loop(lscan_server* s, StreamSlot* sl)
                 s->stats.failed++;
         }
         s->policy->release(sl->batch.bytes);
+        if (sl->batch.solo) s->exclusive = false;
         sl->batch = lscan::serve::Batch();
         sl->launched = false;
         sl->busy = false;
@@ -212,6 +222,17 @@ lscan_status warm_up(lscan_server* s)
                 }
         if (st == LSCAN_OK) st = lscan_check(sl->stream);
     }
+    // the plain full-device kernels that solo requests use
+    hipStream_t s0 = s->slots.front()->stream;
+    for (int dt = LSCAN_I32; dt <= LSCAN_BF16 && st == LSCAN_OK; ++dt)
+        for (int op = LSCAN_ADD; op <= LSCAN_MIN && st == LSCAN_OK; ++op)
+            for (uint32_t comp = 0; comp <= 1 && st == LSCAN_OK; ++comp) {
+                if (comp && !(op == LSCAN_ADD && (dt == LSCAN_F32 || dt == LSCAN_BF16))) continue;
+                char* base = static_cast<char*>(buf);
+                st = lscan_inclusive(base, base + n * 8, int64_t(n), lscan_dtype(dt), lscan_op(op),
+                                     comp ? LSCAN_F_COMPENSATED : 0u, s0);
+            }
+    if (st == LSCAN_OK) st = lscan_check(s0);
     (void)hipDeviceSynchronize();
     (void)hipFree(buf);
     return st;
@@ -242,6 +263,7 @@ lscan_status lscan_server_default_config(lscan_server_config* cfg)
     cfg->hbm_budget_bytes = uint64_t(32) << 30;
     cfg->max_queue = 1 << 16;
     cfg->max_batch = 4096;
+    cfg->solo_bytes = uint64_t(64) << 20;
     return LSCAN_OK;
 }
 
@@ -261,7 +283,9 @@ lscan_status lscan_server_create(const lscan_server_config* cfg, lscan_server** 
     if (!s) return LSCAN_ERR_NO_MEMORY;
     s->cfg = *cfg;
     std::memset(&s->stats, 0, sizeof(s->stats));
-    s->policy.reset(new lscan::serve::Policy(cfg->hbm_budget_bytes, size_t(cfg->max_queue), size_t(cfg->max_batch)));
+    const uint64_t solo = cfg->solo_bytes ? cfg->solo_bytes : (uint64_t(64) << 20);
+    s->policy.reset(
+        new lscan::serve::Policy(cfg->hbm_budget_bytes, size_t(cfg->max_queue), size_t(cfg->max_batch), solo));
     for (int i = 0; i < cfg->num_streams; ++i) {
         std::unique_ptr<StreamSlot> sl(new StreamSlot());
         // groups_per_cu == 0: share kMaxWorkgroupsPerCu among the streams,

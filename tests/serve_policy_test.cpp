@@ -81,6 +81,29 @@ int main()
         p.release(5);
         CHECK(p.in_flight_bytes() == 0);
     }
+    {   // large requests run alone, in submit order; smaller ones of the key are not grouped with them
+        Policy p(1000, 100, 100, 100);
+        p.submit(req(1, 1, 10));
+        p.submit(req(2, 1, 150));   // solo
+        p.submit(req(3, 1, 20));
+        CHECK(!p.head_is_solo());
+        Batch b = p.next_batch();
+        CHECK(!b.solo && b.tickets == v({1, 3}));  // 2 is skipped: it never joins a batch
+        CHECK(p.head_is_solo());
+        b = p.next_batch();
+        CHECK(b.solo && b.tickets == v({2}) && b.bytes == 150);
+        CHECK(p.in_flight_bytes() == 180);
+    }
+    {   // a solo request still waits for budget like any other
+        Policy p(200, 100, 100, 100);
+        p.submit(req(1, 1, 90));
+        p.submit(req(2, 2, 150));
+        CHECK(p.next_batch().tickets == v({1}));
+        CHECK(p.next_batch().tickets.empty());
+        p.release(90);
+        Batch b = p.next_batch();
+        CHECK(b.solo && b.tickets == v({2}));
+    }
     if (failures == 0) std::printf("serve policy: all checks passed\n");
     return failures == 0 ? 0 : 1;
 }

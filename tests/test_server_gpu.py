@@ -20,7 +20,8 @@ def _alone(gpu_lib, x, op, comp, excl):
     return fn(x, op, comp)
 
 
-def test_mix_equals_alone(gpu_lib):
+@pytest.mark.parametrize("solo_bytes", [0, 4 << 20], ids=["solo64MiB", "solo4MiB"])
+def test_mix_equals_alone(gpu_lib, solo_bytes):
     rng = np.random.default_rng(42)
     reqs = []
     for k in range(240):
@@ -31,7 +32,7 @@ def test_mix_equals_alone(gpu_lib):
         y = torch.empty(n, dtype=gpu_lib.out_dtype(x), device="cuda")
         reqs.append((dtype, op, comp, excl, xh, x, y))
     torch.cuda.synchronize()
-    with gpu_lib.Server(num_streams=2) as srv:
+    with gpu_lib.Server(num_streams=2, solo_bytes=solo_bytes) as srv:
         tickets = [srv.submit(x, y, op, excl, comp) for dtype, op, comp, excl, xh, x, y in reqs]
         results = [srv.wait(t) for t in tickets]
         st = srv.stats()

@@ -578,22 +578,23 @@ lscan_status validate_request(const void* x, const void* y, int64_t n, int dt, i
 
 uint64_t request_bytes(int64_t n, int dt) { return uint64_t(n) * uint64_t(in_bytes_of(dt) + out_bytes_of(dt)); }
 
-int batched_kernel_vgprs(int dt, int op, uint32_t flags, int threads, int vectors)
+int kernel_vgprs(bool batched, int dt, int op, uint32_t flags, int threads, int vectors)
 {
     const int oc = opcode_of(dt, op, flags & LSCAN_F_COMPENSATED);
     const int sh = shape_index(threads, vectors);
     if (oc < 0 || sh < 0) return -1;
     hipFuncAttributes attr;
-    if (hipFuncGetAttributes(&attr, table()[kModeBatched][oc][sh].func) != hipSuccess) return -1;
+    if (hipFuncGetAttributes(&attr, table()[batched ? kModeBatched : kModePlain][oc][sh].func) != hipSuccess)
+        return -1;
     return attr.numRegs;
 }
 
 lscan_status launch_single(const void* x, void* y, int64_t n, lscan_dtype dt, lscan_op op, uint32_t flags,
-                           void* stream, uint32_t* status_host)
+                           const lscan_params* p, void* stream, uint32_t* status_host)
 {
     Request r;
     lscan_status st = make_request(kModePlain, x, y, n, nullptr, 0, nullptr, 0, dt, op, flags & LSCAN_F_COMPENSATED,
-                                   (flags & LSCAN_F_EXCLUSIVE) != 0, nullptr, &r);
+                                   (flags & LSCAN_F_EXCLUSIVE) != 0, p, &r);
     if (st != LSCAN_OK) return st;
     r.status_host = status_host;
     return run(r, stream);

@@ -7,10 +7,11 @@
 // workgroup) of the batched kernels, 4 vectors per lane (2 for the
 // compensated pair, whose state is twice as wide), and the workgroups per CU
 // of all streams sum to at most 3, so at most three of those waves share a
-// SIMD.  At creation the server reads every such kernel's VGPR count from
-// the code object and refuses to start unless three waves of the largest
-// fit in one SIMD's 512 registers (on gfx950 they need at most 130 each),
-// so the grids of all streams are always resident together.
+// SIMD.  Batches of one request use the plain kernel of the same shape (no
+// descriptor upload).  At creation the server reads every such kernel's
+// VGPR count from the code object and refuses to start unless three waves
+// of the largest fit in one SIMD's 512 registers (on gfx950 they need at
+// most 130 each), so the grids of all streams are always resident together.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -140,10 +141,18 @@ void schedule_locked(lscan_server* s, std::unique_lock<std::mutex>& lock)
         prm.groups_per_cu = slot->groups;
         prm.reserved = 0;
         lock.unlock();
-        lscan_status st = b.solo ? lscan::launch_single(table[0].x, table[0].y, table[0].n, dt, op, flags,
-                                                        slot->stream, slot->status_dev)
-                                 : lscan::launch_batched(table.data(), int64_t(table.size()), dt, op, flags, &prm,
-                                                         slot->stream, slot->status_dev);
+        // solo: the full-device default kernel; one request: the plain kernel
+        // on this stream's grid share (no descriptor upload); else batched
+        lscan_status st;
+        if (b.solo)
+            st = lscan::launch_single(table[0].x, table[0].y, table[0].n, dt, op, flags, nullptr, slot->stream,
+                                      slot->status_dev);
+        else if (table.size() == 1)
+            st = lscan::launch_single(table[0].x, table[0].y, table[0].n, dt, op, flags, &prm, slot->stream,
+                                      slot->status_dev);
+        else
+            st = lscan::launch_batched(table.data(), int64_t(table.size()), dt, op, flags, &prm, slot->stream,
+                                       slot->status_dev);
         if (st == LSCAN_OK && hipEventRecord(slot->done, slot->stream) != hipSuccess) st = LSCAN_ERR_DEVICE;
         const uint64_t t_launch = now_ns();
         lock.lock();
@@ -216,9 +225,12 @@ lscan_status warm_up(lscan_server* s)
                     if (comp && !(op == LSCAN_ADD && (dt == LSCAN_F32 || dt == LSCAN_BF16))) continue;
                     prm.vectors_per_lane = server_vectors(comp ? LSCAN_F_COMPENSATED : 0u);
                     char* base = static_cast<char*>(buf);
-                    lscan_array a{base, base + n * 8, int64_t(n)};
-                    st = lscan_batched_with_params(&a, 1, lscan_dtype(dt), lscan_op(op),
+                    lscan_array a[2] = {{base, base + n * 8, int64_t(n) / 2}, {base + n * 4, base + n * 12, 64}};
+                    st = lscan_batched_with_params(a, 2, lscan_dtype(dt), lscan_op(op),
                                                    comp ? LSCAN_F_COMPENSATED : 0u, &prm, sl->stream);
+                    if (st == LSCAN_OK)
+                        st = lscan_scan_with_params(base, base + n * 8, int64_t(n), lscan_dtype(dt), lscan_op(op),
+                                                    comp ? LSCAN_F_COMPENSATED : 0u, 0, &prm, sl->stream);
                 }
         if (st == LSCAN_OK) st = lscan_check(sl->stream);
     }
@@ -313,8 +325,10 @@ lscan_status lscan_server_create(const lscan_server_config* cfg, lscan_server** 
             for (uint32_t comp = 0; comp <= 1; ++comp) {
                 if (comp && !(op == LSCAN_ADD && (dt == LSCAN_F32 || dt == LSCAN_BF16))) continue;
                 const uint32_t f = comp ? LSCAN_F_COMPENSATED : 0u;
-                const int v = lscan::batched_kernel_vgprs(dt, op, f, kServerThreads, server_vectors(f));
-                max_vgprs = (v < 0) ? kSimdVgprs : std::max(max_vgprs, v);
+                for (int batched = 0; batched <= 1; ++batched) {
+                    const int v = lscan::kernel_vgprs(batched != 0, dt, op, f, kServerThreads, server_vectors(f));
+                    max_vgprs = (v < 0) ? kSimdVgprs : std::max(max_vgprs, v);
+                }
             }
     const int alloc = (max_vgprs + kVgprGranule - 1) / kVgprGranule * kVgprGranule;
     if (kMaxWorkgroupsPerCu * alloc > kSimdVgprs) {

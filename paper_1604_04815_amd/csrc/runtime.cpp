@@ -117,17 +117,20 @@ bool capturing(hipStream_t stream)
 void init_params_locked()
 {
     if (g_params_init) return;
-    const Params t512x8{1, 1}, t1024x4{4, 1}, t256x16{3, 2};
-    for (int o = kI32Add; o <= kI32Min; ++o) g_params[kModePlain][o] = t512x8;
-    for (int o = kI64Add; o <= kI64Min; ++o) g_params[kModePlain][o] = t1024x4;
-    g_params[kModePlain][kF32Add] = t512x8;
-    g_params[kModePlain][kF32AddComp] = t512x8;
-    g_params[kModePlain][kF32Max] = t512x8;
-    g_params[kModePlain][kF32Min] = t512x8;
-    g_params[kModePlain][kBF16Add] = t256x16;
+    // measured on MI355X (shape x groups/CU sweep of the persistent scan)
+    const Params t512x8{1, 1}, t512x8g2{1, 2}, t1024x4{4, 1}, t256x16g2{3, 2};
+    g_params[kModePlain][kI32Add] = t256x16g2;
+    g_params[kModePlain][kI32Max] = t512x8g2;
+    g_params[kModePlain][kI32Min] = t512x8g2;
+    for (int o = kI64Add; o <= kI64Min; ++o) g_params[kModePlain][o] = t512x8g2;
+    g_params[kModePlain][kF32Add] = t256x16g2;
+    g_params[kModePlain][kF32AddComp] = t1024x4;
+    g_params[kModePlain][kF32Max] = t512x8g2;
+    g_params[kModePlain][kF32Min] = t512x8g2;
+    g_params[kModePlain][kBF16Add] = t256x16g2;
     g_params[kModePlain][kBF16AddComp] = t1024x4;
-    g_params[kModePlain][kBF16Max] = t256x16;
-    g_params[kModePlain][kBF16Min] = t256x16;
+    g_params[kModePlain][kBF16Max] = t256x16g2;
+    g_params[kModePlain][kBF16Min] = t256x16g2;
     for (int o = 0; o < kNumOpCodes; ++o) {
         g_params[kModeSegmented][o] = t512x8;
         g_params[kModeBatched][o] = g_params[kModePlain][o];

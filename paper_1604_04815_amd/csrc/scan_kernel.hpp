@@ -162,6 +162,16 @@ __device__ typename Op::V window_fold(const uint64_t* slots, int64_t lo, int64_t
     return acc;
 }
 
+// Read-only data reached through the constant address space: wave-uniform
+// loads from it go through the scalar cache and do not queue behind the
+// vector loads of the data.
+typedef const int64_t __attribute__((address_space(4))) CInt64;
+typedef const BatchArray __attribute__((address_space(4))) CBatchArray;
+
+// Up to this many segment heads in a block are matched by a wave-uniform loop;
+// more take a per-lane binary search.
+constexpr int64_t kFewHeads = 32;
+
 // First index k in [lo, hi) with off[k] >= v, or hi.
 __device__ __forceinline__ int64_t lower_bound_i64(const int64_t* off, int64_t lo, int64_t hi, int64_t v)
 {
@@ -278,9 +288,15 @@ __global__ void __launch_bounds__(T) scan_kernel(ScanArgs a)
     VB carry = BOp::identity();         // wave 0: P(j - B) for the pending block j
 
     int parity = 0;
-    for (int64_t i = blockIdx.x;; i += B, parity ^= 1) {
-        const bool have_new = i < a.num_blocks;
-        if (!have_new && !have_pend) break;
+    int64_t arr_lo = 0;  // batched scans: the array of this workgroup's last block
+    // One pipeline step: load and scan block i (when have_new) while the pending
+    // block is resolved and stored.  The step that only drains the last
+    // pending block is a separate instantiation, so inside the main loop every
+    // load issued is consumed on every path and the compiler never has to
+    // drain the previous step's stores before the next loads go out.
+    // Returns false if the pending block's window timed out.
+    auto step = [&](auto new_tag, int64_t i) -> bool {
+        constexpr bool have_new = decltype(new_tag)::value;
 
         // -- 1. where the new block lives, and its loads (issued first)
         const In* x = nullptr;
@@ -295,15 +311,25 @@ __global__ void __launch_bounds__(T) scan_kernel(ScanArgs a)
         if (have_new) {
             bool vec_ok;
             if constexpr (MODE == kModeBatched) {
-                int64_t lo = 0, hi = a.num_arrays;  // last array with first_block <= i
+                // last array with first_block <= i: a wave-uniform search through
+                // the scalar cache (the table is read-only during the launch),
+                // starting from this workgroup's previous array, since a
+                // workgroup's blocks only move forward
+                const CBatchArray* arr = (const CBatchArray*)(a.arrays);
+                int64_t lo = arr_lo, hi = a.num_arrays;
                 while (hi - lo > 1) {
                     const int64_t mid = (lo + hi) >> 1;
-                    if (a.arrays[mid].first_block <= i)
+                    if (arr[mid].first_block <= i)
                         lo = mid;
                     else
                         hi = mid;
                 }
-                const BatchArray d = a.arrays[lo];
+                arr_lo = lo;
+                BatchArray d;  // field by field: no copy constructor binds the constant address space
+                d.x = arr[lo].x;
+                d.y = arr[lo].y;
+                d.n = arr[lo].n;
+                d.first_block = arr[lo].first_block;
                 x = static_cast<const In*>(d.x);
                 y = static_cast<Out*>(d.y);
                 n = d.n;
@@ -320,11 +346,42 @@ __global__ void __launch_bounds__(T) scan_kernel(ScanArgs a)
             }
             lane0 = tile0 + int64_t(wave) * (R * ROW) + int64_t(lane) * E;
             full = vec_ok && (tile0 + L <= n);
+            if (full) {
+#pragma unroll
+                for (int r = 0; r < R; ++r) load_vector<In, E>(x + lane0 + int64_t(r) * ROW, raw[r]);
+            }
             if constexpr (MODE == kModeSegmented) {  // segment heads inside this lane's vectors
+                // Found while the data loads are in flight.  The block's range
+                // of offsets comes from two interleaved wave-uniform binary
+                // searches through the scalar cache (the offsets are read-only
+                // during the launch); a few heads are then matched against
+                // every lane's vectors, many by a per-lane search.
+                const CInt64* off = (const CInt64*)(a.offsets);
                 const int64_t S = a.num_segments;
-                const int64_t s_lo = lower_bound_i64(a.offsets, 0, S, tile0);
-                const int64_t s_hi = lower_bound_i64(a.offsets, s_lo, S, tile0 + L);
-                if (s_lo < s_hi) {
+                int64_t lo1 = 0, hi1 = S, lo2 = 0, hi2 = S;
+                while (lo1 < hi1 || lo2 < hi2) {
+                    const bool a1 = lo1 < hi1, a2 = lo2 < hi2;
+                    const int64_t m1 = a1 ? lo1 + ((hi1 - lo1) >> 1) : 0;
+                    const int64_t m2 = a2 ? lo2 + ((hi2 - lo2) >> 1) : 0;
+                    const int64_t v1 = off[m1], v2 = off[m2];
+                    if (a1) {
+                        if (v1 < tile0) lo1 = m1 + 1; else hi1 = m1;
+                    }
+                    if (a2) {
+                        if (v2 < tile0 + L) lo2 = m2 + 1; else hi2 = m2;
+                    }
+                }
+                const int64_t s_lo = lo1, s_hi = lo2;
+                if (s_hi - s_lo <= kFewHeads) {
+                    for (int64_t k = s_lo; k < s_hi; ++k) {
+                        const int64_t rel = off[k] - lane0;
+#pragma unroll
+                        for (int r = 0; r < R; ++r) {
+                            const int64_t d = rel - int64_t(r) * ROW;
+                            if (uint64_t(d) < uint64_t(E)) head[r] |= 1u << uint32_t(d);
+                        }
+                    }
+                } else {
 #pragma unroll
                     for (int r = 0; r < R; ++r) {
                         const int64_t p = lane0 + int64_t(r) * ROW;
@@ -338,10 +395,6 @@ __global__ void __launch_bounds__(T) scan_kernel(ScanArgs a)
                         head[r] = h;
                     }
                 }
-            }
-            if (full) {
-#pragma unroll
-                for (int r = 0; r < R; ++r) load_vector<In, E>(x + lane0 + int64_t(r) * ROW, raw[r]);
             }
         }
 
@@ -415,7 +468,7 @@ __global__ void __launch_bounds__(T) scan_kernel(ScanArgs a)
         }
 
         __syncthreads();  // wave totals of the new block and the pending block's prefix are visible
-        if (have_pend && s_abort[parity]) break;
+        if (have_pend && s_abort[parity]) return false;
 
         // -- 4. the new block's aggregate (published by wave 0) and its block-local
         //       scan: wave prefix, row prefix and lane prefix folded into each value,
@@ -505,7 +558,14 @@ __global__ void __launch_bounds__(T) scan_kernel(ScanArgs a)
                 }
             }
         }
-    }
+        return true;
+    };
+
+    int64_t i = blockIdx.x;
+    bool live = true;
+    for (; i < a.num_blocks; i += B, parity ^= 1)
+        if (!(live = step(std::true_type{}, i))) break;
+    if (live && have_pend) step(std::false_type{}, i);
 
     // Every workgroup counts itself out; the last one advances the epoch so
     // the next launch on this workspace uses a fresh tag (no memset needed).

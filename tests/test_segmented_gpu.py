@@ -81,3 +81,21 @@ def test_segmented_every_shape(gpu_lib, shape):
             p = gpu_lib.Params(t, r, groups, 0)
             got = run(gpu_lib, x, off, dtype, op, False, comp, params=p)
             compare(got, x, dtype, op, False, comp, offsets=off, what=f"seg T={t} R={r} g={groups} {dtype}")
+
+
+@pytest.mark.parametrize("max_len", [1024, 2048, 96])
+def test_heads_per_block_around_matching_limit(gpu_lib, max_len):
+    # Segment lengths uniform in [0, max_len] (empty segments included): blocks
+    # of 16K elements then hold about 32 heads (max_len 1024), about 16 (2048)
+    # or hundreds (96), so both ways of locating heads inside a block are used,
+    # often in neighbouring blocks.
+    rng = np.random.default_rng(1604 + max_len)
+    lens = rng.integers(0, max_len + 1, size=(3 << 21) // max_len)
+    off = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    n = int(off[-1])
+    log(f"[seg] heads test max_len={max_len} n={n} segments={len(lens)}")
+    for dtype, op, comp in (("int32", "add", False), ("float32", "add", True), ("int64", "min", False)):
+        x = make_input(dtype, op, n, seed=9)
+        for excl in (False, True):
+            got = run(gpu_lib, x, off, dtype, op, excl, comp)
+            compare(got, x, dtype, op, excl, comp, offsets=off, what=f"heads {max_len} {dtype}/{op}/excl={excl}")

@@ -18,8 +18,9 @@ Prints ONE JSON line on stdout.  Besides the contract keys it carries
                 array,
   configs       the other workloads (int64 add, int32 max, float32 add plain
                 and compensated, bf16 -> float32, a 4096-array segmented scan
-                against 4096 plain launches, and the 2^20 latency case), plus
-                a device copy of the same size as the practical ceiling.
+                against 4096 plain launches, the 2^20 latency case, and the
+                paper's serial prefix chain at 2^20 and 2^28 against the
+                default window hand-off), plus a device copy of the same size.
 
 Progress lines go to stderr.  ``--gpus N`` with N > 1 is refused: this build
 runs on one GPU.
@@ -238,6 +239,30 @@ def bench_latency(binding, workloads, steps):
         host.append((time.perf_counter() - t0) * 1e3)
     e = rate_entry(8 * (1 << 20), 1 << 20, ms, per)
     e.update({"host_call_sync_ms_p50": round(pct(host, 50), 4), "host_call_sync_ms_p99": round(pct(host, 99), 4)})
+    return e
+
+
+def bench_chain(binding, x_host, steps):
+    """The paper's prefix chain (every block waits for its predecessor's
+    inclusive prefix) against the default window hand-off, same shape and
+    input: time per launch, and the time per hand-off in the chain."""
+    import torch
+
+    xd = to_device(x_host, "int32")
+    n = xd.shape[0]
+    y = torch.empty_like(xd)
+    binding.inclusive(xd, "add", out=y)
+    window = y.clone()
+    p = binding.Params(0, 0, 0, binding.HANDOFF_CHAIN)
+    ms, per = time_steps(lambda: binding.inclusive(xd, "add", out=y, params=p), steps, 1)
+    binding.lscan_check(torch.cuda.current_stream().cuda_stream)
+    info = binding.lscan_last_launch()
+    e = rate_entry(8 * n, n, ms, per)
+    e.update({"n": n, "num_blocks": info.num_blocks, "grid": info.grid, "block_threads": info.block_threads,
+              "us_per_handoff": round(ms * 1e3 / info.num_blocks, 4),
+              "bit_equal_to_window": bool(torch.equal(y, window))})
+    del xd, y, window
+    torch.cuda.empty_cache()
     return e
 
 
@@ -460,6 +485,12 @@ def main(argv=None) -> int:
                     f"{hv['serial_plain']['p50_us']}/{hv['serial_plain']['p99_us']} us")
         log("latency: int32 add N=2^20")
         configs["int32_add_2p20_latency"] = bench_latency(binding, workloads, args.steps)
+        log("the paper's prefix chain: int32 add N=2^20 and N=2^28")
+        configs["int32_add_2p20_chain"] = bench_chain(
+            binding, workloads.uniform_int(1 << 20, -1000, 1000, workloads.seed_for(0)), 10)
+        configs["int32_add_2p28_chain"] = bench_chain(binding, x, 3)
+        log(f"  chain {configs['int32_add_2p28_chain']['gbs']} GB/s, "
+            f"{configs['int32_add_2p28_chain']['us_per_handoff']} us per hand-off")
         try:
             xd = to_device(x, "int32")
             yd = torch.empty_like(xd)

@@ -148,6 +148,20 @@ lscan_status lscan_batched(const lscan_array *arrays, int64_t count,
  *                     (so K = vectors_per_lane * 16 / sizeof(input))
  *   groups_per_cu     resident workgroups per compute unit; B = this times
  *                     the CU count, capped by the occupancy limit and by M
+ *   handoff           how a block obtains the prefix of the blocks before it
+ *                     (Section 4.3, Algorithm 4):
+ *                     LSCAN_HANDOFF_WINDOW (0, default): every block publishes
+ *                       its aggregate; block i folds its workgroup's previous
+ *                       inclusive prefix P(i-B) with the aggregates of blocks
+ *                       i-B+1 .. i-1 in a fixed order;
+ *                     LSCAN_HANDOFF_CHAIN (1): the paper's chain: block i
+ *                       waits for the inclusive prefix published by block
+ *                       i-1 and publishes its own, so the M blocks form one
+ *                       serial chain of flag hand-offs (the paper-faithful
+ *                       baseline; slow on a device with 8 separate L2s);
+ *                     other values are invalid (LSCAN_ERR_INVALID_ARG).
+ *                     Both give the same integer / max / min results; float
+ *                     sums differ only in association.
  * The persistent grid needs all B workgroups resident at once (paper,
  * Section 5.1).  Before the first launch of a (kernel, groups_per_cu) pair
  * on a device, the library runs that kernel once in a test mode in which
@@ -157,11 +171,14 @@ lscan_status lscan_batched(const lscan_array *arrays, int64_t count,
  * made while the stream is being captured into a graph
  * (LSCAN_ERR_UNSUPPORTED).
  */
+#define LSCAN_HANDOFF_WINDOW 0
+#define LSCAN_HANDOFF_CHAIN 1
+
 typedef struct {
     int32_t block_threads;
     int32_t vectors_per_lane;
     int32_t groups_per_cu;
-    int32_t reserved;
+    int32_t handoff;
 } lscan_params;
 
 /* Number of compiled (block_threads, vectors_per_lane) tile shapes, and the

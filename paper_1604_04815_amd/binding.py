@@ -37,7 +37,7 @@ class LscanError(RuntimeError):
 
 class Params(ctypes.Structure):
     _fields_ = [("block_threads", ctypes.c_int32), ("vectors_per_lane", ctypes.c_int32),
-                ("groups_per_cu", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("groups_per_cu", ctypes.c_int32), ("handoff", ctypes.c_int32)]
 
 
 class Array(ctypes.Structure):
@@ -254,6 +254,7 @@ def lscan_tile_shapes() -> list[tuple[int, int]]:
 
 
 KIND_PLAIN, KIND_SEGMENTED, KIND_BATCHED = 0, 1, 2
+HANDOFF_WINDOW, HANDOFF_CHAIN = 0, 1
 
 
 def lscan_get_params(dt, op, flags=0, kind=KIND_PLAIN) -> Params:

@@ -33,12 +33,13 @@ struct ScanArgs {
     int64_t num_arrays;
     uint64_t* slots;          // M * slot_words flag words (epoch tag | data)
     uint32_t* ctrl;           // [0] last epoch tag, [1] exit counter, [2] timeout flag,
+                              // [3] tag of the last launch that gave up a wait,
                               // [4] residency arrivals, [5] residency failure, [6] residency exits
     uint64_t spin_limit;      // wall-clock ticks one wait may last
     int32_t exclusive;        // 1: exclusive scan
     int32_t vec_ok;           // 1: x and y allow full-width vector access
     int32_t residency_check;  // 1: only test that all workgroups are resident at once, then exit
-    int32_t pad_;
+    int32_t chain;            // 1: the paper's prefix chain (block i waits for P(i - 1))
     uint32_t* status_host;    // optional host-visible word that also receives the timeout flag
 };
 

@@ -89,6 +89,7 @@ struct Workspace {
 struct Params {
     int shape;
     int groups_per_cu;
+    int handoff = LSCAN_HANDOFF_WINDOW;
 };
 
 std::mutex g_mu;
@@ -185,6 +186,7 @@ lscan_status check_params(const lscan_params* p)
         shape_index(p->block_threads, p->vectors_per_lane) < 0)
         return LSCAN_ERR_UNSUPPORTED;
     if (p->groups_per_cu < 0) return LSCAN_ERR_INVALID_ARG;
+    if (p->handoff != LSCAN_HANDOFF_WINDOW && p->handoff != LSCAN_HANDOFF_CHAIN) return LSCAN_ERR_INVALID_ARG;
     return LSCAN_OK;
 }
 
@@ -327,8 +329,11 @@ lscan_status ensure_workspace(Workspace& ws, hipStream_t stream, size_t words, s
         e = hipMemsetAsync(ws.ctrl, 0, 64, stream);
         if (e != hipSuccess) return device_error(e);
     } else if (need_reset) {
-        // keep the timeout flag (word 2); restart the tag and the exit counter
+        // keep the timeout flag (word 2); restart the tag and the exit counter,
+        // and forget the tag of the last launch that gave up (word 3), which
+        // a restarted tag could otherwise meet again
         e = hipMemsetAsync(ws.ctrl, 0, 2 * sizeof(uint32_t), stream);
+        if (e == hipSuccess) e = hipMemsetAsync(ws.ctrl + 3, 0, sizeof(uint32_t), stream);
         if (e != hipSuccess) return device_error(e);
     }
     if (need_reset) ws.launches = 0;
@@ -439,6 +444,7 @@ lscan_status plan_locked(const Request& r, int dev, Workspace* ws_fixed, hipStre
     if (r.p && (r.p->block_threads != 0 || r.p->vectors_per_lane != 0))
         prm.shape = shape_index(r.p->block_threads, r.p->vectors_per_lane);
     if (r.p && r.p->groups_per_cu > 0) prm.groups_per_cu = r.p->groups_per_cu;
+    if (r.p) prm.handoff = r.p->handoff;
     const KernelEntry& k = table()[r.mode][r.oc][prm.shape];
 
     DeviceInfo* info = nullptr;
@@ -524,6 +530,7 @@ lscan_status plan_locked(const Request& r, int dev, Workspace* ws_fixed, hipStre
     a.ctrl = ws->ctrl;
     a.spin_limit = info->spin_limit;
     a.exclusive = r.exclusive ? 1 : 0;
+    a.chain = (prm.handoff == LSCAN_HANDOFF_CHAIN) ? 1 : 0;
     a.residency_check = 0;
     a.status_host = r.status_host;
 
@@ -812,7 +819,7 @@ lscan_status lscan_tile_shape(int32_t idx, lscan_params* out)
     out->block_threads = kShapeThreads[idx];
     out->vectors_per_lane = kShapeVectors[idx];
     out->groups_per_cu = 0;
-    out->reserved = 0;
+    out->handoff = LSCAN_HANDOFF_WINDOW;
     return LSCAN_OK;
 }
 
@@ -828,7 +835,7 @@ lscan_status lscan_get_params(lscan_dtype dt, lscan_op op, uint32_t flags, int32
     out->block_threads = kShapeThreads[p.shape];
     out->vectors_per_lane = kShapeVectors[p.shape];
     out->groups_per_cu = p.groups_per_cu;
-    out->reserved = 0;
+    out->handoff = p.handoff;
     return LSCAN_OK;
 }
 
@@ -841,9 +848,10 @@ lscan_status lscan_set_params(lscan_dtype dt, lscan_op op, uint32_t flags, int32
     const int s = shape_index(p->block_threads, p->vectors_per_lane);
     if (s < 0) return LSCAN_ERR_UNSUPPORTED;
     if (p->groups_per_cu <= 0) return LSCAN_ERR_INVALID_ARG;
+    if (p->handoff != LSCAN_HANDOFF_WINDOW && p->handoff != LSCAN_HANDOFF_CHAIN) return LSCAN_ERR_INVALID_ARG;
     std::lock_guard<std::mutex> lock(g_mu);
     init_params_locked();
-    g_params[kind][oc] = Params{s, p->groups_per_cu};
+    g_params[kind][oc] = Params{s, p->groups_per_cu, p->handoff};
     return LSCAN_OK;
 }
 

@@ -98,10 +98,12 @@ __device__ __forceinline__ void publish_slot(uint64_t* slot, const V& v, uint32_
     }
 }
 
-// Re-read a flag word until it carries this launch's tag, or give up after
-// `limit` wall-clock ticks (ok = false).
+// Re-read a flag word until it carries this launch's tag, or give up
+// (ok = false) after `limit` wall-clock ticks or as soon as another
+// workgroup of this launch has given up (*abort_word == tag), so one timeout
+// does not turn into a cascade of waits for values that never come.
 __device__ __forceinline__ uint64_t await_word(const uint64_t* p, uint64_t w, uint32_t tag,
-                                               uint64_t limit, bool& ok)
+                                               uint64_t limit, const uint32_t* abort_word, bool& ok)
 {
     if (uint32_t(w >> 32) == tag || !ok) return w;
     const uint64_t t0 = wall_clock64();
@@ -109,6 +111,8 @@ __device__ __forceinline__ uint64_t await_word(const uint64_t* p, uint64_t w, ui
         __builtin_amdgcn_s_sleep(1);
         w = slot_load(p);
         if (uint32_t(w >> 32) == tag) return w;
+        if (__hip_atomic_load(const_cast<uint32_t*>(abort_word), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == tag)
+            break;
     } while (wall_clock64() - t0 < limit);
     ok = false;
     return w;
@@ -119,7 +123,7 @@ __device__ __forceinline__ uint64_t await_word(const uint64_t* p, uint64_t w, ui
 // cross-lane scan (a fixed tree), rounds folded left to right.
 template <class Op>
 __device__ typename Op::V window_fold(const uint64_t* slots, int64_t lo, int64_t cnt, uint32_t tag,
-                                      uint64_t limit, int lane, bool& ok)
+                                      uint64_t limit, const uint32_t* abort_word, int lane, bool& ok)
 {
     using V = typename Op::V;
     constexpr int W = sizeof(V) / 4;
@@ -140,7 +144,7 @@ __device__ typename Op::V window_fold(const uint64_t* slots, int64_t lo, int64_t
             if (j < cnt) {
 #pragma unroll
                 for (int k = 0; k < W; ++k)
-                    w[q][k] = await_word(slots + (lo + j) * W + k, w[q][k], tag, limit, ok);
+                    w[q][k] = await_word(slots + (lo + j) * W + k, w[q][k], tag, limit, abort_word, ok);
             }
         }
 #pragma unroll
@@ -160,6 +164,28 @@ __device__ typename Op::V window_fold(const uint64_t* slots, int64_t lo, int64_t
         }
     }
     return acc;
+}
+
+// The paper's hand-off (Algorithm 4): wait for the inclusive prefix that the
+// previous block published in its slot.  Lanes 0 .. W-1 each wait for one
+// word; the value is assembled from their lanes.
+template <class Op>
+__device__ __forceinline__ typename Op::V chain_prefix(const uint64_t* slot, uint32_t tag, uint64_t limit,
+                                                       const uint32_t* abort_word, int lane, bool& ok)
+{
+    using V = typename Op::V;
+    constexpr int W = sizeof(V) / 4;
+    uint64_t w = uint64_t(tag) << 32;
+    if (lane < W) {
+        w = slot_load(slot + lane);
+        w = await_word(slot + lane, w, tag, limit, abort_word, ok);
+    }
+    uint32_t d[W];
+#pragma unroll
+    for (int k = 0; k < W; ++k) d[k] = __builtin_amdgcn_readlane(uint32_t(w), k);
+    V v;
+    __builtin_memcpy(&v, d, sizeof(V));
+    return v;
 }
 
 // Read-only data reached through the constant address space: wave-uniform
@@ -401,17 +427,26 @@ __global__ void __launch_bounds__(T) scan_kernel(ScanArgs a)
         // -- 2. inter-block communication for the pending block (wave 0)
         if (have_pend && wave == 0) {
             const int64_t j = p_i;
-            const int64_t cnt = (j < B - 1) ? j : (B - 1);
             bool ok = true;
-            const VB win = window_fold<BOp>(a.slots, j - cnt, cnt, tag, a.spin_limit, lane, ok);
-            const VB prefix = BOp::combine(carry, win);  // P(j - 1)
-            carry = BOp::combine(prefix, p_agg);         // P(j)
+            VB prefix;  // P(j - 1)
+            if (a.chain) {
+                // the paper's chain: P(j - 1) from block j - 1's slot, then P(j) published
+                prefix = (j == 0) ? BOp::identity() : chain_prefix<BOp>(a.slots + (j - 1) * W, tag, a.spin_limit,
+                                                                        a.ctrl + 3, lane, ok);
+                publish_slot(a.slots + j * W, BOp::combine(prefix, p_agg), tag, lane);
+            } else {
+                const int64_t cnt = (j < B - 1) ? j : (B - 1);
+                const VB win = window_fold<BOp>(a.slots, j - cnt, cnt, tag, a.spin_limit, a.ctrl + 3, lane, ok);
+                prefix = BOp::combine(carry, win);
+                carry = BOp::combine(prefix, p_agg);  // P(j)
+            }
             const bool abort = __ballot(!ok) != 0;
             if (lane == 0) {
                 s_block_prefix[parity] = prefix;
                 s_abort[parity] = abort ? 1 : 0;
                 if (abort) {
                     __hip_atomic_store(a.ctrl + 2, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    __hip_atomic_store(a.ctrl + 3, tag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     if (a.status_host)
                         __hip_atomic_store(a.status_host, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
                 }
@@ -485,7 +520,7 @@ __global__ void __launch_bounds__(T) scan_kernel(ScanArgs a)
                     agg = BOp::make(agg_e, block_head);
                 else
                     agg = agg_e;
-                publish_slot(a.slots + i * W, agg, tag, lane);
+                if (!a.chain) publish_slot(a.slots + i * W, agg, tag, lane);
             }
         }
 

@@ -139,7 +139,7 @@ void schedule_locked(lscan_server* s, std::unique_lock<std::mutex>& lock)
         prm.block_threads = kServerThreads;
         prm.vectors_per_lane = server_vectors(flags);
         prm.groups_per_cu = slot->groups;
-        prm.reserved = 0;
+        prm.handoff = LSCAN_HANDOFF_WINDOW;
         lock.unlock();
         // solo: the full-device default kernel; one request: the plain kernel
         // on this stream's grid share (no descriptor upload); else batched
@@ -218,7 +218,7 @@ lscan_status warm_up(lscan_server* s)
         lscan_params prm;
         prm.block_threads = kServerThreads;
         prm.groups_per_cu = sl->groups;
-        prm.reserved = 0;
+        prm.handoff = LSCAN_HANDOFF_WINDOW;
         for (int dt = LSCAN_I32; dt <= LSCAN_BF16 && st == LSCAN_OK; ++dt)
             for (int op = LSCAN_ADD; op <= LSCAN_MIN && st == LSCAN_OK; ++op)
                 for (uint32_t comp = 0; comp <= 1 && st == LSCAN_OK; ++comp) {

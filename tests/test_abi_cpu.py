@@ -115,6 +115,23 @@ def test_params_validation(lib):
     neg = binding.Params(0, 0, -1, 0)
     st = lib.lscan_scan_with_params(FAKE_X, FAKE_Y, 8, 0, 0, 0, 0, ctypes.byref(neg), None)
     assert st == binding.ERR_INVALID_ARG
+    for handoff in (-1, 2, 7):
+        bad = binding.Params(0, 0, 0, handoff)
+        st = lib.lscan_scan_with_params(FAKE_X, FAKE_Y, 8, 0, 0, 0, 0, ctypes.byref(bad), None)
+        assert st == binding.ERR_INVALID_ARG, handoff
+        st = lib.lscan_set_params(binding.I32, binding.ADD, 0, binding.KIND_PLAIN,
+                                  ctypes.byref(binding.Params(256, 8, 1, handoff)))
+        assert st == binding.ERR_INVALID_ARG, handoff
+
+
+def test_handoff_default_roundtrip(lib):
+    p = binding.lscan_get_params(binding.I64, binding.MAX)
+    assert p.handoff == binding.HANDOFF_WINDOW
+    q = binding.Params(p.block_threads, p.vectors_per_lane, p.groups_per_cu, binding.HANDOFF_CHAIN)
+    binding.lscan_set_params(binding.I64, binding.MAX, 0, False, q)
+    assert binding.lscan_get_params(binding.I64, binding.MAX).handoff == binding.HANDOFF_CHAIN
+    binding.lscan_set_params(binding.I64, binding.MAX, 0, False, p)
+    assert binding.lscan_get_params(binding.I64, binding.MAX).handoff == binding.HANDOFF_WINDOW
 
 
 def test_raising_wrappers(lib):

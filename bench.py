@@ -22,6 +22,10 @@ Prints ONE JSON line on stdout.  Besides the contract keys it carries
                 paper's serial prefix chain at 2^20 and 2^28 against the
                 default window hand-off), plus a device copy of the same size.
 
+Before the warmup steps of every measurement the device runs the same call
+for about SETTLE_S seconds (untimed), so that clocks have left the idle state
+that input generation or a host-side oracle check leaves behind.
+
 Progress lines go to stderr.  ``--gpus N`` with N > 1 is refused: this build
 runs on one GPU.
 """
@@ -85,11 +89,29 @@ def read_traffic():
 # device timing
 # ---------------------------------------------------------------------------
 
-def time_steps(fn, steps: int, warmup: int):
-    """Run fn warmup + steps times on the current stream; returns
-    (mean ms per step over the whole timed region, per-step ms list)."""
+SETTLE_S = 0.15
+
+
+def settle(fn, seconds: float = SETTLE_S):
+    """Keep the device busy with fn for about `seconds` before any warmup or
+    timing: after an idle stretch (input generation, an oracle check on the
+    host) the GPU takes milliseconds to return to its working clocks, which
+    a few warmup steps of a sub-millisecond kernel do not cover."""
     import torch
 
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < seconds:
+        for _ in range(8):
+            fn()
+        torch.cuda.synchronize()
+
+
+def time_steps(fn, steps: int, warmup: int):
+    """Settle the device, run fn warmup + steps times on the current stream;
+    returns (mean ms per step over the whole timed region, per-step ms list)."""
+    import torch
+
+    settle(fn)
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
@@ -535,6 +557,7 @@ def main(argv=None) -> int:
                      "frac": round(kernel_gbs / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "algorithmic_bytes_per_launch": head["bytes"], "launch_ms_mean": head["launch_ms_mean"]},
         "cpu_baseline": cpu,
+        "settle_s": SETTLE_S,
         "step_ms_p50": head.get("ms_p50"),
         "step_ms_p99": head.get("ms_p99"),
         "configs": configs,

@@ -28,8 +28,9 @@
 //     each workgroup, and the association is fixed, so float results are
 //     deterministic for a given (T, R, B).
 //   * Intra-block global scan (Algorithm 5): each element becomes
-//     P(i - 1) (+) wave prefix (+) row prefix (+) lane prefix (+) its in-lane
-//     scan value, and is stored once, coalesced.
+//     (P(i - 1) (+) (wave prefix (+) row prefix (+) lane prefix)) (+) its
+//     in-lane scan value -- the block prefix joins each lane-row once, then
+//     its elements -- and is stored once, coalesced.
 //
 // Forward progress: all B workgroups must be resident at once (Section 5.1
 // notes the deadlock otherwise); the host caps B by the occupancy limit.  A
@@ -304,12 +305,14 @@ __global__ void __launch_bounds__(T) scan_kernel(ScanArgs a)
     bool p_full = false;
     uint32_t p_block_head = 0;
     uint32_t p_head[R];
-    // block-local scan values (inclusive, or exclusive for exclusive scans);
-    // segmented scans keep the value and, per row, a bit per element telling
-    // whether a segment head lies at or before it inside the block
+    // the in-lane inclusive scan values of each row and, per row, the local
+    // prefix of the lane (waves, rows and lanes before it); segmented scans
+    // keep each value's head flag as a bit of p_seen (a head lies at or
+    // before it inside the lane's vector)
     using PV = typename BaseOp::V;
     PV pe[R][E];
     uint32_t p_seen[R];
+    V p_lp[R];
     VB p_agg = BOp::identity();         // wave 0: the pending block's aggregate
     VB carry = BOp::identity();         // wave 0: P(j - B) for the pending block j
 
@@ -524,7 +527,8 @@ __global__ void __launch_bounds__(T) scan_kernel(ScanArgs a)
             }
         }
 
-        // -- 5. intra-block global scan and one coalesced store per vector, for the pending block
+        // -- 5. intra-block global scan and one coalesced store per vector, for the pending block:
+        //       the block prefix joins each row's lane prefix once, then each element
         if (have_pend) {
             V prefix;
             if constexpr (MODE == kModeBatched)  // the first block of an array starts from the identity
@@ -533,16 +537,28 @@ __global__ void __launch_bounds__(T) scan_kernel(ScanArgs a)
                 prefix = s_block_prefix[parity];
 #pragma unroll
             for (int r = 0; r < R; ++r) {
+                const V q = EOp::combine(prefix, p_lp[r]);  // everything before this lane's vector
+                V ev[E];
+#pragma unroll
+                for (int k = 0; k < E; ++k) {
+                    if constexpr (MODE == kModeSegmented)
+                        ev[k] = EOp::make(pe[r][k], (p_seen[r] >> k) & 1u);
+                    else
+                        ev[k] = pe[r][k];
+                }
                 Out out[E];
 #pragma unroll
                 for (int k = 0; k < E; ++k) {
-                    if constexpr (MODE == kModeSegmented) {
-                        const PV v = ((p_seen[r] >> k) & 1u) ? pe[r][k] : BaseOp::combine(prefix.v, pe[r][k]);
+                    V v;
+                    if (!a.exclusive)
+                        v = EOp::combine(q, ev[k]);
+                    else
+                        v = (k == 0) ? q : EOp::combine(q, ev[k - 1]);
+                    if constexpr (MODE == kModeSegmented)
                         out[k] = (a.exclusive && ((p_head[r] >> k) & 1u)) ? BaseOp::lower(BaseOp::identity())
-                                                                          : BaseOp::lower(v);
-                    } else {
-                        out[k] = BaseOp::lower(EOp::combine(prefix, pe[r][k]));
-                    }
+                                                                          : BaseOp::lower(v.v);
+                    else
+                        out[k] = BaseOp::lower(v);
                 }
                 const int64_t p = p_lane0 + int64_t(r) * ROW;
                 if (p_full) {
@@ -569,27 +585,18 @@ __global__ void __launch_bounds__(T) scan_kernel(ScanArgs a)
             for (int r = 0; r < R; ++r) {
                 p_head[r] = head[r];
                 // local prefix of this lane's row: waves before, rows before, lanes before
-                const V lp = EOp::combine(EOp::combine(wave_prefix, row_prefix[r]), lane_prefix[r]);
-                V loc[E];
-                if (!a.exclusive) {
-#pragma unroll
-                    for (int k = 0; k < E; ++k) loc[k] = EOp::combine(lp, e[r][k]);
-                } else {
-#pragma unroll
-                    for (int k = E - 1; k > 0; --k) loc[k] = EOp::combine(lp, e[r][k - 1]);
-                    loc[0] = lp;
-                }
+                p_lp[r] = EOp::combine(EOp::combine(wave_prefix, row_prefix[r]), lane_prefix[r]);
                 if constexpr (MODE == kModeSegmented) {
                     uint32_t seen = 0;
 #pragma unroll
                     for (int k = 0; k < E; ++k) {
-                        pe[r][k] = loc[k].v;
-                        seen |= (loc[k].f ? 1u : 0u) << k;
+                        pe[r][k] = e[r][k].v;
+                        seen |= (e[r][k].f ? 1u : 0u) << k;
                     }
                     p_seen[r] = seen;
                 } else {
 #pragma unroll
-                    for (int k = 0; k < E; ++k) pe[r][k] = loc[k];
+                    for (int k = 0; k < E; ++k) pe[r][k] = e[r][k];
                 }
             }
         }

@@ -92,13 +92,14 @@ def read_traffic():
 SETTLE_S = 0.15
 
 
-def settle(fn, seconds: float = SETTLE_S):
+def settle(fn, seconds: float | None = None):
     """Keep the device busy with fn for about `seconds` before any warmup or
     timing: after an idle stretch (input generation, an oracle check on the
     host) the GPU takes milliseconds to return to its working clocks, which
     a few warmup steps of a sub-millisecond kernel do not cover."""
     import torch
 
+    seconds = SETTLE_S if seconds is None else seconds
     t0 = time.perf_counter()
     while time.perf_counter() - t0 < seconds:
         for _ in range(8):
@@ -419,6 +420,7 @@ def cpu_baseline(x_host, budget_s: float):
 
 
 def main(argv=None) -> int:
+    global SETTLE_S
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
@@ -432,7 +434,10 @@ def main(argv=None) -> int:
     ap.add_argument("--serve-heavy-rate", type=float, default=20000.0,
                     help="a second, heavier trace where requests queue and batching pays")
     ap.add_argument("--serve-heavy-seconds", type=float, default=1.0)
+    ap.add_argument("--settle", type=float, default=SETTLE_S,
+                    help="seconds the device runs each measured call, untimed, before its warmup steps")
     args = ap.parse_args(argv)
+    SETTLE_S = max(0.0, args.settle)
 
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the scan is not sharded "

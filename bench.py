@@ -233,16 +233,68 @@ def bench_segmented(binding, workloads, steps, warmup):
         ms_plain, _ = time_steps(plain_all, max(2, steps // 5), 1)
         binding.lscan_check(torch.cuda.current_stream().cuda_stream)
         same = bool(torch.equal(seg_y, y)) if dtype == "int32" else None
+        # the same segmented launch captured once in a hipGraph and replayed
+        code = binding.I32 if dtype == "int32" else binding.F32
+        g = binding.lscan_graph_create_segmented(xd.data_ptr(), y.data_ptr(), n, od.data_ptr(), 4096, code,
+                                                 binding.ADD)
+        ms_graph, per_graph = time_steps(g.launch, steps, warmup)
+        g.check()
+        g.destroy()
+        graph_same = bool(torch.equal(seg_y, y))
         nbytes = n * 8
         e = rate_entry(nbytes, n, ms_seg, per)
         e.update({"n": n, "segments": 4096, "plain_4096_launches_ms": round(ms_plain, 4),
-                  "speedup_vs_plain_launches": round(ms_plain / ms_seg, 2)})
+                  "speedup_vs_plain_launches": round(ms_plain / ms_seg, 2),
+                  "graph": rate_entry(nbytes, n, ms_graph, per_graph),
+                  "graph_speedup_vs_plain_launches": round(ms_plain / ms_graph, 2),
+                  "graph_bit_equal_to_eager": graph_same})
         if same is not None:
             e["bit_equal_to_plain_launches"] = same
         out[f"segmented_4096_{dtype}_add"] = e
         del xd, y, seg_y, views, od
         torch.cuda.empty_cache()
     return out
+
+
+def cpu_parallel_scan(x, repeats: int = 3):
+    """Context, not the oracle: a two-pass chunked scan over all host cores
+    (per-chunk totals, a scan of the totals, per-chunk scans with their
+    offsets; numpy releases the interpreter lock inside each pass), the
+    analogue of a multi-core library scan on the CPU."""
+    import numpy as np
+    from concurrent.futures import ThreadPoolExecutor
+
+    threads = len(os.sched_getaffinity(0))
+    n = x.shape[0]
+    y = np.empty_like(x)
+    bounds = np.linspace(0, n, threads + 1).astype(np.int64)
+    times = []
+    with ThreadPoolExecutor(threads) as ex:
+        for _ in range(repeats):
+            t0 = time.perf_counter()
+            totals = list(ex.map(lambda k: x[bounds[k]:bounds[k + 1]].sum(dtype=x.dtype), range(threads)))
+            offs = np.concatenate([[0], np.cumsum(np.array(totals, dtype=x.dtype), dtype=x.dtype)[:-1]])
+
+            def chunk(k):
+                seg = y[bounds[k]:bounds[k + 1]]
+                np.cumsum(x[bounds[k]:bounds[k + 1]], out=seg)
+                seg += x.dtype.type(offs[k])
+
+            list(ex.map(chunk, range(threads)))
+            times.append(time.perf_counter() - t0)
+    t = statistics.median(times)
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "")
+    except OSError:
+        pass
+    nbytes = 2 * n * x.dtype.itemsize
+    ok = bool(y[-1] == x.sum(dtype=x.dtype)) if n else True
+    return {"value": round(nbytes / t / 1e9, 3), "unit": "GB/s", "threads": threads, "cpu_model": model,
+            "last_equals_total": ok,
+            "ms": round(t * 1e3, 2), "kind": "two-pass chunked scan (numpy, threads)",
+            "sample": f"the full int32 add N=2^{int(np.log2(n))} array, median of {repeats}"}
 
 
 def bench_latency(binding, workloads, steps):
@@ -529,6 +581,8 @@ def main(argv=None) -> int:
 
     cpu = None
     if not args.no_cpu:
+        log("CPU parallel scan (context)")
+        configs["cpu_parallel_scan_context"] = cpu_parallel_scan(x)
         log(f"CPU oracle baseline (~{args.cpu_seconds:.0f} s)")
         cpu = cpu_baseline(x, args.cpu_seconds)
         cpu["cores_available"] = len(os.sched_getaffinity(0))

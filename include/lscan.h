@@ -62,6 +62,10 @@ typedef enum { LSCAN_ADD = 0, LSCAN_MAX = 1, LSCAN_MIN = 2 } lscan_op;
 
 /* flags */
 #define LSCAN_F_COMPENSATED 0x1u /* F32/BF16 add: carry a TwoSum error term */
+/* LSCAN_F_DETERMINISTIC asks for a fixed association of the float sums; it
+ * is accepted everywhere and always met: both hand-offs fold in a fixed
+ * order, so one tile shape and grid give the same bits on every run. */
+#define LSCAN_F_DETERMINISTIC 0x2u
 #define LSCAN_F_EXCLUSIVE 0x4u   /* lscan_segmented only: exclusive scan */
 
 typedef int32_t lscan_status;
@@ -82,7 +86,7 @@ typedef int32_t lscan_status;
  *   y      device pointer, n elements of the output type (F32 for BF16)
  *   n      element count, n >= 0; n == 0 is a no-op returning LSCAN_OK
  *   flags  0 or LSCAN_F_COMPENSATED (F32/BF16 with LSCAN_ADD only, else
- *          LSCAN_ERR_UNSUPPORTED)
+ *          LSCAN_ERR_UNSUPPORTED), optionally | LSCAN_F_DETERMINISTIC
  * Float add results depend on the association fixed by the launch
  * parameters; for a fixed parameter set they are deterministic.
  */

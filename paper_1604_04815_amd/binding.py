@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(PKG, "liblscan.so")
 I32, I64, F32, BF16 = 0, 1, 2, 3
 ADD, MAX, MIN = 0, 1, 2
 F_COMPENSATED = 0x1
+F_DETERMINISTIC = 0x2
 F_EXCLUSIVE = 0x4
 
 OK, PENDING = 0, 1

@@ -211,7 +211,7 @@ lscan_status make_request(int mode, const void* x, void* y, int64_t n, const int
                           const lscan_array* arrays, int64_t num_arrays, int dt, int op, uint32_t flags,
                           bool exclusive, const lscan_params* p, Request* r)
 {
-    const uint32_t allowed = (mode == kModePlain) ? LSCAN_F_COMPENSATED : (LSCAN_F_COMPENSATED | LSCAN_F_EXCLUSIVE);
+    const uint32_t allowed = LSCAN_F_COMPENSATED | LSCAN_F_DETERMINISTIC | (mode == kModePlain ? 0u : LSCAN_F_EXCLUSIVE);
     if (flags & ~allowed) return LSCAN_ERR_INVALID_ARG;
     const int oc = opcode_of(dt, op, flags);
     if (oc == -1) return LSCAN_ERR_INVALID_ARG;
@@ -579,7 +579,7 @@ lscan_status run(const Request& r, void* stream_ptr)
 
 lscan_status validate_request(const void* x, const void* y, int64_t n, int dt, int op, uint32_t flags)
 {
-    if (flags & ~(LSCAN_F_COMPENSATED | LSCAN_F_EXCLUSIVE)) return LSCAN_ERR_INVALID_ARG;
+    if (flags & ~(LSCAN_F_COMPENSATED | LSCAN_F_DETERMINISTIC | LSCAN_F_EXCLUSIVE)) return LSCAN_ERR_INVALID_ARG;
     const int oc = opcode_of(dt, op, flags);
     if (oc == -1) return LSCAN_ERR_INVALID_ARG;
     if (oc == -2) return LSCAN_ERR_UNSUPPORTED;

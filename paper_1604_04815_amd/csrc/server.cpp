@@ -66,7 +66,9 @@ struct StreamSlot {
 
 uint64_t batch_key(const lscan_request& r)
 {
-    return uint64_t(uint32_t(r.dt)) | (uint64_t(uint32_t(r.op)) << 8) | (uint64_t(r.flags) << 16);
+    // every launch is deterministic, so that flag does not split batches
+    const uint32_t f = r.flags & ~LSCAN_F_DETERMINISTIC;
+    return uint64_t(uint32_t(r.dt)) | (uint64_t(uint32_t(r.op)) << 8) | (uint64_t(f) << 16);
 }
 
 }  // namespace

@@ -190,3 +190,13 @@ def test_params_kinds(lib):
     assert lib.lscan_get_params(binding.F32, binding.ADD, 0, 3, ctypes.byref(p)) == binding.ERR_INVALID_ARG
     assert lib.lscan_get_params(binding.I32, binding.MAX, binding.F_COMPENSATED, 0,
                                 ctypes.byref(p)) == binding.ERR_UNSUPPORTED
+
+
+def test_deterministic_flag_is_accepted(lib):
+    # n == 0 is a no-op after validation, so these reach the flag check only
+    for flags in (binding.F_DETERMINISTIC, binding.F_DETERMINISTIC | binding.F_COMPENSATED):
+        assert lib.lscan_inclusive(FAKE_X, FAKE_Y, 0, binding.F32, binding.ADD, flags, None) == binding.OK
+    assert lib.lscan_inclusive(FAKE_X, FAKE_Y, 0, binding.I32, binding.ADD, 0x8, None) == binding.ERR_INVALID_ARG
+    assert lib.lscan_segmented(None, None, 0, None, 0, binding.I32, binding.MAX,
+                               binding.F_DETERMINISTIC | binding.F_EXCLUSIVE, None) == binding.OK
+

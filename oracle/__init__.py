@@ -91,6 +91,8 @@ class Oracle:
         lib.oracle_scan.restype = i32
         lib.oracle_segscan.argtypes = [vp, vp, vp, vp, i64, i32, i32, i32]
         lib.oracle_segscan.restype = i32
+        lib.oracle_compact.argtypes = [vp, vp, i64, i32, vp]
+        lib.oracle_compact.restype = i64
         self.lib = lib
         self.path = path
 
@@ -133,6 +135,24 @@ class Oracle:
         return (y, absum) if absum is not None else y
 
 
+    def compact(self, x, keep=None):
+        """Stream compaction: the elements of ``x`` (1-D numpy array of 2-, 4-
+        or 8-byte items) whose ``keep`` flag (uint8) is non-zero, or with
+        ``keep`` None whose bytes are not all zero, in order."""
+        x = np.ascontiguousarray(x)
+        n = x.shape[0]
+        if keep is not None:
+            keep = np.ascontiguousarray(keep, dtype=np.uint8)
+            if keep.shape[0] != n:
+                raise ValueError("keep must have one flag per element")
+        out = np.zeros(n, dtype=x.dtype)
+        count = self.lib.oracle_compact(x.ctypes.data, keep.ctypes.data if keep is not None else None,
+                                        n, x.dtype.itemsize, out.ctypes.data)
+        if count < 0:
+            raise ValueError(f"oracle_compact rejected its arguments (rc={count})")
+        return out[:count]
+
+
 _default = None
 
 
@@ -154,6 +174,10 @@ def scan(x, dtype="int32", op="add", exclusive=False, with_absum=False, out=None
 
 def segscan(x, offsets, dtype="int32", op="add", exclusive=False, with_absum=False):
     return default().segscan(x, offsets, dtype, op, exclusive, with_absum)
+
+
+def compact(x, keep=None):
+    return default().compact(x, keep)
 
 
 def float_error_ratio(y, y64, absum):

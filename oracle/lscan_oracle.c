@@ -273,3 +273,40 @@ int oracle_segscan(const void *x, void *y, double *absum, const int64_t *off,
     }
     return OR_OK;
 }
+
+/* ------------------------------------------------------------------ */
+/* stream compaction (a consumer of the scan)                          */
+/* ------------------------------------------------------------------ */
+
+/*
+ * oracle_compact: the selection that a +-scan of 0/1 flags drives, one of
+ * the uses of the scan the paper lists (Section 1: sorting, graph
+ * algorithms): every element x[i] of elem_size bytes whose keep[i] is not
+ * zero -- or, with keep == NULL, whose bytes are not all zero -- is copied,
+ * in index order, to out.  Returns the number copied, or -1 for bad
+ * arguments.  The position of a kept x[i] in out is the number of kept
+ * elements before it, i.e. the exclusive +-scan of the flags at i.
+ */
+int64_t oracle_compact(const void *x, const uint8_t *keep, int64_t n,
+                       int elem_size, void *out)
+{
+    if (n < 0 || (elem_size != 2 && elem_size != 4 && elem_size != 8))
+        return -1;
+    const unsigned char *src = (const unsigned char *)x;
+    unsigned char *dst = (unsigned char *)out;
+    int64_t count = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        const unsigned char *e = src + i * elem_size;
+        int take = 0;
+        if (keep) {
+            take = keep[i] != 0;
+        } else {
+            for (int b = 0; b < elem_size; ++b) take |= e[b] != 0;
+        }
+        if (take) {
+            memcpy(dst + count * elem_size, e, (size_t)elem_size);
+            ++count;
+        }
+    }
+    return count;
+}

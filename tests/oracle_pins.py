@@ -300,8 +300,35 @@ def check_segmented(orc, seed=13):
             assert a[lo] == abs(float(xf[lo]))
 
 
+def check_compact(orc, seed=17):
+    """Stream compaction against closed forms and numpy's boolean indexing."""
+    g = np.random.default_rng(seed)
+    n = 1000
+    for dt in (np.int32, np.int64, np.float32, np.uint16):
+        x = g.integers(1, 1 << 15, n).astype(dt)
+        # closed forms: keep everything / nothing / every other element
+        assert np.array_equal(orc.compact(x, np.ones(n, np.uint8)), x), dt
+        assert orc.compact(x, np.zeros(n, np.uint8)).shape[0] == 0, dt
+        alt = (np.arange(n) % 2 == 0).astype(np.uint8)
+        assert np.array_equal(orc.compact(x, alt), x[0::2]), dt
+        # random flags (any non-zero byte keeps): numpy boolean indexing
+        keep = g.integers(0, 4, n).astype(np.uint8)
+        assert np.array_equal(orc.compact(x, keep), x[keep != 0]), dt
+    # distinct values 0..n-1: the kept values are the kept indices, in order
+    idx = np.arange(n, dtype=np.int64)
+    keep = (g.random(n) < 0.3).astype(np.uint8)
+    assert np.array_equal(orc.compact(idx, keep), np.flatnonzero(keep))
+    # no flags: keep the elements whose bits are not all zero (-0.0 is kept)
+    xf = np.array([0.0, -0.0, 1.5, 0.0, -2.0, 0.0], dtype=np.float32)
+    assert np.array_equal(orc.compact(xf).view(np.uint32), np.array([-0.0, 1.5, -2.0], np.float32).view(np.uint32))
+    xi = g.integers(-3, 4, n).astype(np.int64)
+    assert np.array_equal(orc.compact(xi), xi[xi != 0])
+    # empty input
+    assert orc.compact(np.zeros(0, np.int32), np.zeros(0, np.uint8)).shape[0] == 0
+
+
 ALL_CHECKS = (check_golden, check_closed_forms, check_brute_force, check_invariants,
-              check_cancellation, check_segmented)
+              check_cancellation, check_segmented, check_compact)
 
 
 def failing_checks(orc):

@@ -33,6 +33,11 @@ MUTANTS = [
     ("float_max_identity", "float acc = (op == OR_MAX) ? -INFINITY : INFINITY;", "float acc = (op == OR_MAX) ? 0.0f : INFINITY;", 0),
     ("seg_offset_bytes", "(const char *)x + lo * isz", "(const char *)x + lo", 0),
     ("seg_len_short", "hi - lo, dtype, op,", "hi - lo - (hi > lo), dtype, op,", 0),
+    ("compact_keep_inverted", "take = keep[i] != 0;", "take = keep[i] == 0;", 0),
+    ("compact_last_dropped", "for (int64_t i = 0; i < n; ++i) {\n        const unsigned char *e", "for (int64_t i = 0; i + 1 < n; ++i) {\n        const unsigned char *e", 0),
+    ("compact_first_byte_only", "for (int b = 0; b < elem_size; ++b) take |= e[b] != 0;", "take = e[0] != 0;", 0),
+    ("compact_stride_one", "const unsigned char *e = src + i * elem_size;", "const unsigned char *e = src + i;", 0),
+    ("compact_dst_not_advanced", "memcpy(dst + count * elem_size, e, (size_t)elem_size);", "memcpy(dst, e, (size_t)elem_size);", 0),
     ("excl_float_stale_abs", "if (absum) absum[j] = a;\n        }\n        neumaier_add(&s, &c, v);\n        a += fabs(v);\n        if (!exclusive) {\n            y64[j] = s + c;",
      "if (absum) absum[j] = a + fabs(v);\n        }\n        neumaier_add(&s, &c, v);\n        a += fabs(v);\n        if (!exclusive) {\n            y64[j] = s + c;", 0),
 ]

@@ -20,7 +20,8 @@ Prints ONE JSON line on stdout.  Besides the contract keys it carries
                 and compensated, bf16 -> float32, a 4096-array segmented scan
                 against 4096 plain launches, the 2^20 latency case, and the
                 paper's serial prefix chain at 2^20 and 2^28 against the
-                default window hand-off), plus a device copy of the same size.
+                default window hand-off, stream compaction of the headline
+                array), plus a device copy of the same size.
 
 Before the warmup steps of every measurement the device runs the same call
 for about SETTLE_S seconds (untimed), so that clocks have left the idle state
@@ -254,6 +255,38 @@ def bench_segmented(binding, workloads, steps, warmup):
         del xd, y, seg_y, views, od
         torch.cuda.empty_cache()
     return out
+
+
+def bench_compact(binding, x_host, steps, warmup, seed):
+    """Stream compaction of the headline array with half of the items kept
+    (independent random keep bytes): algorithmic bytes are N items and N
+    flags read, the kept items written and the 8-byte count."""
+    import numpy as np
+    import torch
+
+    n = x_host.shape[0]
+    g = np.random.default_rng(seed)
+    keep_host = (g.random(n) < 0.5).astype(np.uint8)
+    xd = to_device(x_host, "int32")
+    kd = torch.from_numpy(keep_host).to("cuda")
+    out = torch.empty_like(xd)
+    count = torch.empty(1, dtype=torch.int64, device="cuda")
+    ms, per = time_steps(lambda: binding.compact(xd, kd, out=out, count=count), steps, warmup)
+    binding.lscan_check(torch.cuda.current_stream().cuda_stream)
+    info = binding.lscan_last_launch()
+    kept = int(count.item())
+    nbytes = 4 * n + n + 4 * kept + 8
+    e = rate_entry(nbytes, n, ms, per)
+    mask = kd.bool()
+    ms_torch, _ = time_steps(lambda: torch.masked_select(xd, mask), max(2, steps // 2), 1)
+    ref = torch.masked_select(xd, mask)
+    e.update({"n": n, "kept": kept, "bytes": nbytes, "grid": info.grid, "block_threads": info.block_threads,
+              "tile_elems": info.tile_elems, "equal_to_torch_masked_select": bool(torch.equal(out[:kept], ref)),
+              "torch_masked_select_ms": round(ms_torch, 5),
+              "speedup_vs_torch_masked_select": round(ms_torch / ms, 2)})
+    del xd, kd, out, mask, ref
+    torch.cuda.empty_cache()
+    return e
 
 
 def cpu_parallel_scan(x, repeats: int = 3):
@@ -564,6 +597,11 @@ def main(argv=None) -> int:
                     f"{hv['serial_plain']['p50_us']}/{hv['serial_plain']['p99_us']} us")
         log("latency: int32 add N=2^20")
         configs["int32_add_2p20_latency"] = bench_latency(binding, workloads, args.steps)
+        log("stream compaction: int32 N=2^28, half kept")
+        configs["compact_int32_2p28_half"] = bench_compact(binding, x, args.steps, args.warmup,
+                                                           workloads.seed_for(5, 1))
+        log(f"  {configs['compact_int32_2p28_half']['gbs']} GB/s, "
+            f"{configs['compact_int32_2p28_half']['speedup_vs_torch_masked_select']}x torch.masked_select")
         log("the paper's prefix chain: int32 add N=2^20 and N=2^28")
         configs["int32_add_2p20_chain"] = bench_chain(
             binding, workloads.uniform_int(1 << 20, -1000, 1000, workloads.seed_for(0)), 10)

@@ -190,10 +190,13 @@ typedef struct {
 int32_t lscan_num_tile_shapes(void);
 lscan_status lscan_tile_shape(int32_t idx, lscan_params *out);
 
-/* Kernel kinds for lscan_get_params / lscan_set_params. */
+/* Kernel kinds for lscan_get_params / lscan_set_params (for
+ * LSCAN_KIND_COMPACT only the item width of dt matters: op and flags are
+ * ignored). */
 #define LSCAN_KIND_PLAIN 0
 #define LSCAN_KIND_SEGMENTED 1
 #define LSCAN_KIND_BATCHED 2
+#define LSCAN_KIND_COMPACT 3
 
 /* Default parameters for (dt, op, flags & LSCAN_F_COMPENSATED) and a kernel
  * kind; set replaces them (e.g. from an autotuner). */
@@ -220,6 +223,36 @@ lscan_status lscan_batched_with_params(const lscan_array *arrays,
                                        int64_t count, lscan_dtype dt,
                                        lscan_op op, uint32_t flags,
                                        const lscan_params *p, void *stream);
+
+/*
+ * Stream compaction, the selection a +-scan of 0/1 flags drives (the paper
+ * lists sorting and graph algorithms among the uses of the scan, Section 1):
+ * every x[i] whose keep[i] is non-zero -- or, with keep == NULL, whose bits
+ * are not all zero (so -0.0f is kept) -- is written, in index order, to out,
+ * and the number written to *count.  One persistent launch on the scan's
+ * machinery: the flags are counted and scanned per block, block counts are
+ * handed forward through the flag slots, and each block scatters its kept
+ * items to out[number kept before them].
+ *   x      device pointer, n items of dt (LSCAN_I32, LSCAN_F32: 4 bytes,
+ *          moved as bits; LSCAN_I64: 8 bytes; LSCAN_BF16:
+ *          LSCAN_ERR_UNSUPPORTED)
+ *   keep   device pointer to n bytes, or NULL
+ *   out    device pointer with room for n items; only out[0, *count) is
+ *          written; out may not overlap x, keep or count
+ *          (LSCAN_ERR_INVALID_ARG)
+ *   count  device pointer to one int64_t, 8-byte aligned; written by the
+ *          launch (n == 0: set to 0 by a memset on the stream)
+ * Results are exact (no arithmetic on the items).  lscan_compact_with_params
+ * takes a tile shape and groups per CU as the scans do (handoff must be
+ * LSCAN_HANDOFF_WINDOW, else LSCAN_ERR_UNSUPPORTED).
+ */
+lscan_status lscan_compact(const void *x, const uint8_t *keep, void *out,
+                           int64_t *count, int64_t n, lscan_dtype dt,
+                           void *stream);
+lscan_status lscan_compact_with_params(const void *x, const uint8_t *keep,
+                                       void *out, int64_t *count, int64_t n,
+                                       lscan_dtype dt, const lscan_params *p,
+                                       void *stream);
 
 /*
  * Graph-captured launches.  lscan_graph_create_* prepares one segmented or

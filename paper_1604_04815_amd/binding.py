@@ -95,6 +95,8 @@ SIGNATURES = {
     "lscan_batched": ([ctypes.POINTER(Array), _i64, _i32, _i32, _u32, _vp], _i32),
     "lscan_batched_with_params": ([ctypes.POINTER(Array), _i64, _i32, _i32, _u32, ctypes.POINTER(Params), _vp],
                                   _i32),
+    "lscan_compact": ([_vp, _vp, _vp, _vp, _i64, _i32, _vp], _i32),
+    "lscan_compact_with_params": ([_vp, _vp, _vp, _vp, _i64, _i32, ctypes.POINTER(Params), _vp], _i32),
     "lscan_graph_create_segmented": ([_vp, _vp, _i64, _vp, _i64, _i32, _i32, _u32, ctypes.POINTER(Params),
                                       ctypes.POINTER(_vp)], _i32),
     "lscan_graph_create_batched": ([ctypes.POINTER(Array), _i64, _i32, _i32, _u32, ctypes.POINTER(Params),
@@ -254,7 +256,7 @@ def lscan_tile_shapes() -> list[tuple[int, int]]:
     return out
 
 
-KIND_PLAIN, KIND_SEGMENTED, KIND_BATCHED = 0, 1, 2
+KIND_PLAIN, KIND_SEGMENTED, KIND_BATCHED, KIND_COMPACT = 0, 1, 2, 3
 HANDOFF_WINDOW, HANDOFF_CHAIN = 0, 1
 
 
@@ -394,6 +396,36 @@ def batched(xs, op="add", exclusive=False, compensated=False, outs=None, stream=
     flags = (F_COMPENSATED if compensated else 0) | (F_EXCLUSIVE if exclusive else 0)
     lscan_batched(table, dt, OPS[op], flags, _stream(stream), params)
     return ys
+
+
+def compact(x, keep=None, out=None, count=None, stream=None, params: Params | None = None):
+    """Stream compaction on the device: the items of ``x`` whose ``keep``
+    byte (a uint8 or bool device tensor) is non-zero, or with ``keep`` None
+    whose bits are not all zero, in order.  Returns ``(out, count)``: ``out``
+    has room for every item and holds the kept ones in ``out[:count]``;
+    ``count`` is a one-element int64 device tensor (read it after the stream
+    has synchronized)."""
+    import torch
+
+    _flat(x, "x")
+    n = x.shape[0]
+    if keep is not None:
+        _flat(keep, "keep")
+        if keep.dtype not in (torch.uint8, torch.bool) or keep.shape[0] != n:
+            raise ValueError("keep must be uint8 or bool with one flag per item")
+    if out is None:
+        out = torch.empty_like(x)
+    else:
+        _flat(out, "out")
+        if out.dtype != x.dtype or out.shape[0] < n:
+            raise ValueError("out must have x's dtype and room for every item")
+    if count is None:
+        count = torch.empty(1, dtype=torch.int64, device=x.device)
+    keep_ptr = keep.data_ptr() if keep is not None else None
+    p = ctypes.byref(params) if params is not None else None
+    _check(load().lscan_compact_with_params(x.data_ptr(), keep_ptr, out.data_ptr(), count.data_ptr(), n,
+                                            dtype_code(x), p, _stream(stream)), "lscan_compact")
+    return out, count
 
 
 class Server:

@@ -18,8 +18,10 @@ struct BatchArray {
 };
 
 // Kernel flavours: one array; one array cut into segments by offsets (heads
-// inside blocks); many arrays, each starting on a block boundary.
-enum ScanMode : int { kModePlain = 0, kModeSegmented = 1, kModeBatched = 2 };
+// inside blocks); many arrays, each starting on a block boundary; stream
+// compaction (a scan of keep flags driving a scatter).
+enum ScanMode : int { kModePlain = 0, kModeSegmented = 1, kModeBatched = 2, kModeCompact = 3 };
+constexpr int kNumModes = 4;
 
 // Arguments of one persistent scan launch.
 struct ScanArgs {
@@ -41,6 +43,8 @@ struct ScanArgs {
     int32_t residency_check;  // 1: only test that all workgroups are resident at once, then exit
     int32_t chain;            // 1: the paper's prefix chain (block i waits for P(i - 1))
     uint32_t* status_host;    // optional host-visible word that also receives the timeout flag
+    const uint8_t* keep;      // compaction: one keep byte per item (null: keep non-zero items)
+    int64_t* count;           // compaction: receives the number of kept items (device)
 };
 
 using LaunchFn = hipError_t (*)(const ScanArgs&, int grid, hipStream_t);
@@ -72,7 +76,7 @@ constexpr int kShapeThreads[kNumShapes] = {256, 512, 512, 256, 1024, 1024, 512, 
 constexpr int kShapeVectors[kNumShapes] = {8, 8, 4, 16, 4, 2, 2, 4, 2, 1};
 
 // table[mode][opcode][shape]
-using KernelTable = KernelEntry[3][kNumOpCodes][kNumShapes];
+using KernelTable = KernelEntry[kNumModes][kNumOpCodes][kNumShapes];
 
 void register_i32_kernels(KernelTable& t);
 void register_i64_kernels(KernelTable& t);
@@ -86,5 +90,6 @@ void register_i32_batch_kernels(KernelTable& t);
 void register_i64_batch_kernels(KernelTable& t);
 void register_f32_batch_kernels(KernelTable& t);
 void register_bf16_batch_kernels(KernelTable& t);
+void register_compact_kernels(KernelTable& t);
 
 }  // namespace lscan

@@ -37,6 +37,7 @@ void init_table()
     register_i64_batch_kernels(g_table);
     register_f32_batch_kernels(g_table);
     register_bf16_batch_kernels(g_table);
+    register_compact_kernels(g_table);
 }
 
 const KernelTable& table()
@@ -58,8 +59,6 @@ constexpr double kResidencyWaitSeconds = 0.02;
 // Tags are 32-bit and 0 marks a never-written slot: reset a workspace well
 // before its tag counter could wrap.
 constexpr uint64_t kMaxLaunchesPerEpochRun = 0xfffffff0ull;
-
-constexpr int kNumModes = 3;
 
 struct DeviceInfo {
     int cu_count = 0;
@@ -135,6 +134,7 @@ void init_params_locked()
     for (int o = 0; o < kNumOpCodes; ++o) {
         g_params[kModeSegmented][o] = t512x8;
         g_params[kModeBatched][o] = g_params[kModePlain][o];
+        g_params[kModeCompact][o] = t512x8g2;
     }
     g_params_init = true;
 }
@@ -205,6 +205,8 @@ struct Request {
     const lscan_params* p = nullptr;
     bool empty = false;                  // nothing to do
     uint32_t* status_host = nullptr;     // optional host-visible timeout word
+    const uint8_t* keep = nullptr;       // compaction: keep flags (may be null)
+    int64_t* count = nullptr;            // compaction: device count of kept items
 };
 
 lscan_status make_request(int mode, const void* x, void* y, int64_t n, const int64_t* offsets, int64_t num_segments,
@@ -248,6 +250,53 @@ lscan_status make_request(int mode, const void* x, void* y, int64_t n, const int
     r->n = n;
     r->offsets = offsets;
     r->num_segments = num_segments;
+    r->empty = (n == 0);
+    return LSCAN_OK;
+}
+
+// Stream compaction: items of 4 (I32, F32) or 8 (I64) bytes, moved as bits;
+// the kernel-table row is the add opcode of that width.
+int compact_opcode(int dt)
+{
+    if (dt == LSCAN_I32 || dt == LSCAN_F32) return kI32Add;
+    if (dt == LSCAN_I64) return kI64Add;
+    return -1;
+}
+
+bool ranges_overlap(const void* a, int64_t abytes, const void* b, int64_t bbytes)
+{
+    const uintptr_t a0 = reinterpret_cast<uintptr_t>(a), b0 = reinterpret_cast<uintptr_t>(b);
+    return a0 < b0 + uintptr_t(bbytes) && b0 < a0 + uintptr_t(abytes);
+}
+
+lscan_status make_compact_request(const void* x, const uint8_t* keep, void* out, int64_t* count, int64_t n, int dt,
+                                  const lscan_params* p, Request* r)
+{
+    if (dt < LSCAN_I32 || dt > LSCAN_BF16) return LSCAN_ERR_INVALID_ARG;
+    const int oc = compact_opcode(dt);
+    if (oc < 0) return LSCAN_ERR_UNSUPPORTED;
+    if (n < 0 || !count || reinterpret_cast<uintptr_t>(count) % 8) return LSCAN_ERR_INVALID_ARG;
+    lscan_status st = check_params(p);
+    if (st != LSCAN_OK) return st;
+    if (p && p->handoff != LSCAN_HANDOFF_WINDOW) return LSCAN_ERR_UNSUPPORTED;
+    st = check_array(x, out, n, dt);
+    if (st != LSCAN_OK) return st;
+    const int64_t bytes = n * int64_t(in_bytes_of(dt));
+    if (n > 0) {
+        // kept items move towards the front: out may not share memory with x,
+        // the flags or the count
+        if (ranges_overlap(x, bytes, out, bytes)) return LSCAN_ERR_INVALID_ARG;
+        if (keep && ranges_overlap(keep, n, out, bytes)) return LSCAN_ERR_INVALID_ARG;
+        if (ranges_overlap(count, 8, out, bytes)) return LSCAN_ERR_INVALID_ARG;
+    }
+    r->mode = kModeCompact;
+    r->oc = oc;
+    r->p = p;
+    r->x = x;
+    r->y = out;
+    r->n = n;
+    r->keep = keep;
+    r->count = count;
     r->empty = (n == 0);
     return LSCAN_OK;
 }
@@ -515,6 +564,16 @@ lscan_status plan_locked(const Request& r, int dev, Workspace* ws_fixed, hipStre
         a.arrays = ws->desc;
         a.num_arrays = r.num_arrays;
         a.vec_ok = 1;  // decided per array in the kernel
+    } else if (r.mode == kModeCompact) {
+        // full tiles read 16-byte item vectors and E-byte flag words; the
+        // scatter writes single items
+        a.x = r.x;
+        a.y = r.y;
+        a.n = r.n;
+        a.keep = r.keep;
+        a.count = r.count;
+        a.vec_ok = (reinterpret_cast<uintptr_t>(r.x) % 16 == 0 &&
+                    reinterpret_cast<uintptr_t>(r.keep) % uintptr_t(k.elems_per_vec) == 0) ? 1 : 0;
     } else {
         const int vec_bytes = k.in_bytes * k.elems_per_vec;
         a.x = r.x;
@@ -530,7 +589,7 @@ lscan_status plan_locked(const Request& r, int dev, Workspace* ws_fixed, hipStre
     a.ctrl = ws->ctrl;
     a.spin_limit = info->spin_limit;
     a.exclusive = r.exclusive ? 1 : 0;
-    a.chain = (prm.handoff == LSCAN_HANDOFF_CHAIN) ? 1 : 0;
+    a.chain = (r.mode != kModeCompact && prm.handoff == LSCAN_HANDOFF_CHAIN) ? 1 : 0;
     a.residency_check = 0;
     a.status_host = r.status_host;
 
@@ -826,8 +885,8 @@ lscan_status lscan_tile_shape(int32_t idx, lscan_params* out)
 lscan_status lscan_get_params(lscan_dtype dt, lscan_op op, uint32_t flags, int32_t kind, lscan_params* out)
 {
     if (!out || kind < 0 || kind >= kNumModes) return LSCAN_ERR_INVALID_ARG;
-    const int oc = opcode_of(dt, op, flags & LSCAN_F_COMPENSATED);
-    if (oc == -1) return LSCAN_ERR_INVALID_ARG;
+    const int oc = (kind == kModeCompact) ? compact_opcode(dt) : opcode_of(dt, op, flags & LSCAN_F_COMPENSATED);
+    if (oc == -1) return (kind == kModeCompact && dt == LSCAN_BF16) ? LSCAN_ERR_UNSUPPORTED : LSCAN_ERR_INVALID_ARG;
     if (oc == -2) return LSCAN_ERR_UNSUPPORTED;
     std::lock_guard<std::mutex> lock(g_mu);
     init_params_locked();
@@ -842,9 +901,10 @@ lscan_status lscan_get_params(lscan_dtype dt, lscan_op op, uint32_t flags, int32
 lscan_status lscan_set_params(lscan_dtype dt, lscan_op op, uint32_t flags, int32_t kind, const lscan_params* p)
 {
     if (!p || kind < 0 || kind >= kNumModes) return LSCAN_ERR_INVALID_ARG;
-    const int oc = opcode_of(dt, op, flags & LSCAN_F_COMPENSATED);
-    if (oc == -1) return LSCAN_ERR_INVALID_ARG;
+    const int oc = (kind == kModeCompact) ? compact_opcode(dt) : opcode_of(dt, op, flags & LSCAN_F_COMPENSATED);
+    if (oc == -1) return (kind == kModeCompact && dt == LSCAN_BF16) ? LSCAN_ERR_UNSUPPORTED : LSCAN_ERR_INVALID_ARG;
     if (oc == -2) return LSCAN_ERR_UNSUPPORTED;
+    if (kind == kModeCompact && p->handoff != LSCAN_HANDOFF_WINDOW) return LSCAN_ERR_UNSUPPORTED;
     const int s = shape_index(p->block_threads, p->vectors_per_lane);
     if (s < 0) return LSCAN_ERR_UNSUPPORTED;
     if (p->groups_per_cu <= 0) return LSCAN_ERR_INVALID_ARG;
@@ -853,6 +913,25 @@ lscan_status lscan_set_params(lscan_dtype dt, lscan_op op, uint32_t flags, int32
     init_params_locked();
     g_params[kind][oc] = Params{s, p->groups_per_cu, p->handoff};
     return LSCAN_OK;
+}
+
+lscan_status lscan_compact_with_params(const void* x, const uint8_t* keep, void* out, int64_t* count, int64_t n,
+                                       lscan_dtype dt, const lscan_params* p, void* stream)
+{
+    Request r;
+    lscan_status st = make_compact_request(x, keep, out, count, n, dt, p, &r);
+    if (st != LSCAN_OK) return st;
+    if (r.empty) {  // nothing is launched: the count is zero
+        hipError_t e = hipMemsetAsync(count, 0, sizeof(int64_t), static_cast<hipStream_t>(stream));
+        return e == hipSuccess ? LSCAN_OK : device_error(e);
+    }
+    return run(r, stream);
+}
+
+lscan_status lscan_compact(const void* x, const uint8_t* keep, void* out, int64_t* count, int64_t n, lscan_dtype dt,
+                           void* stream)
+{
+    return lscan_compact_with_params(x, keep, out, count, n, dt, nullptr, stream);
 }
 
 lscan_status lscan_last_launch(lscan_launch_info* out)

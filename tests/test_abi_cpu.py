@@ -185,9 +185,10 @@ def test_graph_validation(lib):
 
 def test_params_kinds(lib):
     p = binding.Params()
-    for kind in (binding.KIND_PLAIN, binding.KIND_SEGMENTED, binding.KIND_BATCHED):
+    for kind in (binding.KIND_PLAIN, binding.KIND_SEGMENTED, binding.KIND_BATCHED, binding.KIND_COMPACT):
         assert lib.lscan_get_params(binding.F32, binding.ADD, binding.F_COMPENSATED, kind, ctypes.byref(p)) == 0
-    assert lib.lscan_get_params(binding.F32, binding.ADD, 0, 3, ctypes.byref(p)) == binding.ERR_INVALID_ARG
+    assert lib.lscan_get_params(binding.F32, binding.ADD, 0, 4, ctypes.byref(p)) == binding.ERR_INVALID_ARG
+    assert lib.lscan_get_params(binding.F32, binding.ADD, 0, -1, ctypes.byref(p)) == binding.ERR_INVALID_ARG
     assert lib.lscan_get_params(binding.I32, binding.MAX, binding.F_COMPENSATED, 0,
                                 ctypes.byref(p)) == binding.ERR_UNSUPPORTED
 
@@ -199,4 +200,39 @@ def test_deterministic_flag_is_accepted(lib):
     assert lib.lscan_inclusive(FAKE_X, FAKE_Y, 0, binding.I32, binding.ADD, 0x8, None) == binding.ERR_INVALID_ARG
     assert lib.lscan_segmented(None, None, 0, None, 0, binding.I32, binding.MAX,
                                binding.F_DETERMINISTIC | binding.F_EXCLUSIVE, None) == binding.OK
+
+
+def test_compact_validation(lib):
+    cnt = FAKE_Y + (1 << 24)  # aligned, never dereferenced
+    # bf16 items are not supported; bad enum is invalid
+    assert lib.lscan_compact(FAKE_X, None, FAKE_Y, cnt, 8, binding.BF16, None) == binding.ERR_UNSUPPORTED
+    assert lib.lscan_compact(FAKE_X, None, FAKE_Y, cnt, 8, 9, None) == binding.ERR_INVALID_ARG
+    # count missing or misaligned, negative n
+    assert lib.lscan_compact(FAKE_X, None, FAKE_Y, None, 8, binding.I32, None) == binding.ERR_INVALID_ARG
+    assert lib.lscan_compact(FAKE_X, None, FAKE_Y, cnt + 4, 8, binding.I32, None) == binding.ERR_INVALID_ARG
+    assert lib.lscan_compact(FAKE_X, None, FAKE_Y, cnt, -1, binding.I32, None) == binding.ERR_INVALID_ARG
+    # out may not overlap x (not even exactly), the flags or the count
+    assert lib.lscan_compact(FAKE_X, None, FAKE_X, cnt, 8, binding.I32, None) == binding.ERR_INVALID_ARG
+    assert lib.lscan_compact(FAKE_X, None, FAKE_X + 16, cnt, 8, binding.I64, None) == binding.ERR_INVALID_ARG
+    assert lib.lscan_compact(FAKE_X, FAKE_Y + 4, FAKE_Y, cnt, 64, binding.I32, None) == binding.ERR_INVALID_ARG
+    assert lib.lscan_compact(FAKE_X, None, FAKE_Y, FAKE_Y + 8, 8, binding.I32, None) == binding.ERR_INVALID_ARG
+    # the chain hand-off is not offered for compaction; bad shapes as for scans
+    chain = binding.Params(0, 0, 0, binding.HANDOFF_CHAIN)
+    assert lib.lscan_compact_with_params(FAKE_X, None, FAKE_Y, cnt, 8, binding.I32, ctypes.byref(chain),
+                                         None) == binding.ERR_UNSUPPORTED
+    bad = binding.Params(192, 3, 1, 0)
+    assert lib.lscan_compact_with_params(FAKE_X, None, FAKE_Y, cnt, 8, binding.I32, ctypes.byref(bad),
+                                         None) == binding.ERR_UNSUPPORTED
+
+
+def test_compact_params_kind(lib):
+    p = binding.lscan_get_params(binding.F32, binding.MAX, 0, binding.KIND_COMPACT)
+    q = binding.lscan_get_params(binding.I32, binding.ADD, 0, binding.KIND_COMPACT)
+    assert (p.block_threads, p.vectors_per_lane, p.groups_per_cu) == (q.block_threads, q.vectors_per_lane,
+                                                                      q.groups_per_cu)
+    with pytest.raises(binding.LscanError):
+        binding.lscan_get_params(binding.BF16, binding.ADD, 0, binding.KIND_COMPACT)
+    with pytest.raises(binding.LscanError):
+        binding.lscan_set_params(binding.I64, binding.ADD, 0, binding.KIND_COMPACT,
+                                 binding.Params(q.block_threads, q.vectors_per_lane, 1, binding.HANDOFF_CHAIN))
 

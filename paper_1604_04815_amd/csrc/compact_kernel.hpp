@@ -7,7 +7,9 @@
 // scan_kernel.hpp with the flags as its input and a scatter as its fix-up:
 //   * data blocks of L = T * R * E elements, taken cyclically by B resident
 //     workgroups (Section 4); each lane holds R vectors of E elements of x
-//     and the E keep bytes beside them, read once, coalesced;
+//     and the E keep bytes beside each, read once, coalesced (the flags of a
+//     wave's rows are one span, read in 16-byte chunks per lane and handed
+//     to their lanes through LDS);
 //   * per lane and row the kept elements are counted (popcount of the
 //     flags); the counts are scanned across the wave (DPP), across rows and
 //     across waves (LDS), giving each lane-row the number of kept elements
@@ -17,7 +19,10 @@
 //     own previous P(i - B) and the B - 1 counts in between (the window
 //     hand-off of the scan), so the count carried between blocks is 64-bit;
 //   * the pending block then writes each kept element to its position; the
-//     kept elements of a wave-row land in one contiguous range of out.
+//     kept elements of a wave-row land in one contiguous range of out, so
+//     each wave stages the row in LDS at its offsets from the aligned vector
+//     below the range and writes it as whole aligned 16-byte vectors (items
+//     one by one only in the partial vectors at both ends).
 // The workgroup that resolves the last block writes the total count.
 #pragma once
 
@@ -33,19 +38,35 @@ struct CompactItem {
     static constexpr int E = 16 / int(sizeof(T));  // items per 16-byte vector
 };
 
-// The E keep bytes of one lane-row as a bit mask (bit k: item k is kept).
+// The E keep bytes of one lane-row (in LDS) as a bit mask (bit k: item k is kept).
 template <int E>
-__device__ __forceinline__ uint32_t keep_bits_vector(const uint8_t* k)
+__device__ __forceinline__ uint32_t keep_bits(const uint8_t* k)
 {
     if constexpr (E == 4) {
-        const uint32_t w = __builtin_nontemporal_load(reinterpret_cast<const uint32_t*>(k));
+        const uint32_t w = *reinterpret_cast<const uint32_t*>(k);
         return ((w & 0xffu) ? 1u : 0u) | ((w & 0xff00u) ? 2u : 0u) | ((w & 0xff0000u) ? 4u : 0u) |
                ((w & 0xff000000u) ? 8u : 0u);
     } else {
-        const uint16_t w = __builtin_nontemporal_load(reinterpret_cast<const uint16_t*>(k));
+        const uint16_t w = *reinterpret_cast<const uint16_t*>(k);
         return ((w & 0xffu) ? 1u : 0u) | ((w & 0xff00u) ? 2u : 0u);
     }
 }
+
+// Flag bytes a lane reads per load: the wave's R rows of flags are one
+// contiguous span of R * 64 * E bytes, read in chunks of up to 16 bytes per
+// lane (full-width loads even though each lane-row needs only E bytes).
+template <int C> struct FlagWord;
+template <> struct FlagWord<16> { using type = u32x4; };
+template <> struct FlagWord<8> { using type = u32x2; };
+template <> struct FlagWord<4> { using type = uint32_t; };
+template <> struct FlagWord<2> { using type = uint16_t; };
+
+template <int R, int E>
+struct FlagChunks {
+    static constexpr int C = (R * E >= 16) ? 16 : R * E;  // bytes per lane per load
+    static constexpr int N = (R * E) / C;                 // loads per lane
+    using Word = typename FlagWord<C>::type;
+};
 
 template <class T, int TT, int R>
 __global__ void __launch_bounds__(TT) compact_kernel(ScanArgs a)
@@ -69,6 +90,13 @@ __global__ void __launch_bounds__(TT) compact_kernel(ScanArgs a)
     __shared__ int32_t s_wave_total[2][NWAVE];
     __shared__ VB s_block_prefix[2];
     __shared__ int s_abort[2];
+    // per wave: one row of kept items, laid out as in out (shifted by the
+    // row's misalignment), so that it leaves in aligned 16-byte vectors
+    __shared__ __attribute__((aligned(16))) T s_stage[NWAVE][ROW + E];
+    // per wave: the keep bytes of its R rows, as read from memory
+    __shared__ __attribute__((aligned(16))) uint8_t s_flags[NWAVE][R * ROW];
+    using FC = FlagChunks<R, E>;
+    static_assert(FC::N * FC::C == R * E, "flag chunks tile the wave's flag span");
 
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
@@ -79,12 +107,16 @@ __global__ void __launch_bounds__(TT) compact_kernel(ScanArgs a)
     const uint8_t* keep = a.keep;
     const int64_t n = a.n;
 
-    // pending block: its items, keep masks and the kept count before each lane-row
+    // pending block: its items, keep masks, and per row the kept count of the
+    // block before the wave-row, before the lane inside it, and in the row
     bool have_pend = false;
     int64_t p_i = 0;
     T p_x[R][E];
     uint32_t p_bits[R];
-    int32_t p_lp[R];
+    int32_t p_row0[R];
+    int32_t p_lane[R];
+    int32_t p_rowcnt[R];
+    const bool out_vec = (reinterpret_cast<uintptr_t>(out) % 16) == 0;
     VB p_agg = 0;    // wave 0: kept items in the pending block
     VB carry = 0;    // wave 0: kept items before block (pending - B + 1)
 
@@ -98,11 +130,15 @@ __global__ void __launch_bounds__(TT) compact_kernel(ScanArgs a)
         const bool full = have_new && a.vec_ok && (tile0 + L <= n);
         T raw[R][E];
         uint32_t bits[R];
+        typename FC::Word fw[FC::N];
         if (have_new && full) {
 #pragma unroll
-            for (int r = 0; r < R; ++r) {
-                load_vector<T, E>(x + lane0 + int64_t(r) * ROW, raw[r]);
-                if (keep) bits[r] = keep_bits_vector<E>(keep + lane0 + int64_t(r) * ROW);
+            for (int r = 0; r < R; ++r) load_vector<T, E>(x + lane0 + int64_t(r) * ROW, raw[r]);
+            if (keep) {
+                const uint8_t* kw = keep + tile0 + int64_t(wave) * (R * ROW) + lane * FC::C;
+#pragma unroll
+                for (int q = 0; q < FC::N; ++q)
+                    fw[q] = __builtin_nontemporal_load(reinterpret_cast<const typename FC::Word*>(kw + q * 64 * FC::C));
             }
         }
 
@@ -132,6 +168,7 @@ __global__ void __launch_bounds__(TT) compact_kernel(ScanArgs a)
         // -- 3. counts of the new block: per lane-row, across the wave, across rows
         int32_t lane_prefix[R];
         int32_t row_prefix[R];
+        int32_t row_total[R];
         if (have_new) {
             if (!full) {  // the tail block, or unaligned pointers: item by item
 #pragma unroll
@@ -156,8 +193,16 @@ __global__ void __launch_bounds__(TT) compact_kernel(ScanArgs a)
                     for (int k = 0; k < E; ++k) m |= (raw[r][k] != T(0) ? 1u : 0u) << k;
                     bits[r] = m;
                 }
+            } else {  // the flag span through LDS: each lane then takes its rows' E bytes
+                uint8_t* sf = s_flags[wave];
+#pragma unroll
+                for (int q = 0; q < FC::N; ++q)
+                    *reinterpret_cast<typename FC::Word*>(sf + q * 64 * FC::C + lane * FC::C) = fw[q];
+                __builtin_amdgcn_wave_barrier();
+#pragma unroll
+                for (int r = 0; r < R; ++r) bits[r] = keep_bits<E>(sf + r * ROW + lane * E);
+                __builtin_amdgcn_wave_barrier();
             }
-            int32_t row_total[R];
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 const int32_t sc = wave_inclusive_scan<EOp>(int32_t(__builtin_popcount(bits[r])));
@@ -187,19 +232,50 @@ __global__ void __launch_bounds__(TT) compact_kernel(ScanArgs a)
             }
         }
 
-        // -- 5. scatter of the pending block's kept items
+        // -- 5. the pending block's kept items to out
         if (have_pend) {
             const VB base = s_block_prefix[parity];
+            T* stage = s_stage[wave];
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                const int64_t at = base + p_lp[r];
-                uint32_t m = p_bits[r];
-                int32_t before = 0;
+                const int64_t g0 = base + p_row0[r];  // first position of this wave-row's items
+                const uint32_t m = p_bits[r];
+                if (!out_vec) {  // out not 16-byte aligned: item by item
+                    int32_t before = 0;
+#pragma unroll
+                    for (int k = 0; k < E; ++k) {
+                        if ((m >> k) & 1u) out[g0 + p_lane[r] + before] = p_x[r][k];
+                        before += int32_t((m >> k) & 1u);
+                    }
+                    continue;
+                }
+                // stage the row's kept items at their offsets from the aligned
+                // vector below g0, then write whole aligned vectors (and the
+                // partial vectors at both ends item by item)
+                const int32_t shift = int32_t(g0 & int64_t(E - 1));
+                int32_t at = shift + p_lane[r];
 #pragma unroll
                 for (int k = 0; k < E; ++k) {
-                    if ((m >> k) & 1u) out[at + before] = p_x[r][k];
-                    before += int32_t((m >> k) & 1u);
+                    if ((m >> k) & 1u) stage[at] = p_x[r][k];
+                    at += int32_t((m >> k) & 1u);
                 }
+                __builtin_amdgcn_wave_barrier();
+                const int32_t span = shift + p_rowcnt[r];  // staged items occupy [shift, span)
+                T* dst = out + (g0 - shift);
+                for (int32_t c = lane * E; c < span; c += 64 * E) {
+                    if (c >= shift && c + E <= span) {
+                        T v[E];
+                        __builtin_memcpy(v, stage + c, 16);
+                        u32x4 w;
+                        __builtin_memcpy(&w, v, 16);
+                        *reinterpret_cast<u32x4*>(dst + c) = w;
+                    } else {
+#pragma unroll
+                        for (int k = 0; k < E; ++k)
+                            if (c + k >= shift && c + k < span) dst[c + k] = stage[c + k];
+                    }
+                }
+                __builtin_amdgcn_wave_barrier();
             }
         }
 
@@ -211,7 +287,9 @@ __global__ void __launch_bounds__(TT) compact_kernel(ScanArgs a)
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 p_bits[r] = bits[r];
-                p_lp[r] = wave_prefix + row_prefix[r] + lane_prefix[r];
+                p_row0[r] = wave_prefix + row_prefix[r];
+                p_lane[r] = lane_prefix[r];
+                p_rowcnt[r] = row_total[r];
 #pragma unroll
                 for (int k = 0; k < E; ++k) p_x[r][k] = raw[r][k];
             }

@@ -134,7 +134,7 @@ void init_params_locked()
     for (int o = 0; o < kNumOpCodes; ++o) {
         g_params[kModeSegmented][o] = t512x8;
         g_params[kModeBatched][o] = g_params[kModePlain][o];
-        g_params[kModeCompact][o] = t512x8g2;
+        g_params[kModeCompact][o] = t1024x4;
     }
     g_params_init = true;
 }
@@ -565,15 +565,14 @@ lscan_status plan_locked(const Request& r, int dev, Workspace* ws_fixed, hipStre
         a.num_arrays = r.num_arrays;
         a.vec_ok = 1;  // decided per array in the kernel
     } else if (r.mode == kModeCompact) {
-        // full tiles read 16-byte item vectors and E-byte flag words; the
-        // scatter writes single items
+        // full tiles read 16-byte item vectors and 16-byte flag chunks
         a.x = r.x;
         a.y = r.y;
         a.n = r.n;
         a.keep = r.keep;
         a.count = r.count;
         a.vec_ok = (reinterpret_cast<uintptr_t>(r.x) % 16 == 0 &&
-                    reinterpret_cast<uintptr_t>(r.keep) % uintptr_t(k.elems_per_vec) == 0) ? 1 : 0;
+                    reinterpret_cast<uintptr_t>(r.keep) % 16 == 0) ? 1 : 0;
     } else {
         const int vec_bytes = k.in_bytes * k.elems_per_vec;
         a.x = r.x;

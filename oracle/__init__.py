@@ -93,6 +93,8 @@ class Oracle:
         lib.oracle_segscan.restype = i32
         lib.oracle_compact.argtypes = [vp, vp, i64, i32, vp]
         lib.oracle_compact.restype = i64
+        lib.oracle_radix_offsets.argtypes = [vp, i64, i32, i32, i32, i64, vp]
+        lib.oracle_radix_offsets.restype = i64
         self.lib = lib
         self.path = path
 
@@ -153,6 +155,23 @@ class Oracle:
         return out[:count]
 
 
+    def radix_offsets(self, keys, shift, bits, block_items):
+        """Digit offsets of one radix-sort pass over ``keys`` (uint32 or
+        uint64 numpy array): an int64 array of shape (2**bits, M), entry
+        [d, b] = keys with a smaller digit + keys of digit d in earlier blocks."""
+        keys = np.ascontiguousarray(keys)
+        if keys.dtype.itemsize not in (4, 8):
+            raise TypeError("keys must have 4- or 8-byte items")
+        n = keys.shape[0]
+        m = (n + block_items - 1) // block_items
+        out = np.zeros((1 << bits) * max(m, 0), dtype=np.int64)
+        rc = self.lib.oracle_radix_offsets(keys.ctypes.data, n, keys.dtype.itemsize, shift, bits, block_items,
+                                           out.ctypes.data)
+        if rc < 0:
+            raise ValueError(f"oracle_radix_offsets rejected its arguments (rc={rc})")
+        return out.reshape(1 << bits, m)
+
+
 _default = None
 
 
@@ -178,6 +197,10 @@ def segscan(x, offsets, dtype="int32", op="add", exclusive=False, with_absum=Fal
 
 def compact(x, keep=None):
     return default().compact(x, keep)
+
+
+def radix_offsets(keys, shift, bits, block_items):
+    return default().radix_offsets(keys, shift, bits, block_items)
 
 
 def float_error_ratio(y, y64, absum):

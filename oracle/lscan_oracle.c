@@ -310,3 +310,41 @@ int64_t oracle_compact(const void *x, const uint8_t *keep, int64_t n,
     }
     return count;
 }
+
+/*
+ * oracle_radix_offsets: the digit offsets of one radix-sort pass, the other
+ * scan consumer named with sorting in the paper's introduction (Section 1).
+ * The keys (key_bytes = 4 or 8, unsigned bit patterns) are cut into blocks
+ * of block_items; digit(k) = (k >> shift) & (2^bits - 1).  For digit d and
+ * block b, out[d * M + b] (M = number of blocks) is the number of keys whose
+ * digit is smaller than d, plus the number of keys with digit d in blocks
+ * before b: where block b's first key of digit d goes in a stable
+ * partition by digit.  Returns M, or -1 for bad arguments.
+ */
+int64_t oracle_radix_offsets(const void *keys, int64_t n, int key_bytes,
+                             int shift, int bits, int64_t block_items,
+                             int64_t *out)
+{
+    if (n < 0 || (key_bytes != 4 && key_bytes != 8) || bits < 1 || bits > 8 ||
+        shift < 0 || shift + bits > 8 * key_bytes || block_items < 1)
+        return -1;
+    const int64_t m = (n + block_items - 1) / block_items;
+    const int64_t nd = (int64_t)1 << bits;
+    const uint64_t mask = (uint64_t)nd - 1;
+    for (int64_t i = 0; i < nd * m; ++i) out[i] = 0;
+    /* counts per (digit, block) */
+    for (int64_t i = 0; i < n; ++i) {
+        uint64_t k = (key_bytes == 4) ? (uint64_t)((const uint32_t *)keys)[i]
+                                      : ((const uint64_t *)keys)[i];
+        int64_t d = (int64_t)((k >> shift) & mask);
+        out[d * m + i / block_items] += 1;
+    }
+    /* exclusive running sum in digit-major order */
+    int64_t acc = 0;
+    for (int64_t i = 0; i < nd * m; ++i) {
+        int64_t c = out[i];
+        out[i] = acc;
+        acc += c;
+    }
+    return m;
+}

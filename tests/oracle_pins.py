@@ -327,8 +327,47 @@ def check_compact(orc, seed=17):
     assert orc.compact(np.zeros(0, np.int32), np.zeros(0, np.uint8)).shape[0] == 0
 
 
+def check_radix_offsets(orc, seed=19):
+    """Digit offsets against numpy (bincount per block, cumulative sums) and
+    against a stable sort by digit that uses them."""
+    g = np.random.default_rng(seed)
+    for dt, kb in ((np.uint32, 32), (np.uint64, 64)):
+        n, blk = 5000, 384
+        keys = g.integers(0, 1 << 62, n, dtype=np.uint64).astype(dt)
+        for shift, bits in ((0, 8), (kb - 8, 8), (3, 1), (kb - 5, 5)):
+            off = orc.radix_offsets(keys, shift, bits, blk)
+            nd, m = 1 << bits, (n + blk - 1) // blk
+            assert off.shape == (nd, m)
+            dig = ((keys.astype(np.uint64) >> np.uint64(shift)) & np.uint64(nd - 1)).astype(np.int64)
+            counts = np.zeros((nd, m), np.int64)
+            for b in range(m):
+                counts[:, b] = np.bincount(dig[b * blk:(b + 1) * blk], minlength=nd)
+            flat = counts.reshape(-1)
+            want = np.concatenate([[0], np.cumsum(flat)[:-1]]).reshape(nd, m)
+            assert np.array_equal(off, want), (dt, shift, bits)
+            # placing every key at its block's offset for its digit, then one
+            # past the previous key of the same digit and block, is a stable
+            # sort by digit
+            pos = np.empty(n, np.int64)
+            nxt = off.copy()
+            for i in range(n):
+                d, b = dig[i], i // blk
+                pos[i] = nxt[d, b]
+                nxt[d, b] += 1
+            placed = np.empty_like(keys)
+            placed[pos] = keys
+            assert np.array_equal(placed, keys[np.argsort(dig, kind="stable")]), (dt, shift, bits)
+    # closed forms: all keys equal -> one digit takes block offsets b * blk
+    keys = np.full(1000, 0xAB, np.uint32)
+    off = orc.radix_offsets(keys, 0, 8, 100)
+    assert np.array_equal(off[0xAB], np.arange(10) * 100)
+    assert np.all(off[:0xAB] == 0) and np.all(off[0xAB + 1:] == 1000)
+    # empty input
+    assert orc.radix_offsets(np.zeros(0, np.uint32), 0, 4, 64).shape == (16, 0)
+
+
 ALL_CHECKS = (check_golden, check_closed_forms, check_brute_force, check_invariants,
-              check_cancellation, check_segmented, check_compact)
+              check_cancellation, check_segmented, check_compact, check_radix_offsets)
 
 
 def failing_checks(orc):

@@ -38,6 +38,10 @@ MUTANTS = [
     ("compact_first_byte_only", "for (int b = 0; b < elem_size; ++b) take |= e[b] != 0;", "take = e[0] != 0;", 0),
     ("compact_stride_one", "const unsigned char *e = src + i * elem_size;", "const unsigned char *e = src + i;", 0),
     ("compact_dst_not_advanced", "memcpy(dst + count * elem_size, e, (size_t)elem_size);", "memcpy(dst, e, (size_t)elem_size);", 0),
+    ("radix_block_major", "out[d * m + i / block_items] += 1;", "out[(i / block_items) * nd + d] += 1;", 0),
+    ("radix_inclusive", "out[i] = acc;\n        acc += c;", "acc += c;\n        out[i] = acc;", 0),
+    ("radix_shift_ignored", "int64_t d = (int64_t)((k >> shift) & mask);", "int64_t d = (int64_t)(k & mask);", 0),
+    ("radix_key_truncated", ": ((const uint64_t *)keys)[i];", ": (uint64_t)((const uint32_t *)keys)[i];", 0),
     ("excl_float_stale_abs", "if (absum) absum[j] = a;\n        }\n        neumaier_add(&s, &c, v);\n        a += fabs(v);\n        if (!exclusive) {\n            y64[j] = s + c;",
      "if (absum) absum[j] = a + fabs(v);\n        }\n        neumaier_add(&s, &c, v);\n        a += fabs(v);\n        if (!exclusive) {\n            y64[j] = s + c;", 0),
 ]

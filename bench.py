@@ -21,7 +21,8 @@ Prints ONE JSON line on stdout.  Besides the contract keys it carries
                 against 4096 plain launches, the 2^20 latency case, and the
                 paper's serial prefix chain at 2^20 and 2^28 against the
                 default window hand-off, stream compaction of the headline
-                array), plus a device copy of the same size.
+                array, radix-sort digit offsets), plus a device copy of the
+                same size.
 
 Before the warmup steps of every measurement the device runs the same call
 for about SETTLE_S seconds (untimed), so that clocks have left the idle state
@@ -285,6 +286,34 @@ def bench_compact(binding, x_host, steps, warmup, seed):
               "torch_masked_select_ms": round(ms_torch, 5),
               "speedup_vs_torch_masked_select": round(ms_torch / ms, 2)})
     del xd, kd, out, mask, ref
+    torch.cuda.empty_cache()
+    return e
+
+
+def bench_radix(binding, workloads, steps, warmup):
+    """Digit offsets of one 8-bit radix-sort pass over 2^28 int32 keys in
+    blocks of 16K keys: the digit-count kernel plus the exclusive scan of the
+    2^8 x M counts.  Algorithmic bytes: the keys read once, the counts
+    written, then read and written by the scan."""
+    import torch
+
+    n, block, bits = 1 << 28, 1 << 14, 8
+    kd = to_device(workloads.full_range_int32(n, workloads.seed_for(6)), "int32")
+    m = (n + block - 1) // block
+    out = torch.empty((1 << bits) * m, dtype=torch.int64, device="cuda")
+    ms, per = time_steps(lambda: binding.radix_offsets(kd, 0, bits, block, out=out), steps, warmup)
+    binding.lscan_check(torch.cuda.current_stream().cuda_stream)
+    counts_bytes = 8 * (1 << bits) * m
+    nbytes = 4 * n + 3 * counts_bytes
+    e = rate_entry(nbytes, n, ms, per)
+    e.update({"n": n, "block_items": block, "bits": bits, "blocks": m, "bytes": nbytes,
+              "key_gbs": round(4 * n / (ms * 1e-3) / 1e9, 1),
+              "last_offset_plus_count_is_n": None})
+    # the last digit's offsets end at n
+    last = out.view(1 << bits, m)[-1, -1].item()
+    hist_last = int(((kd[(m - 1) * block:].to(torch.int64) & 0xFF) == 0xFF).sum().item())
+    e["last_offset_plus_count_is_n"] = bool(last + hist_last == n)
+    del kd, out
     torch.cuda.empty_cache()
     return e
 
@@ -602,6 +631,9 @@ def main(argv=None) -> int:
                                                            workloads.seed_for(5, 1))
         log(f"  {configs['compact_int32_2p28_half']['gbs']} GB/s, "
             f"{configs['compact_int32_2p28_half']['speedup_vs_torch_masked_select']}x torch.masked_select")
+        log("radix-sort digit offsets: 2^28 int32 keys, 8 bits, 16K-key blocks")
+        configs["radix_offsets_int32_2p28_8bit"] = bench_radix(binding, workloads, args.steps, args.warmup)
+        log(f"  {configs['radix_offsets_int32_2p28_8bit']['key_gbs']} GB/s of keys")
         log("the paper's prefix chain: int32 add N=2^20 and N=2^28")
         configs["int32_add_2p20_chain"] = bench_chain(
             binding, workloads.uniform_int(1 << 20, -1000, 1000, workloads.seed_for(0)), 10)

@@ -255,6 +255,27 @@ lscan_status lscan_compact_with_params(const void *x, const uint8_t *keep,
                                        void *stream);
 
 /*
+ * Digit offsets of one radix-sort pass, the other scan consumer (sorting is
+ * among the uses of the scan in Section 1): keys (unsigned bit patterns of
+ * 4 bytes for LSCAN_I32 / LSCAN_F32, 8 bytes for LSCAN_I64; LSCAN_BF16:
+ * LSCAN_ERR_UNSUPPORTED) are cut into M = ceil(n / block_items) blocks, and
+ *   offsets[d * M + b] = (keys whose digit is below d)
+ *                      + (keys of digit d in blocks before b),
+ * digit = (key >> shift) & (2^bits - 1): where block b's first key of digit d
+ * goes in a stable partition by digit.  A digit-count kernel writes the
+ * counts digit-major into offsets, then the single-pass exclusive scan
+ * (int64 add) turns them into offsets in place.
+ *   bits         1 .. 8; shift >= 0 and shift + bits <= key width
+ *   block_items  >= 1
+ *   offsets      device array of 2^bits * M int64, 8-byte aligned, not
+ *                overlapping keys; n == 0 writes nothing
+ */
+lscan_status lscan_radix_offsets(const void *keys, int64_t n, lscan_dtype dt,
+                                 int32_t shift, int32_t bits,
+                                 int64_t block_items, int64_t *offsets,
+                                 void *stream);
+
+/*
  * Graph-captured launches.  lscan_graph_create_* prepares one segmented or
  * batched launch (workspace, co-residency test, descriptor upload, all on a
  * private stream, synchronously) and captures it into a hipGraph that owns

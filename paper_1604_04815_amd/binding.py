@@ -96,6 +96,7 @@ SIGNATURES = {
     "lscan_batched_with_params": ([ctypes.POINTER(Array), _i64, _i32, _i32, _u32, ctypes.POINTER(Params), _vp],
                                   _i32),
     "lscan_compact": ([_vp, _vp, _vp, _vp, _i64, _i32, _vp], _i32),
+    "lscan_radix_offsets": ([_vp, _i64, _i32, _i32, _i32, _i64, _vp, _vp], _i32),
     "lscan_compact_with_params": ([_vp, _vp, _vp, _vp, _i64, _i32, ctypes.POINTER(Params), _vp], _i32),
     "lscan_graph_create_segmented": ([_vp, _vp, _i64, _vp, _i64, _i32, _i32, _u32, ctypes.POINTER(Params),
                                       ctypes.POINTER(_vp)], _i32),
@@ -426,6 +427,26 @@ def compact(x, keep=None, out=None, count=None, stream=None, params: Params | No
     _check(load().lscan_compact_with_params(x.data_ptr(), keep_ptr, out.data_ptr(), count.data_ptr(), n,
                                             dtype_code(x), p, _stream(stream)), "lscan_compact")
     return out, count
+
+
+def radix_offsets(keys, shift, bits, block_items, out=None, stream=None):
+    """Digit offsets of one radix-sort pass over the device tensor ``keys``
+    (int32 / float32 / int64, read as unsigned bit patterns): an int64 device
+    tensor of shape (2**bits, M), M = ceil(n / block_items)."""
+    import torch
+
+    _flat(keys, "keys")
+    n = keys.shape[0]
+    m = (n + block_items - 1) // block_items if n else 0
+    if out is None:
+        out = torch.empty((1 << bits) * m, dtype=torch.int64, device=keys.device)
+    else:
+        _flat(out, "out")
+        if out.dtype != torch.int64 or out.shape[0] != (1 << bits) * m:
+            raise ValueError("out must be int64 with 2**bits * M entries")
+    _check(load().lscan_radix_offsets(keys.data_ptr(), n, dtype_code(keys), shift, bits, block_items,
+                                      out.data_ptr(), _stream(stream)), "lscan_radix_offsets")
+    return out.view(1 << bits, m)
 
 
 class Server:

@@ -13,6 +13,7 @@
 #include <utility>
 
 #include "kernel_table.hpp"
+#include "radix_kernel.hpp"
 #include "lscan.h"
 #include "runtime_internal.hpp"
 
@@ -931,6 +932,46 @@ lscan_status lscan_compact(const void* x, const uint8_t* keep, void* out, int64_
                            void* stream)
 {
     return lscan_compact_with_params(x, keep, out, count, n, dt, nullptr, stream);
+}
+
+lscan_status lscan_radix_offsets(const void* keys, int64_t n, lscan_dtype dt, int32_t shift, int32_t bits,
+                                 int64_t block_items, int64_t* offsets, void* stream)
+{
+    if (dt < LSCAN_I32 || dt > LSCAN_BF16) return LSCAN_ERR_INVALID_ARG;
+    if (dt == LSCAN_BF16) return LSCAN_ERR_UNSUPPORTED;
+    const int kb = (dt == LSCAN_I64) ? 8 : 4;
+    if (n < 0 || bits < 1 || bits > 8 || shift < 0 || shift + bits > 8 * kb || block_items < 1)
+        return LSCAN_ERR_INVALID_ARG;
+    if (n == 0) return LSCAN_OK;
+    if (!keys || !offsets || reinterpret_cast<uintptr_t>(keys) % uintptr_t(kb) ||
+        reinterpret_cast<uintptr_t>(offsets) % 8)
+        return LSCAN_ERR_INVALID_ARG;
+    const int64_t m = (n - 1) / block_items + 1;
+    const int64_t digits = int64_t(1) << bits;
+    if (m > (INT64_MAX / 16) / digits) return LSCAN_ERR_INVALID_ARG;
+    const int64_t total = digits * m;
+    if (ranges_overlap(keys, n * kb, offsets, total * 8)) return LSCAN_ERR_INVALID_ARG;
+    RadixArgs a;
+    a.keys = keys;
+    a.n = n;
+    a.block_items = block_items;
+    a.num_blocks = m;
+    // enough workgroups to fill the device, each writing a run of counts per
+    // digit; the table of a workgroup stays within 32 KiB of LDS
+    const int64_t want = (m + 1023) / 1024;
+    a.group = std::max<int64_t>(1, std::min<int64_t>(want, 8192 / digits));
+    a.counts = offsets;
+    a.key_bytes = kb;
+    a.shift = shift;
+    a.bits = bits;
+    a.vec_ok = (reinterpret_cast<uintptr_t>(keys) % 16 == 0 && block_items % (16 / kb) == 0) ? 1 : 0;
+    hipError_t e = lscan::launch_digit_counts(a, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return device_error(e);
+    // the offsets: exclusive +-scan of the digit-major counts, in place
+    Request r;
+    lscan_status st = make_request(kModePlain, offsets, offsets, total, nullptr, 0, nullptr, 0, LSCAN_I64, LSCAN_ADD, 0,
+                                   true, nullptr, &r);
+    return st != LSCAN_OK ? st : run(r, stream);
 }
 
 lscan_status lscan_last_launch(lscan_launch_info* out)

@@ -236,3 +236,21 @@ def test_compact_params_kind(lib):
         binding.lscan_set_params(binding.I64, binding.ADD, 0, binding.KIND_COMPACT,
                                  binding.Params(q.block_threads, q.vectors_per_lane, 1, binding.HANDOFF_CHAIN))
 
+
+def test_radix_offsets_validation(lib):
+    off = FAKE_Y
+    f = lib.lscan_radix_offsets
+    assert f(FAKE_X, 8, binding.BF16, 0, 8, 4, off, None) == binding.ERR_UNSUPPORTED
+    assert f(FAKE_X, 8, 7, 0, 8, 4, off, None) == binding.ERR_INVALID_ARG
+    for shift, bits in ((0, 0), (0, 9), (-1, 4), (25, 8), (28, 5)):
+        assert f(FAKE_X, 8, binding.I32, shift, bits, 4, off, None) == binding.ERR_INVALID_ARG, (shift, bits)
+    assert f(FAKE_X, 8, binding.I32, 0, 8, 0, off, None) == binding.ERR_INVALID_ARG
+    assert f(FAKE_X, -1, binding.I32, 0, 8, 4, off, None) == binding.ERR_INVALID_ARG
+    assert f(FAKE_X + 2, 8, binding.I32, 0, 8, 4, off, None) == binding.ERR_INVALID_ARG
+    assert f(FAKE_X, 8, binding.I32, 0, 8, 4, off + 4, None) == binding.ERR_INVALID_ARG
+    assert f(FAKE_X, 8, binding.I32, 0, 8, 4, None, None) == binding.ERR_INVALID_ARG
+    # offsets over the keys
+    assert f(FAKE_X, 1024, binding.I32, 0, 8, 64, FAKE_X + 64, None) == binding.ERR_INVALID_ARG
+    # nothing to do
+    assert f(None, 0, binding.I32, 0, 8, 4, None, None) == binding.OK
+

@@ -22,7 +22,8 @@ from dataclasses import asdict, dataclass, field
 
 from . import binding
 
-KINDS = {"plain": binding.KIND_PLAIN, "segmented": binding.KIND_SEGMENTED, "batched": binding.KIND_BATCHED}
+KINDS = {"plain": binding.KIND_PLAIN, "segmented": binding.KIND_SEGMENTED, "batched": binding.KIND_BATCHED,
+         "compact": binding.KIND_COMPACT}
 DTYPE_CODES = {"int32": binding.I32, "int64": binding.I64, "float32": binding.F32, "bfloat16": binding.BF16}
 GROUPS = (1, 2, 3, 4, 5, 6, 8)
 
@@ -132,11 +133,12 @@ def _time(fn, reps: int, warmup: int) -> float:
     return a.elapsed_time(b) / reps
 
 
-def tune(x, op="add", compensated=False, kind="plain", offsets=None, arrays=None, reps=8, warmup=2,
+def tune(x, op="add", compensated=False, kind="plain", offsets=None, arrays=None, keep=None, reps=8, warmup=2,
          shapes=None, groups=GROUPS, verbose=False) -> Entry:
     """Time every (shape, groups) for scanning device tensor ``x`` (or the
-    batch ``arrays`` of device tensors, or ``x`` cut by ``offsets``) and
-    return the best as an Entry (not yet applied)."""
+    batch ``arrays`` of device tensors, or ``x`` cut by ``offsets``, or
+    compacting ``x`` by the ``keep`` flags) and return the best as an Entry
+    (not yet applied)."""
     import torch
 
     binding.load()
@@ -150,6 +152,7 @@ def tune(x, op="add", compensated=False, kind="plain", offsets=None, arrays=None
         y = torch.empty(x.shape[0], dtype=binding.out_dtype(x), device=x.device)
         n = int(x.shape[0])
         dtype_t = x
+    count = torch.empty(1, dtype=torch.int64, device=x.device) if kind == "compact" else None
     cands = []
     for t, r in shapes:
         for g in groups:
@@ -159,6 +162,8 @@ def tune(x, op="add", compensated=False, kind="plain", offsets=None, arrays=None
             elif kind == "segmented":
                 fn = lambda p=p: binding.segmented(x, offsets, op, compensated=compensated, out=y,  # noqa: E731
                                                    params=p)
+            elif kind == "compact":
+                fn = lambda p=p: binding.compact(x, keep, out=y, count=count, params=p)  # noqa: E731
             else:
                 fn = lambda p=p: binding.batched(xs, op, compensated=compensated, outs=ys,  # noqa: E731
                                                  params=p)
@@ -177,7 +182,13 @@ def tune(x, op="add", compensated=False, kind="plain", offsets=None, arrays=None
     best = pick_best(cands)
     in_bytes = 2 if dtype_t.dtype == torch.bfloat16 else dtype_t.element_size()
     out_bytes = 4 if dtype_t.dtype == torch.bfloat16 else dtype_t.element_size()
-    gbs = n * (in_bytes + out_bytes) / (best.ms * 1e-3) / 1e9
+    if kind == "compact":  # items and flags read, the kept items written
+        fn()
+        torch.cuda.synchronize()
+        kept = int(count.item())
+        gbs = (n * (in_bytes + (1 if keep is not None else 0)) + kept * out_bytes) / (best.ms * 1e-3) / 1e9
+    else:
+        gbs = n * (in_bytes + out_bytes) / (best.ms * 1e-3) / 1e9
     dtype_name = {v: k for k, v in DTYPE_CODES.items()}[binding.dtype_code(dtype_t)]
     return Entry(device=torch.cuda.get_device_name(), dtype=dtype_name, op=op, compensated=bool(compensated),
                  kind=kind, size_bucket=size_bucket(n), block_threads=best.block_threads,

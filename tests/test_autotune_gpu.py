@@ -38,3 +38,21 @@ def test_tune_batched_and_segmented(gpu_lib):
     e = autotune.tune(to_device(xh, "int32"), "add", kind="segmented", offsets=od, shapes=[(256, 8), (512, 4)],
                       groups=(1, 2), reps=2, warmup=1)
     assert e.kind == "segmented"
+
+
+def test_tune_compact(gpu_lib):
+    import numpy as np
+    from paper_1604_04815_amd import autotune
+    n = 2_000_003
+    x = to_device(make_input("int32", "add", n, seed=14), "int32")
+    keep = torch.from_numpy((np.random.default_rng(15).random(n) < 0.4).astype(np.uint8)).to("cuda")
+    before = gpu_lib.lscan_get_params(gpu_lib.I32, gpu_lib.ADD, 0, gpu_lib.KIND_COMPACT)
+    e = autotune.tune(x, "add", kind="compact", keep=keep, shapes=[(256, 8), (1024, 4)], groups=(1, 2), reps=2,
+                      warmup=1)
+    assert e.kind == "compact" and e.gbs > 0
+    autotune.apply(e)
+    out, count = gpu_lib.compact(x, keep)
+    torch.cuda.synchronize()
+    want = torch.masked_select(x, keep.bool())
+    assert int(count.item()) == want.shape[0] and torch.equal(out[:want.shape[0]], want)
+    gpu_lib.lscan_set_params(gpu_lib.I32, gpu_lib.ADD, 0, gpu_lib.KIND_COMPACT, before)

@@ -95,6 +95,8 @@ class Oracle:
         lib.oracle_compact.restype = i64
         lib.oracle_radix_offsets.argtypes = [vp, i64, i32, i32, i32, i64, vp]
         lib.oracle_radix_offsets.restype = i64
+        lib.oracle_argscan.argtypes = [vp, vp, i64, i32, i32, i32]
+        lib.oracle_argscan.restype = i32
         self.lib = lib
         self.path = path
 
@@ -172,6 +174,19 @@ class Oracle:
         return out.reshape(1 << bits, m)
 
 
+    def argscan(self, x, dtype="int32", op="argmax", exclusive=False):
+        """Running argmax / argmin: int64 indices of the best element of each
+        prefix (earliest among ties; -1 for the empty prefix)."""
+        dt, _ = _codes(dtype, "max")
+        x = _as_input(x, dt)
+        y = np.empty(x.shape[0], dtype=np.int64)
+        rc = self.lib.oracle_argscan(x.ctypes.data, y.ctypes.data, x.shape[0], dt, int(op == "argmax"),
+                                     int(bool(exclusive)))
+        if rc != 0:
+            raise ValueError(f"oracle_argscan rejected its arguments (rc={rc})")
+        return y
+
+
 _default = None
 
 
@@ -201,6 +216,10 @@ def compact(x, keep=None):
 
 def radix_offsets(keys, shift, bits, block_items):
     return default().radix_offsets(keys, shift, bits, block_items)
+
+
+def argscan(x, dtype="int32", op="argmax", exclusive=False):
+    return default().argscan(x, dtype, op, exclusive)
 
 
 def float_error_ratio(y, y64, absum):

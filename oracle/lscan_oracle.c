@@ -348,3 +348,41 @@ int64_t oracle_radix_offsets(const void *keys, int64_t n, int key_bytes,
     }
     return m;
 }
+
+/* ------------------------------------------------------------------ */
+/* argmax / argmin scans (a pair operator: value and index)            */
+/* ------------------------------------------------------------------ */
+
+/*
+ * oracle_argscan: y[j] = the index of the largest (want_max) or smallest
+ * element of x[0..j] (inclusive) or x[0..j-1] (exclusive; -1 for j = 0),
+ * the earliest index among equal values.  dtype OR_I32, OR_I64 or OR_F32
+ * (float order: IEEE totalOrder restricted to non-NaN values, as for max /
+ * min above).  One left fold, keeping (best value, its index).
+ */
+int oracle_argscan(const void *x, int64_t *y, int64_t n, int dtype,
+                   int want_max, int exclusive)
+{
+    if (n < 0 || (dtype != OR_I32 && dtype != OR_I64 && dtype != OR_F32))
+        return OR_BAD_ARG;
+    int64_t best = -1;
+    for (int64_t j = 0; j < n; ++j) {
+        if (exclusive) y[j] = best;
+        int better;
+        if (best < 0) {
+            better = 1;
+        } else if (dtype == OR_I32) {
+            int32_t v = ((const int32_t *)x)[j], b = ((const int32_t *)x)[best];
+            better = want_max ? (v > b) : (v < b);
+        } else if (dtype == OR_I64) {
+            int64_t v = ((const int64_t *)x)[j], b = ((const int64_t *)x)[best];
+            better = want_max ? (v > b) : (v < b);
+        } else {
+            float v = ((const float *)x)[j], b = ((const float *)x)[best];
+            better = want_max ? total_less(b, v) : total_less(v, b);
+        }
+        if (better) best = j;
+        if (!exclusive) y[j] = best;
+    }
+    return OR_OK;
+}

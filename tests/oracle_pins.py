@@ -366,8 +366,43 @@ def check_radix_offsets(orc, seed=19):
     assert orc.radix_offsets(np.zeros(0, np.uint32), 0, 4, 64).shape == (16, 0)
 
 
+def check_argscan(orc, seed=23):
+    """Running argmax / argmin against closed forms, brute force over the
+    prefixes (Python max / min with the earliest index) and numpy."""
+    g = np.random.default_rng(seed)
+    n = 40
+    # closed forms: increasing -> j (argmax) / 0 (argmin); constant -> 0
+    inc = np.arange(n, dtype=np.int32)
+    assert np.array_equal(orc.argscan(inc, "int32", "argmax"), np.arange(n))
+    assert np.array_equal(orc.argscan(inc, "int32", "argmin"), np.zeros(n, np.int64))
+    assert np.array_equal(orc.argscan(np.full(n, 5, np.int64), "int64", "argmax"), np.zeros(n, np.int64))
+    excl = orc.argscan(inc, "int32", "argmax", exclusive=True)
+    assert excl[0] == -1 and np.array_equal(excl[1:], np.arange(n - 1))
+    for dtype in ("int32", "int64", "float32"):
+        if dtype == "float32":
+            x = g.choice(np.array([-1.5, -0.0, 0.0, 2.0, 2.0, 7.25], np.float32), n)
+            key = lambda v: (float(v), math.copysign(1.0, float(v)))  # totalOrder on non-NaN: -0 < +0
+        else:
+            x = g.integers(-4, 5, n).astype(NP_OF[dtype])
+            key = lambda v: int(v)
+        for op in ("argmax", "argmin"):
+            got = orc.argscan(x, dtype, op)
+            gote = orc.argscan(x, dtype, op, exclusive=True)
+            pick = max if op == "argmax" else min
+            for j in range(n):
+                best = pick(range(j + 1), key=lambda i: (key(x[i]), -i if op == "argmax" else i))
+                assert got[j] == best, (dtype, op, j)
+                assert gote[j] == (got[j - 1] if j else -1), (dtype, op, j)
+    # numpy: the value at the running argmax is the running maximum
+    x = g.integers(-1000, 1000, 5000).astype(np.int32)
+    idx = orc.argscan(x, "int32", "argmax")
+    assert np.array_equal(x[idx], np.maximum.accumulate(x))
+    first = np.array([np.flatnonzero(x[:j + 1] == m)[0] for j, m in enumerate(np.maximum.accumulate(x[:300]))])
+    assert np.array_equal(idx[:300], first)
+
+
 ALL_CHECKS = (check_golden, check_closed_forms, check_brute_force, check_invariants,
-              check_cancellation, check_segmented, check_compact, check_radix_offsets)
+              check_cancellation, check_segmented, check_compact, check_radix_offsets, check_argscan)
 
 
 def failing_checks(orc):

@@ -42,6 +42,10 @@ MUTANTS = [
     ("radix_inclusive", "out[i] = acc;\n        acc += c;", "acc += c;\n        out[i] = acc;", 0),
     ("radix_shift_ignored", "int64_t d = (int64_t)((k >> shift) & mask);", "int64_t d = (int64_t)(k & mask);", 0),
     ("radix_key_truncated", ": ((const uint64_t *)keys)[i];", ": (uint64_t)((const uint32_t *)keys)[i];", 0),
+    ("argscan_ties_to_last", "better = want_max ? (v > b) : (v < b);\n        } else if (dtype == OR_I64)", "better = want_max ? (v >= b) : (v <= b);\n        } else if (dtype == OR_I64)", 0),
+    ("argscan_i64_inverted", "better = want_max ? (v > b) : (v < b);\n        } else {", "better = want_max ? (v < b) : (v > b);\n        } else {", 0),
+    ("argscan_float_zero_order", "better = want_max ? total_less(b, v) : total_less(v, b);", "better = want_max ? (v > b) : (v < b);", 0),
+    ("argscan_excl_after", "if (exclusive) y[j] = best;\n        int better;", "int better;", 0),
     ("excl_float_stale_abs", "if (absum) absum[j] = a;\n        }\n        neumaier_add(&s, &c, v);\n        a += fabs(v);\n        if (!exclusive) {\n            y64[j] = s + c;",
      "if (absum) absum[j] = a + fabs(v);\n        }\n        neumaier_add(&s, &c, v);\n        a += fabs(v);\n        if (!exclusive) {\n            y64[j] = s + c;", 0),
 ]

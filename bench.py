@@ -21,8 +21,8 @@ Prints ONE JSON line on stdout.  Besides the contract keys it carries
                 against 4096 plain launches, the 2^20 latency case, and the
                 paper's serial prefix chain at 2^20 and 2^28 against the
                 default window hand-off, stream compaction of the headline
-                array, radix-sort digit offsets), plus a device copy of the
-                same size.
+                array, radix-sort digit offsets, running argmax), plus a
+                device copy of the same size.
 
 Before the warmup steps of every measurement the device runs the same call
 for about SETTLE_S seconds (untimed), so that clocks have left the idle state
@@ -631,6 +631,19 @@ def main(argv=None) -> int:
                                                            workloads.seed_for(5, 1))
         log(f"  {configs['compact_int32_2p28_half']['gbs']} GB/s, "
             f"{configs['compact_int32_2p28_half']['speedup_vs_torch_masked_select']}x torch.masked_select")
+        log("running argmax: int32 N=2^28 (int64 indices)")
+        xa = to_device(workloads.full_range_int32(1 << 28, workloads.seed_for(7)), "int32")
+        ya = torch.empty(1 << 28, dtype=torch.int64, device="cuda")
+        ms_a, per_a = time_steps(lambda: binding.inclusive(xa, "argmax", out=ya), args.steps, args.warmup)
+        binding.lscan_check(torch.cuda.current_stream().cuda_stream)
+        info_a = binding.lscan_last_launch()
+        configs["argmax_int32_2p28"] = rate_entry(12 * (1 << 28), 1 << 28, ms_a, per_a)
+        configs["argmax_int32_2p28"].update({"bytes": 12 * (1 << 28), "grid": info_a.grid,
+                                             "block_threads": info_a.block_threads,
+                                             "tile_elems": info_a.tile_elems})
+        del xa, ya
+        torch.cuda.empty_cache()
+        log(f"  {configs['argmax_int32_2p28']['gbs']} GB/s")
         log("radix-sort digit offsets: 2^28 int32 keys, 8 bits, 16K-key blocks")
         configs["radix_offsets_int32_2p28_8bit"] = bench_radix(binding, workloads, args.steps, args.warmup)
         log(f"  {configs['radix_offsets_int32_2p28_8bit']['key_gbs']} GB/s of keys")

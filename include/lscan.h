@@ -58,7 +58,20 @@ typedef enum {
     LSCAN_BF16 = 3 /* input only; the output is float32 */
 } lscan_dtype;
 
-typedef enum { LSCAN_ADD = 0, LSCAN_MAX = 1, LSCAN_MIN = 2 } lscan_op;
+/* LSCAN_ARGMAX / LSCAN_ARGMIN: running argmax / argmin, a pair operator on
+ * (value, index): y[j] is the int64 index of the largest / smallest element
+ * of the prefix, the earliest among equal values (float32 under totalOrder,
+ * so -0 < +0); the exclusive form gives -1 for the empty prefix.  Keys
+ * LSCAN_I32, LSCAN_I64, LSCAN_F32; plain inclusive / exclusive scans only
+ * (segmented, batched, served, compensated and bf16: LSCAN_ERR_UNSUPPORTED).
+ * y holds n int64 and may not overlap x. */
+typedef enum {
+    LSCAN_ADD = 0,
+    LSCAN_MAX = 1,
+    LSCAN_MIN = 2,
+    LSCAN_ARGMAX = 3,
+    LSCAN_ARGMIN = 4
+} lscan_op;
 
 /* flags */
 #define LSCAN_F_COMPENSATED 0x1u /* F32/BF16 add: carry a TwoSum error term */

@@ -27,7 +27,8 @@ OK, PENDING = 0, 1
 ERR_INVALID_ARG, ERR_UNSUPPORTED, ERR_NO_MEMORY, ERR_DEVICE = -1, -2, -3, -4
 ERR_AGAIN, ERR_TIMEOUT, ERR_NOT_FOUND = -5, -6, -7
 
-OPS = {"add": ADD, "max": MAX, "min": MIN}
+ARGMAX, ARGMIN = 3, 4
+OPS = {"add": ADD, "max": MAX, "min": MIN, "argmax": ARGMAX, "argmin": ARGMIN}
 
 
 class LscanError(RuntimeError):
@@ -298,9 +299,11 @@ def dtype_code(t) -> int:
     return table[t.dtype]
 
 
-def out_dtype(t):
+def out_dtype(t, op="add"):
     import torch
 
+    if op in ("argmax", "argmin"):
+        return torch.int64  # indices
     return torch.float32 if t.dtype == torch.bfloat16 else t.dtype
 
 
@@ -320,21 +323,22 @@ def _flat(t, name):
     return t
 
 
-def _out_for(x, out):
+def _out_for(x, out, op="add"):
     import torch
 
     if out is None:
-        return torch.empty(x.shape[0], dtype=out_dtype(x), device=x.device)
+        return torch.empty(x.shape[0], dtype=out_dtype(x, op), device=x.device)
     _flat(out, "out")
-    if out.dtype != out_dtype(x) or out.shape[0] != x.shape[0]:
+    if out.dtype != out_dtype(x, op) or out.shape[0] != x.shape[0]:
         raise ValueError("out has the wrong dtype or length")
     return out
 
 
 def inclusive(x, op="add", compensated=False, out=None, stream=None, params: Params | None = None):
-    """y_j = x_0 (+) ... (+) x_j on the device; returns y."""
+    """y_j = x_0 (+) ... (+) x_j on the device; returns y (for argmax /
+    argmin the int64 index of the best element of each prefix)."""
     _flat(x, "x")
-    y = _out_for(x, out)
+    y = _out_for(x, out, op)
     flags = F_COMPENSATED if compensated else 0
     if params is None:
         lscan_inclusive(x.data_ptr(), y.data_ptr(), x.shape[0], dtype_code(x), OPS[op], flags, _stream(stream))
@@ -347,7 +351,7 @@ def inclusive(x, op="add", compensated=False, out=None, stream=None, params: Par
 def exclusive(x, op="add", compensated=False, out=None, stream=None, params: Params | None = None):
     """y_0 = e, y_j = x_0 (+) ... (+) x_{j-1} on the device; returns y."""
     _flat(x, "x")
-    y = _out_for(x, out)
+    y = _out_for(x, out, op)
     flags = F_COMPENSATED if compensated else 0
     if params is None:
         lscan_exclusive(x.data_ptr(), y.data_ptr(), x.shape[0], dtype_code(x), OPS[op], flags, _stream(stream))

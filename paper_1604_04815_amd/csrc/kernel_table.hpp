@@ -67,6 +67,7 @@ enum OpCode : int {
     kI64Add, kI64Max, kI64Min,
     kF32Add, kF32AddComp, kF32Max, kF32Min,
     kBF16Add, kBF16AddComp, kBF16Max, kBF16Min,
+    kI32ArgMax, kI32ArgMin, kI64ArgMax, kI64ArgMin, kF32ArgMax, kF32ArgMin,  // plain scans only
     kNumOpCodes
 };
 
@@ -91,5 +92,6 @@ void register_i64_batch_kernels(KernelTable& t);
 void register_f32_batch_kernels(KernelTable& t);
 void register_bf16_batch_kernels(KernelTable& t);
 void register_compact_kernels(KernelTable& t);
+void register_arg_kernels(KernelTable& t);
 
 }  // namespace lscan

@@ -39,6 +39,7 @@ void init_table()
     register_f32_batch_kernels(g_table);
     register_bf16_batch_kernels(g_table);
     register_compact_kernels(g_table);
+    register_arg_kernels(g_table);
 }
 
 const KernelTable& table()
@@ -132,6 +133,8 @@ void init_params_locked()
     g_params[kModePlain][kBF16AddComp] = t1024x4;
     g_params[kModePlain][kBF16Max] = t256x16g2;
     g_params[kModePlain][kBF16Min] = t256x16g2;
+    const Params t1024x2{5, 1};
+    for (int o = kI32ArgMax; o <= kF32ArgMin; ++o) g_params[kModePlain][o] = t1024x2;
     for (int o = 0; o < kNumOpCodes; ++o) {
         g_params[kModeSegmented][o] = t512x8;
         g_params[kModeBatched][o] = g_params[kModePlain][o];
@@ -143,8 +146,17 @@ void init_params_locked()
 int opcode_of(int dt, int op, uint32_t flags)
 {
     const bool comp = (flags & LSCAN_F_COMPENSATED) != 0;
-    if (dt < LSCAN_I32 || dt > LSCAN_BF16 || op < LSCAN_ADD || op > LSCAN_MIN) return -1;
+    if (dt < LSCAN_I32 || dt > LSCAN_BF16 || op < LSCAN_ADD || op > LSCAN_ARGMIN) return -1;
     if (comp && !((dt == LSCAN_F32 || dt == LSCAN_BF16) && op == LSCAN_ADD)) return -2;
+    if (op == LSCAN_ARGMAX || op == LSCAN_ARGMIN) {
+        const int k = (op == LSCAN_ARGMAX) ? 0 : 1;
+        switch (dt) {
+        case LSCAN_I32: return kI32ArgMax + k;
+        case LSCAN_I64: return kI64ArgMax + k;
+        case LSCAN_F32: return kF32ArgMax + k;
+        default: return -2;  // bf16 keys are not offered
+        }
+    }
     switch (dt) {
     case LSCAN_I32: return kI32Add + op;
     case LSCAN_I64: return kI64Add + op;
@@ -155,7 +167,13 @@ int opcode_of(int dt, int op, uint32_t flags)
 }
 
 int in_bytes_of(int dt) { return dt == LSCAN_I64 ? 8 : dt == LSCAN_BF16 ? 2 : 4; }
-int out_bytes_of(int dt) { return dt == LSCAN_I64 ? 8 : 4; }
+// output element size; running argmax / argmin write int64 indices
+int out_bytes_of(int dt, int op = LSCAN_ADD)
+{
+    if (op == LSCAN_ARGMAX || op == LSCAN_ARGMIN) return 8;
+    return dt == LSCAN_I64 ? 8 : 4;
+}
+bool is_arg_op(int op) { return op == LSCAN_ARGMAX || op == LSCAN_ARGMIN; }
 
 int shape_index(int threads, int vectors)
 {
@@ -165,13 +183,13 @@ int shape_index(int threads, int vectors)
 }
 
 // x / y of one array: element alignment, and no overlap other than in place.
-lscan_status check_array(const void* x, const void* y, int64_t n, int dt)
+lscan_status check_array(const void* x, const void* y, int64_t n, int dt, int op = LSCAN_ADD)
 {
     if (n < 0) return LSCAN_ERR_INVALID_ARG;
     if (n == 0) return LSCAN_OK;
     if (!x || !y) return LSCAN_ERR_INVALID_ARG;
     const uintptr_t xa = reinterpret_cast<uintptr_t>(x), ya = reinterpret_cast<uintptr_t>(y);
-    const int ib = in_bytes_of(dt), ob = out_bytes_of(dt);
+    const int ib = in_bytes_of(dt), ob = out_bytes_of(dt, op);
     if (xa % uintptr_t(ib) || ya % uintptr_t(ob)) return LSCAN_ERR_INVALID_ARG;
     if (uint64_t(n) > (UINT64_MAX / 16)) return LSCAN_ERR_INVALID_ARG;
     const uintptr_t xe = xa + uintptr_t(n) * uintptr_t(ib), ye = ya + uintptr_t(n) * uintptr_t(ob);
@@ -219,6 +237,7 @@ lscan_status make_request(int mode, const void* x, void* y, int64_t n, const int
     const int oc = opcode_of(dt, op, flags);
     if (oc == -1) return LSCAN_ERR_INVALID_ARG;
     if (oc == -2) return LSCAN_ERR_UNSUPPORTED;
+    if (is_arg_op(op) && mode != kModePlain) return LSCAN_ERR_UNSUPPORTED;  // plain scans only
     lscan_status st = check_params(p);
     if (st != LSCAN_OK) return st;
     r->mode = mode;
@@ -238,7 +257,7 @@ lscan_status make_request(int mode, const void* x, void* y, int64_t n, const int
         r->empty = (total == 0);
         return LSCAN_OK;
     }
-    st = check_array(x, y, n, dt);
+    st = check_array(x, y, n, dt, op);
     if (st != LSCAN_OK) return st;
     if (mode == kModeSegmented) {
         if (num_segments < 0) return LSCAN_ERR_INVALID_ARG;
@@ -496,6 +515,7 @@ lscan_status plan_locked(const Request& r, int dev, Workspace* ws_fixed, hipStre
     if (r.p && r.p->groups_per_cu > 0) prm.groups_per_cu = r.p->groups_per_cu;
     if (r.p) prm.handoff = r.p->handoff;
     const KernelEntry& k = table()[r.mode][r.oc][prm.shape];
+    if (!k.func) return LSCAN_ERR_UNSUPPORTED;  // no kernel of this kind for the operator
 
     DeviceInfo* info = nullptr;
     lscan_status st = device_info_locked(dev, &info);
@@ -642,6 +662,7 @@ lscan_status validate_request(const void* x, const void* y, int64_t n, int dt, i
     const int oc = opcode_of(dt, op, flags);
     if (oc == -1) return LSCAN_ERR_INVALID_ARG;
     if (oc == -2) return LSCAN_ERR_UNSUPPORTED;
+    if (is_arg_op(op)) return LSCAN_ERR_UNSUPPORTED;  // the server batches add / max / min scans
     return check_array(x, y, n, dt);
 }
 

@@ -66,10 +66,12 @@ __device__ __forceinline__ void load_vector(const T* p, T (&out)[E])
 template <class T, int E>
 __device__ __forceinline__ void store_vector(T* p, const T (&v)[E])
 {
-    static_assert(int(sizeof(T)) * E == 16, "16-byte output vectors");
-    u32x4 w;
-    __builtin_memcpy(&w, v, 16);
-    __builtin_nontemporal_store(w, reinterpret_cast<u32x4*>(p));
+    constexpr int kBytes = int(sizeof(T)) * E;
+    static_assert(kBytes == 16 || kBytes == 32, "16- or 32-byte output vectors");
+    u32x4 w[kBytes / 16];
+    __builtin_memcpy(w, v, kBytes);
+#pragma unroll
+    for (int h = 0; h < kBytes / 16; ++h) __builtin_nontemporal_store(w[h], reinterpret_cast<u32x4*>(p) + h);
 }
 
 // ---------------------------------------------------------------------------
@@ -467,9 +469,10 @@ __global__ void __launch_bounds__(T) scan_kernel(ScanArgs a)
 #pragma unroll
                     for (int k = 0; k < E; ++k) {
                         if constexpr (MODE == kModeSegmented)
-                            e[r][k] = EOp::make(BaseOp::lift(raw[r][k]), (head[r] >> k) & 1u);
+                            e[r][k] = EOp::make(lift_elem<BaseOp>(raw[r][k], lane0 + int64_t(r) * ROW + k),
+                                                (head[r] >> k) & 1u);
                         else
-                            e[r][k] = BaseOp::lift(raw[r][k]);
+                            e[r][k] = lift_elem<BaseOp>(raw[r][k], lane0 + int64_t(r) * ROW + k);
                     }
             } else {
 #pragma unroll
@@ -479,9 +482,9 @@ __global__ void __launch_bounds__(T) scan_kernel(ScanArgs a)
                         const int64_t p = lane0 + int64_t(r) * ROW + k;
                         if (p < n) {
                             if constexpr (MODE == kModeSegmented)
-                                e[r][k] = EOp::make(BaseOp::lift(x[p]), (head[r] >> k) & 1u);
+                                e[r][k] = EOp::make(lift_elem<BaseOp>(x[p], p), (head[r] >> k) & 1u);
                             else
-                                e[r][k] = BaseOp::lift(x[p]);
+                                e[r][k] = lift_elem<BaseOp>(x[p], p);
                         } else {
                             e[r][k] = EOp::identity();
                         }

@@ -18,6 +18,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace lscan {
 
 // ---------------------------------------------------------------------------
@@ -216,6 +218,87 @@ struct MinF32 {
     __device__ static V lift(In x) { return order_key(x); }
     __device__ static Out lower(V v) { return bits_to_f32(key_bits(v)); }
 };
+
+// Running argmax / argmin: the value carries the element's index, and the
+// scan keeps the best (key, index) pair, the earlier one among equal keys
+// (a is always the earlier operand, so ties keep a).  An index < 0 marks
+// the identity, which loses to every element.  The output is the int64
+// index.  Keys: int32 / int64 values, float32 as totalOrder keys.  The
+// index is kept as two 32-bit halves so that a 32-bit key gives a
+// three-word value (three DPP moves per step).
+template <class KeyT>
+struct ArgValue;
+template <>
+struct ArgValue<int32_t> {
+    int32_t key;
+    uint32_t lo, hi;
+    __device__ int64_t index() const { return int64_t((uint64_t(hi) << 32) | lo); }
+};
+template <>
+struct ArgValue<int64_t> {
+    int64_t key;
+    uint32_t lo, hi;
+    __device__ int64_t index() const { return int64_t((uint64_t(hi) << 32) | lo); }
+};
+
+template <class In_, class KeyT, bool MAX, bool FLOAT_KEY>
+struct ArgOp {
+    using In = In_; using V = ArgValue<KeyT>; using Out = int64_t;
+    static constexpr int E = 16 / int(sizeof(In));
+    static constexpr bool kIndexed = true;
+    __device__ static V identity()
+    {
+        V v;
+        v.key = 0;
+        v.lo = 0xffffffffu;
+        v.hi = 0xffffffffu;
+        return v;
+    }
+    __device__ static V combine(V a, V b)
+    {
+        // field by field: a select of whole structs would go through memory
+        const bool a_id = int32_t(a.hi) < 0, b_id = int32_t(b.hi) < 0;
+        const bool take_b = a_id || (!b_id && (MAX ? (b.key > a.key) : (b.key < a.key)));
+        V r;
+        r.key = take_b ? b.key : a.key;
+        r.lo = take_b ? b.lo : a.lo;
+        r.hi = take_b ? b.hi : a.hi;
+        return r;
+    }
+    __device__ static V lift_at(In x, int64_t i)
+    {
+        V v;
+        if constexpr (FLOAT_KEY)
+            v.key = order_key(x);
+        else
+            v.key = KeyT(x);
+        v.lo = uint32_t(uint64_t(i));
+        v.hi = uint32_t(uint64_t(i) >> 32);
+        return v;
+    }
+    __device__ static Out lower(const V& v) { return v.index(); }
+};
+using ArgMaxI32 = ArgOp<int32_t, int32_t, true, false>;
+using ArgMinI32 = ArgOp<int32_t, int32_t, false, false>;
+using ArgMaxI64 = ArgOp<int64_t, int64_t, true, false>;
+using ArgMinI64 = ArgOp<int64_t, int64_t, false, false>;
+using ArgMaxF32 = ArgOp<uint32_t, int32_t, true, true>;
+using ArgMinF32 = ArgOp<uint32_t, int32_t, false, true>;
+
+// Element lift for operators with (kIndexed) or without the element index.
+template <class Op, class = void>
+struct is_indexed_op : std::false_type {};
+template <class Op>
+struct is_indexed_op<Op, std::void_t<decltype(Op::kIndexed)>> : std::integral_constant<bool, Op::kIndexed> {};
+
+template <class Op>
+__device__ __forceinline__ typename Op::V lift_elem(typename Op::In x, int64_t i)
+{
+    if constexpr (is_indexed_op<Op>::value)
+        return Op::lift_at(x, i);
+    else
+        return Op::lift(x);
+}
 
 // bfloat16 input: the 16 bits become the high half of an f32 (exact), then
 // the f32 operator runs.  Loads are 8 bytes (4 elements) per lane so that

@@ -254,3 +254,19 @@ def test_radix_offsets_validation(lib):
     # nothing to do
     assert f(None, 0, binding.I32, 0, 8, 4, None, None) == binding.OK
 
+
+def test_argscan_validation(lib):
+    f = lib.lscan_inclusive
+    assert f(FAKE_X, FAKE_Y, 8, binding.BF16, binding.ARGMAX, 0, None) == binding.ERR_UNSUPPORTED
+    assert f(FAKE_X, FAKE_Y, 8, binding.F32, binding.ARGMIN, binding.F_COMPENSATED, None) == binding.ERR_UNSUPPORTED
+    assert f(FAKE_X, FAKE_Y, 8, binding.I32, 5, 0, None) == binding.ERR_INVALID_ARG
+    # int64 indices may not share memory with the int32 keys, not even exactly
+    assert f(FAKE_X, FAKE_X, 8, binding.I32, binding.ARGMAX, 0, None) == binding.ERR_INVALID_ARG
+    # y must be 8-byte aligned for the indices
+    assert f(FAKE_X, FAKE_Y + 4, 8, binding.I32, binding.ARGMAX, 0, None) == binding.ERR_INVALID_ARG
+    # plain scans only
+    assert lib.lscan_segmented(FAKE_X, FAKE_Y, 8, FAKE_X, 1, binding.I32, binding.ARGMAX, 0,
+                               None) == binding.ERR_UNSUPPORTED
+    tab = (binding.Array * 1)(binding.Array(FAKE_X, FAKE_Y, 8))
+    assert lib.lscan_batched(tab, 1, binding.I32, binding.ARGMIN, 0, None) == binding.ERR_UNSUPPORTED
+

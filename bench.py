@@ -57,15 +57,26 @@ def log(msg: str) -> None:
 DEVICE_SOURCES = ("scan_kernel.hpp", "scan_ops.hpp", "kernel_table.hpp")
 
 
+def _code_only(text: str) -> str:
+    """Source text without comments and blank lines (comments do not change
+    the kernels)."""
+    import re
+
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    lines = [re.sub(r"//.*$", "", l).rstrip() for l in text.splitlines()]
+    return "\n".join(l for l in lines if l.strip())
+
+
 def kernel_source_hash() -> str:
     """Hash of the device code (kernel templates, operators, argument layout
-    and instantiation units); host-only changes leave it unchanged."""
+    and instantiation units, comments left out); host-only changes leave it
+    unchanged."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1604_04815_amd", "csrc")
     files = [os.path.join(csrc, f) for f in DEVICE_SOURCES] + sorted(glob.glob(os.path.join(csrc, "kernels_*.hip")))
     for f in files:
         h.update(os.path.basename(f).encode())
-        h.update(open(f, "rb").read())
+        h.update(_code_only(open(f).read()).encode())
     return h.hexdigest()[:16]
 
 

@@ -26,16 +26,28 @@
 //     serial prefix chain of the paper (one cross-workgroup hop per block)
 //     becomes one hop per block plus a chain of M / B steps that stays inside
 //     each workgroup, and the association is fixed, so float results are
-//     deterministic for a given (T, R, B).
+//     deterministic for a given (T, R, B).  The paper's chain itself is
+//     kept as a launch option (ScanArgs::chain): block i waits for the
+//     inclusive prefix P(i - 1) that block i - 1 published, then publishes
+//     P(i).
+//   * Software pipeline: a block's prefix is resolved one round late.  The
+//     iteration that loads block i folds the window of the previous block
+//     i - B (whose aggregates were published a round earlier) while the
+//     loads are in flight, and stores block i - B; block i waits in
+//     registers as block-local values.  The last step, which only drains the
+//     pending block, is a separate instantiation so that inside the loop
+//     every load is consumed on every path.
 //   * Intra-block global scan (Algorithm 5): each element becomes
 //     (P(i - 1) (+) (wave prefix (+) row prefix (+) lane prefix)) (+) its
 //     in-lane scan value -- the block prefix joins each lane-row once, then
 //     its elements -- and is stored once, coalesced.
 //
 // Forward progress: all B workgroups must be resident at once (Section 5.1
-// notes the deadlock otherwise); the host caps B by the occupancy limit.  A
-// wait that outlasts spin_limit raises a timeout flag and the workgroup stops,
-// so every wave always exits.
+// notes the deadlock otherwise); the host caps B by the occupancy limit and
+// by a co-residency test run in this kernel (check_residency).  A wait that
+// outlasts spin_limit raises a timeout flag and the workgroup stops; the
+// others see the launch's tag in the abort word and stop waiting too, so
+// every wave always exits.
 #pragma once
 
 #include <type_traits>

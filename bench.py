@@ -491,7 +491,7 @@ def bench_serving(binding, workloads, seconds: float, rate: float):
     srv.close()
     served = summarize(lat, arrivals[0], t_done_last)
     served.update({"batches": int(stats.batches), "peak_bytes_in_flight": int(stats.peak_bytes_in_flight)})
-    same = True
+    failed = []
     for idx, y in checks:
         alone = binding.inclusive(xs[idx], trace[idx]["op"])
         if trace[idx]["dtype"] == "float32" and trace[idx]["op"] == "add":
@@ -499,10 +499,13 @@ def bench_serving(binding, workloads, seconds: float, rate: float):
             # shapes associate differently), so within twice that of each other
             a = torch.cumsum(xs[idx].abs().to(torch.float64), 0)
             diff = (y.to(torch.float64) - alone.to(torch.float64)).abs()
-            same &= bool((diff <= 2e-6 * a).all())
+            ok = bool((diff <= 2e-6 * a).all())
         else:
-            same &= bool(torch.equal(y, alone))
-    served["spot_checks_equal_alone"] = same
+            ok = bool(torch.equal(y, alone))
+        if not ok:
+            failed.append({"request": idx, "dtype": trace[idx]["dtype"], "op": trace[idx]["op"], "n": trace[idx]["n"]})
+    served["spot_checks_equal_alone"] = not failed
+    served["spot_check_failures"] = failed[:8]
     served["spot_checks"] = len(checks)
     out["served"] = served
 

@@ -41,6 +41,13 @@
  * Thread safety: every entry point may be called from any thread.  Each
  * (device, stream) pair owns its own flag workspace, so launches on one
  * stream are ordered and launches on different streams never share flags.
+ * A scan's persistent grid fills the device, and two such grids running at
+ * once on different streams could each hold part of it and wait for
+ * workgroups that cannot become resident.  So a launch on a stream other
+ * than the device's previous one first waits, on the device, for that
+ * previous launch (hipStreamWaitEvent; launches on one stream pay nothing).
+ * Graph replays and the request server's launches are not part of this
+ * order: do not run them on a device at the same time as other scans.
  */
 #ifndef LSCAN_H
 #define LSCAN_H

@@ -96,6 +96,20 @@ struct Params {
 std::mutex g_mu;
 std::map<int, DeviceInfo> g_dev;
 std::map<std::pair<int, hipStream_t>, Workspace> g_ws;
+
+// Persistent grids on different streams of one device could each hold part
+// of the device and wait for workgroups of their own that cannot become
+// resident.  Scans issued through the C ABI are therefore ordered across
+// streams: a launch on a stream other than the device's previous one first
+// waits (on the device, hipStreamWaitEvent) for that previous launch.
+// Launches on one stream need nothing, and the request server, which sizes
+// its streams' grids to fit side by side, opts out.
+struct DeviceOrder {
+    hipStream_t last = nullptr;
+    bool any = false;
+    hipEvent_t done = nullptr;  // recorded after the device's last ordered launch
+};
+std::map<int, DeviceOrder> g_order;
 Params g_params[kNumModes][kNumOpCodes];
 bool g_params_init = false;
 
@@ -223,6 +237,7 @@ struct Request {
     bool exclusive = false;
     const lscan_params* p = nullptr;
     bool empty = false;                  // nothing to do
+    bool ordered = true;                 // order after other streams' launches (not for the server)
     uint32_t* status_host = nullptr;     // optional host-visible timeout word
     const uint8_t* keep = nullptr;       // compaction: keep flags (may be null)
     int64_t* count = nullptr;            // compaction: device count of kept items
@@ -644,6 +659,21 @@ lscan_status run(const Request& r, void* stream_ptr)
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return device_error(e);
     std::lock_guard<std::mutex> lock(g_mu);
+    DeviceOrder* order = nullptr;
+    if (r.ordered && !capturing(stream)) {
+        order = &g_order[dev];
+        if (!order->done) {
+            e = hipEventCreateWithFlags(&order->done, hipEventDisableTiming);
+            if (e != hipSuccess) {
+                order->done = nullptr;
+                return device_error(e);
+            }
+        }
+        if (order->any && order->last != stream) {  // before the co-residency test, too
+            e = hipStreamWaitEvent(stream, order->done, 0);
+            if (e != hipSuccess) return device_error(e);
+        }
+    }
     Plan plan;
     Workspace* ws = nullptr;
     lscan_status st = plan_locked(r, dev, nullptr, stream, &plan, &ws);
@@ -651,6 +681,12 @@ lscan_status run(const Request& r, void* stream_ptr)
     e = plan.k->launch(plan.a, plan.grid, stream);
     if (e != hipSuccess) return device_error(e);
     ws->launches++;
+    if (order) {
+        e = hipEventRecord(order->done, stream);
+        if (e != hipSuccess) return device_error(e);
+        order->last = stream;
+        order->any = true;
+    }
     return LSCAN_OK;
 }
 
@@ -687,6 +723,7 @@ lscan_status launch_single(const void* x, void* y, int64_t n, lscan_dtype dt, ls
                                    (flags & LSCAN_F_EXCLUSIVE) != 0, p, &r);
     if (st != LSCAN_OK) return st;
     r.status_host = status_host;
+    r.ordered = false;
     return run(r, stream);
 }
 
@@ -698,6 +735,7 @@ lscan_status launch_batched(const lscan_array* arrays, int64_t count, lscan_dtyp
                                    (flags & LSCAN_F_EXCLUSIVE) != 0, p, &r);
     if (st != LSCAN_OK) return st;
     r.status_host = status_host;
+    r.ordered = false;
     return run(r, stream);
 }
 
@@ -1045,6 +1083,7 @@ lscan_status lscan_release_workspaces(void)
             ++it;
         }
     }
+    g_order[dev].any = false;  // the device is idle: nothing to order after
     return LSCAN_OK;
 }
 

@@ -181,3 +181,24 @@ def test_int_wraparound(gpu_lib):
     x64 = np.full(n, 2 ** 62 + 12345, dtype=np.int64)
     compare(to_host(gpu_lib.inclusive(to_device(x64, "int64"), "add")), x64, "int64", "add", False,
             what="wrap64")
+
+
+def test_scans_alternating_on_two_streams_without_sync(gpu_lib):
+    # full-device persistent grids enqueued on two streams back to back: the
+    # runtime orders them across streams, so none waits for workgroups that
+    # cannot become resident, and every result is exact
+    n = (1 << 26) + 3
+    x = torch.randint(-1000, 1001, (n,), dtype=torch.int32, device="cuda")
+    want = torch.cumsum(x.to(torch.int64), 0).to(torch.int32)
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    ys = [torch.empty_like(x) for _ in range(6)]
+    torch.cuda.synchronize()
+    for k, y in enumerate(ys):
+        s = streams[k % 2]
+        with torch.cuda.stream(s):
+            gpu_lib.inclusive(x, "add", out=y)
+    for s in streams:
+        s.synchronize()
+        gpu_lib.lscan_check(s.cuda_stream)
+    for y in ys:
+        assert torch.equal(y, want)

@@ -45,7 +45,8 @@
  * once on different streams could each hold part of it and wait for
  * workgroups that cannot become resident.  So a launch on a stream other
  * than the device's previous one first waits, on the device, for that
- * previous launch (hipStreamWaitEvent; launches on one stream pay nothing).
+ * previous launch (hipStreamWaitEvent; launches on one stream pay nothing,
+ * and the first switch to a second stream synchronizes the device once).
  * Graph replays and the request server's launches are not part of this
  * order: do not run them on a device at the same time as other scans.
  */

@@ -104,9 +104,13 @@ std::map<std::pair<int, hipStream_t>, Workspace> g_ws;
 // waits (on the device, hipStreamWaitEvent) for that previous launch.
 // Launches on one stream need nothing, and the request server, which sizes
 // its streams' grids to fit side by side, opts out.
+// Until a second stream shows up nothing is recorded (one stream is ordered
+// by itself); the first switch drains the device once, and from then on an
+// event is recorded after every launch.
 struct DeviceOrder {
     hipStream_t last = nullptr;
     bool any = false;
+    bool multi = false;         // a second stream has been seen: events are recorded
     hipEvent_t done = nullptr;  // recorded after the device's last ordered launch
 };
 std::map<int, DeviceOrder> g_order;
@@ -662,17 +666,24 @@ lscan_status run(const Request& r, void* stream_ptr)
     DeviceOrder* order = nullptr;
     if (r.ordered && !capturing(stream)) {
         order = &g_order[dev];
-        if (!order->done) {
-            e = hipEventCreateWithFlags(&order->done, hipEventDisableTiming);
-            if (e != hipSuccess) {
-                order->done = nullptr;
-                return device_error(e);
-            }
-        }
         if (order->any && order->last != stream) {  // before the co-residency test, too
-            e = hipStreamWaitEvent(stream, order->done, 0);
+            if (!order->multi) {
+                if (!order->done) {
+                    e = hipEventCreateWithFlags(&order->done, hipEventDisableTiming);
+                    if (e != hipSuccess) {
+                        order->done = nullptr;
+                        return device_error(e);
+                    }
+                }
+                e = hipDeviceSynchronize();  // once: the previous stream's launches have no event
+                order->multi = true;
+            } else {
+                e = hipStreamWaitEvent(stream, order->done, 0);
+            }
             if (e != hipSuccess) return device_error(e);
         }
+        order->any = true;
+        order->last = stream;
     }
     Plan plan;
     Workspace* ws = nullptr;
@@ -681,11 +692,9 @@ lscan_status run(const Request& r, void* stream_ptr)
     e = plan.k->launch(plan.a, plan.grid, stream);
     if (e != hipSuccess) return device_error(e);
     ws->launches++;
-    if (order) {
+    if (order && order->multi) {
         e = hipEventRecord(order->done, stream);
         if (e != hipSuccess) return device_error(e);
-        order->last = stream;
-        order->any = true;
     }
     return LSCAN_OK;
 }
@@ -1084,6 +1093,7 @@ lscan_status lscan_release_workspaces(void)
         }
     }
     g_order[dev].any = false;  // the device is idle: nothing to order after
+    g_order[dev].multi = false;
     return LSCAN_OK;
 }
 

@@ -664,9 +664,10 @@ lscan_status run(const Request& r, void* stream_ptr)
     if (e != hipSuccess) return device_error(e);
     std::lock_guard<std::mutex> lock(g_mu);
     DeviceOrder* order = nullptr;
-    if (r.ordered && !capturing(stream)) {
+    if (r.ordered) {
         order = &g_order[dev];
-        if (order->any && order->last != stream) {  // before the co-residency test, too
+        // (the capture query is made only on a stream switch: it is not free)
+        if (order->any && order->last != stream && !capturing(stream)) {  // before the co-residency test, too
             if (!order->multi) {
                 if (!order->done) {
                     e = hipEventCreateWithFlags(&order->done, hipEventDisableTiming);
@@ -692,7 +693,7 @@ lscan_status run(const Request& r, void* stream_ptr)
     e = plan.k->launch(plan.a, plan.grid, stream);
     if (e != hipSuccess) return device_error(e);
     ws->launches++;
-    if (order && order->multi) {
+    if (order && order->multi && !capturing(stream)) {
         e = hipEventRecord(order->done, stream);
         if (e != hipSuccess) return device_error(e);
     }

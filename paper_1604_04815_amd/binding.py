@@ -311,6 +311,9 @@ def _stream(stream) -> int:
     import torch
 
     if stream is None:
+        raw = getattr(torch._C, "_cuda_getCurrentRawStream", None)
+        if raw is not None:  # the raw handle without building a Stream object (a few microseconds less)
+            return raw(torch.cuda.current_device())
         return torch.cuda.current_stream().cuda_stream
     return stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
 

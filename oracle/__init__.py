@@ -97,6 +97,8 @@ class Oracle:
         lib.oracle_radix_offsets.restype = i64
         lib.oracle_argscan.argtypes = [vp, vp, i64, i32, i32, i32]
         lib.oracle_argscan.restype = i32
+        lib.oracle_bfs_levels.argtypes = [vp, vp, i64, i64, vp, vp]
+        lib.oracle_bfs_levels.restype = i64
         self.lib = lib
         self.path = path
 
@@ -187,6 +189,21 @@ class Oracle:
         return y
 
 
+    def bfs_levels(self, row_ptr, col, src):
+        """BFS levels from ``src`` over a CSR graph (int64 row_ptr, int32
+        col): int32 array, -1 for unreachable vertices."""
+        row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int64)
+        col = np.ascontiguousarray(col, dtype=np.int32)
+        nv = row_ptr.shape[0] - 1
+        level = np.empty(nv, dtype=np.int32)
+        queue = np.empty(max(nv, 1), dtype=np.int32)
+        rc = self.lib.oracle_bfs_levels(row_ptr.ctypes.data, col.ctypes.data, nv, int(src), level.ctypes.data,
+                                        queue.ctypes.data)
+        if rc < 0:
+            raise ValueError(f"oracle_bfs_levels rejected its arguments (rc={rc})")
+        return level
+
+
 _default = None
 
 
@@ -220,6 +237,10 @@ def radix_offsets(keys, shift, bits, block_items):
 
 def argscan(x, dtype="int32", op="argmax", exclusive=False):
     return default().argscan(x, dtype, op, exclusive)
+
+
+def bfs_levels(row_ptr, col, src):
+    return default().bfs_levels(row_ptr, col, src)
 
 
 def float_error_ratio(y, y64, absum):

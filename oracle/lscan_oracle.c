@@ -386,3 +386,42 @@ int oracle_argscan(const void *x, int64_t *y, int64_t n, int dtype,
     }
     return OR_OK;
 }
+
+/* ------------------------------------------------------------------ */
+/* breadth-first search levels (device-level messaging between blocks) */
+/* ------------------------------------------------------------------ */
+
+/*
+ * oracle_bfs_levels: the breadth-first search that the paper names as the
+ * next use of its inter-block hand-off (Section 6): level[v] is the number
+ * of edges on a shortest path from src to v in the directed graph given in
+ * compressed rows (row_ptr[num_vertices + 1], col[row_ptr[V]]), or -1 if v
+ * is unreachable.  A plain queue, vertices visited in FIFO order.  Returns
+ * the number of levels (the largest level + 1), or -1 for bad arguments.
+ * queue must hold num_vertices entries.
+ */
+int64_t oracle_bfs_levels(const int64_t *row_ptr, const int32_t *col,
+                          int64_t num_vertices, int64_t src, int32_t *level,
+                          int32_t *queue)
+{
+    if (num_vertices < 0 || (num_vertices > 0 && (src < 0 || src >= num_vertices)))
+        return -1;
+    for (int64_t v = 0; v < num_vertices; ++v) level[v] = -1;
+    if (num_vertices == 0) return 0;
+    int64_t head = 0, tail = 0, depth = 0;
+    level[src] = 0;
+    queue[tail++] = (int32_t)src;
+    while (head < tail) {
+        int32_t u = queue[head++];
+        if (level[u] + 1 > depth) depth = level[u] + 1;
+        for (int64_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e) {
+            int32_t v = col[e];
+            if (v < 0 || v >= num_vertices) return -1;
+            if (level[v] < 0) {
+                level[v] = level[u] + 1;
+                queue[tail++] = v;
+            }
+        }
+    }
+    return depth;
+}

@@ -401,8 +401,53 @@ def check_argscan(orc, seed=23):
     assert np.array_equal(idx[:300], first)
 
 
+def _csr(n, edges):
+    edges = sorted(edges)
+    row_ptr = np.zeros(n + 1, np.int64)
+    for u, _ in edges:
+        row_ptr[u + 1] += 1
+    return np.cumsum(row_ptr), np.array([v for _, v in edges], np.int32)
+
+
+def check_bfs(orc, seed=29):
+    """BFS levels against closed forms (path, star, cycle, two components)
+    and a Floyd-Warshall all-pairs shortest-path table on small random graphs."""
+    # path 0 -> 1 -> ... -> 9: level = index; reversed source: only itself
+    rp, c = _csr(10, [(i, i + 1) for i in range(9)])
+    assert np.array_equal(orc.bfs_levels(rp, c, 0), np.arange(10))
+    lv = orc.bfs_levels(rp, c, 9)
+    assert lv[9] == 0 and np.all(lv[:9] == -1)
+    # star from 0: everything at level 1
+    rp, c = _csr(50, [(0, v) for v in range(1, 50)])
+    assert np.array_equal(orc.bfs_levels(rp, c, 0), np.array([0] + [1] * 49))
+    # undirected cycle of 12: level = min(i, 12 - i)
+    ed = [(i, (i + 1) % 12) for i in range(12)] + [((i + 1) % 12, i) for i in range(12)]
+    rp, c = _csr(12, ed)
+    assert np.array_equal(orc.bfs_levels(rp, c, 0), np.array([min(i, 12 - i) for i in range(12)]))
+    # random directed graphs against Floyd-Warshall on hop counts
+    g = np.random.default_rng(seed)
+    for n, m in ((30, 60), (40, 200), (25, 20)):
+        ed = set()
+        while len(ed) < m:
+            u, v = (int(t) for t in g.integers(0, n, 2))
+            if u != v:
+                ed.add((u, v))
+        rp, c = _csr(n, list(ed))
+        inf = 10 ** 9
+        d = np.full((n, n), inf, np.int64)
+        np.fill_diagonal(d, 0)
+        for u, v in ed:
+            d[u, v] = 1
+        for k in range(n):
+            d = np.minimum(d, d[:, k:k + 1] + d[k:k + 1, :])
+        for s in (0, n // 2):
+            want = np.where(d[s] >= inf, -1, d[s])
+            assert np.array_equal(orc.bfs_levels(rp, c, s), want), (n, m, s)
+
+
 ALL_CHECKS = (check_golden, check_closed_forms, check_brute_force, check_invariants,
-              check_cancellation, check_segmented, check_compact, check_radix_offsets, check_argscan)
+              check_cancellation, check_segmented, check_compact, check_radix_offsets, check_argscan,
+              check_bfs)
 
 
 def failing_checks(orc):

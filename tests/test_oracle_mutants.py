@@ -46,6 +46,10 @@ MUTANTS = [
     ("argscan_i64_inverted", "better = want_max ? (v > b) : (v < b);\n        } else {", "better = want_max ? (v < b) : (v > b);\n        } else {", 0),
     ("argscan_float_zero_order", "better = want_max ? total_less(b, v) : total_less(v, b);", "better = want_max ? (v > b) : (v < b);", 0),
     ("argscan_excl_after", "if (exclusive) y[j] = best;\n        int better;", "int better;", 0),
+    ("bfs_level_not_incremented", "level[v] = level[u] + 1;", "level[v] = level[u];", 0),
+    ("bfs_stack_order", "int32_t u = queue[head++];", "int32_t u = queue[--tail];", 0),
+    ("bfs_source_level_one", "level[src] = 0;", "level[src] = 1;", 0),
+    ("bfs_first_edge_skipped", "for (int64_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e) {", "for (int64_t e = row_ptr[u] + 1; e < row_ptr[u + 1]; ++e) {", 0),
     ("excl_float_stale_abs", "if (absum) absum[j] = a;\n        }\n        neumaier_add(&s, &c, v);\n        a += fabs(v);\n        if (!exclusive) {\n            y64[j] = s + c;",
      "if (absum) absum[j] = a + fabs(v);\n        }\n        neumaier_add(&s, &c, v);\n        a += fabs(v);\n        if (!exclusive) {\n            y64[j] = s + c;", 0),
 ]

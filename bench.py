@@ -28,8 +28,8 @@ Before the warmup steps of every measurement the device runs the same call
 for about SETTLE_S seconds (untimed), so that clocks have left the idle state
 that input generation or a host-side oracle check leaves behind.
 
-Progress lines go to stderr.  ``--gpus N`` with N > 1 is refused: this build
-runs on one GPU.
+Progress lines go to stderr.  ``--gpus N`` with N > 1 is refused: the scan runs on
+one GPU and is not sharded across GPUs.
 """
 from __future__ import annotations
 
@@ -433,6 +433,30 @@ def _pool_slice(pools, req, rng):
     return pool[off:off + n]
 
 
+def bench_chain(binding, x_host, steps):
+    """The paper's prefix chain (every block waits for its predecessor's
+    inclusive prefix) against the default window hand-off, same shape and
+    input: time per launch, and the time per hand-off in the chain."""
+    import torch
+
+    xd = to_device(x_host, "int32")
+    n = xd.shape[0]
+    y = torch.empty_like(xd)
+    binding.inclusive(xd, "add", out=y)
+    window = y.clone()
+    p = binding.Params(0, 0, 0, binding.HANDOFF_CHAIN)
+    ms, per = time_steps(lambda: binding.inclusive(xd, "add", out=y, params=p), steps, 1)
+    binding.lscan_check(torch.cuda.current_stream().cuda_stream)
+    info = binding.lscan_last_launch()
+    e = rate_entry(8 * n, n, ms, per)
+    e.update({"n": n, "num_blocks": info.num_blocks, "grid": info.grid, "block_threads": info.block_threads,
+              "us_per_handoff": round(ms * 1e3 / info.num_blocks, 4),
+              "bit_equal_to_window": bool(torch.equal(y, window))})
+    del xd, y, window
+    torch.cuda.empty_cache()
+    return e
+
+
 def bench_serving(binding, workloads, seconds: float, rate: float):
     """Poisson trace through the request server, and the same trace as
     serial plain launches (one launch + synchronize per request, FIFO)."""
@@ -571,7 +595,7 @@ def main(argv=None) -> int:
 
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the scan is not sharded "
-              "across GPUs in this build", file=sys.stderr)
+              "across GPUs", file=sys.stderr)
         return 2
     if "WORLD_SIZE" in os.environ and int(os.environ["WORLD_SIZE"]) > 1:
         print("bench.py runs on one GPU only", file=sys.stderr)

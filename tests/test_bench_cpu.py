@@ -1,0 +1,51 @@
+"""Host-side checks of bench.py that need no GPU: every module-level name
+the script uses is defined (a missing helper would only surface at the end of
+a long GPU run), and a request for more than one GPU exits with a message."""
+import ast
+import builtins
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+BENCH = os.path.join(ROOT, "bench.py")
+
+
+def _bound_names(tree):
+    names = set(dir(builtins))
+    for node in ast.walk(tree):
+        if isinstance(node, (ast.FunctionDef, ast.AsyncFunctionDef, ast.ClassDef)):
+            names.add(node.name)
+            a = node.args if not isinstance(node, ast.ClassDef) else None
+            if a is not None:
+                for arg in a.posonlyargs + a.args + a.kwonlyargs:
+                    names.add(arg.arg)
+                for arg in (a.vararg, a.kwarg):
+                    if arg is not None:
+                        names.add(arg.arg)
+        elif isinstance(node, ast.Lambda):
+            for arg in node.args.args + node.args.kwonlyargs:
+                names.add(arg.arg)
+        elif isinstance(node, (ast.Import, ast.ImportFrom)):
+            for al in node.names:
+                names.add((al.asname or al.name).split(".")[0])
+        elif isinstance(node, ast.Name) and isinstance(node.ctx, (ast.Store, ast.Del)):
+            names.add(node.id)
+        elif isinstance(node, ast.ExceptHandler) and node.name:
+            names.add(node.name)
+        elif isinstance(node, (ast.Global, ast.Nonlocal)):
+            names.update(node.names)
+    return names
+
+
+def test_bench_names_are_defined():
+    tree = ast.parse(open(BENCH).read())
+    bound = _bound_names(tree) | {"__file__", "__name__"}
+    used = {n.id for n in ast.walk(tree) if isinstance(n, ast.Name) and isinstance(n.ctx, ast.Load)}
+    assert not sorted(used - bound), f"bench.py uses undefined names: {sorted(used - bound)}"
+
+
+def test_bench_refuses_several_gpus():
+    r = subprocess.run([sys.executable, BENCH, "--gpus", "2"], capture_output=True, text=True, timeout=120, cwd=ROOT)
+    assert r.returncode != 0
+    assert "one GPU" in (r.stdout + r.stderr)

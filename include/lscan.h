@@ -297,6 +297,56 @@ lscan_status lscan_radix_offsets(const void *keys, int64_t n, lscan_dtype dt,
                                  void *stream);
 
 /*
+ * Breadth-first search on the device, the graph search that Section 6 names
+ * as the next use of the paper's inter-block hand-off (Section 4.3): one
+ * persistent launch, the frontier of each level cut into chunks taken
+ * cyclically by a co-resident grid; each chunk claims the undiscovered
+ * endpoints of its edges (compare-and-swap on a per-vertex claim word),
+ * publishes how many it found in an epoch-tagged flag word, and obtains
+ * where they go in the next frontier from the counts published before it
+ * (the window fold of the scan) -- no shared queue-tail counter.  Levels
+ * end with a grid barrier made of the same flag words.
+ *   row_offsets  device array of num_vertices + 1 int64, 8-byte aligned:
+ *                the edges of vertex u are cols[row_offsets[u] ..
+ *                row_offsets[u + 1]) (a directed graph in compressed rows)
+ *   cols         device array of num_edges int32 (may be null if
+ *                num_edges == 0)
+ *   num_vertices 0 .. 2^31 - 2; 0 does nothing (stats, if given, zeroed)
+ *   source       0 .. num_vertices - 1
+ *   levels       device array of num_vertices int32 (output): the number of
+ *                edges on a shortest path from source, -1 if unreachable;
+ *                unique, so exact
+ *   parents      device array of num_vertices int32 (output), or null: a
+ *                breadth-first tree -- parents[source] = source, for every
+ *                other reached v an edge parents[v] -> v with
+ *                levels[parents[v]] = levels[v] - 1, -1 if unreached
+ *                (which parent is chosen is not fixed: any valid one)
+ *   stats        device array of 4 int64 (output), or null: number of levels,
+ *                vertices reached, edges scanned (the out-degrees of the
+ *                reached vertices), malformed entries met (a row range
+ *                outside [0, num_edges] or a column outside [0,
+ *                num_vertices); those are skipped, never dereferenced)
+ * Outputs may not overlap the inputs or each other.  The library keeps a
+ * per-stream workspace of about 16 bytes per vertex.  Not capturable into a
+ * HIP graph (LSCAN_ERR_UNSUPPORTED while the stream captures: each launch
+ * takes fresh flag tags from the host).  A wait that outlasts the watchdog
+ * stops the whole grid; the next lscan_check on the stream reports
+ * LSCAN_ERR_TIMEOUT and the outputs are undefined.
+ * lscan_bfs_with_params honours groups_per_cu only (a tile shape or the
+ * chain hand-off: LSCAN_ERR_UNSUPPORTED).
+ */
+lscan_status lscan_bfs(const int64_t *row_offsets, const int32_t *cols,
+                       int64_t num_vertices, int64_t num_edges, int32_t source,
+                       int32_t *levels, int32_t *parents, int64_t *stats,
+                       void *stream);
+lscan_status lscan_bfs_with_params(const int64_t *row_offsets,
+                                   const int32_t *cols, int64_t num_vertices,
+                                   int64_t num_edges, int32_t source,
+                                   int32_t *levels, int32_t *parents,
+                                   int64_t *stats, const lscan_params *p,
+                                   void *stream);
+
+/*
  * Graph-captured launches.  lscan_graph_create_* prepares one segmented or
  * batched launch (workspace, co-residency test, descriptor upload, all on a
  * private stream, synchronously) and captures it into a hipGraph that owns

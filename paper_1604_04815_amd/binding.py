@@ -99,6 +99,8 @@ SIGNATURES = {
     "lscan_compact": ([_vp, _vp, _vp, _vp, _i64, _i32, _vp], _i32),
     "lscan_radix_offsets": ([_vp, _i64, _i32, _i32, _i32, _i64, _vp, _vp], _i32),
     "lscan_compact_with_params": ([_vp, _vp, _vp, _vp, _i64, _i32, ctypes.POINTER(Params), _vp], _i32),
+    "lscan_bfs": ([_vp, _vp, _i64, _i64, _i32, _vp, _vp, _vp, _vp], _i32),
+    "lscan_bfs_with_params": ([_vp, _vp, _i64, _i64, _i32, _vp, _vp, _vp, ctypes.POINTER(Params), _vp], _i32),
     "lscan_graph_create_segmented": ([_vp, _vp, _i64, _vp, _i64, _i32, _i32, _u32, ctypes.POINTER(Params),
                                       ctypes.POINTER(_vp)], _i32),
     "lscan_graph_create_batched": ([ctypes.POINTER(Array), _i64, _i32, _i32, _u32, ctypes.POINTER(Params),
@@ -455,6 +457,50 @@ def radix_offsets(keys, shift, bits, block_items, out=None, stream=None):
                                       out.data_ptr(), _stream(stream)), "lscan_radix_offsets")
     return out.view(1 << bits, m)
 
+
+def bfs(row_offsets, cols, source, levels=None, parents=True, stats=None, stream=None,
+        params: Params | None = None):
+    """Breadth-first search on the device over a directed graph in compressed
+    rows (``row_offsets``: int64, V + 1 entries; ``cols``: int32, E
+    entries; both device tensors).  Returns ``(levels, parents, stats)``:
+    int32 levels (-1 unreached); int32 parents of a breadth-first tree, or
+    None when ``parents`` is False; an int64 device tensor of 4 (levels,
+    vertices reached, edges scanned, malformed entries)."""
+    import torch
+
+    _flat(row_offsets, "row_offsets")
+    _flat(cols, "cols")
+    if row_offsets.dtype != torch.int64 or cols.dtype != torch.int32:
+        raise TypeError("row_offsets must be int64 and cols int32")
+    nv = row_offsets.shape[0] - 1
+    if nv < 0:
+        raise ValueError("row_offsets needs V + 1 >= 1 entries")
+    dev = row_offsets.device
+
+    def out_vec(t, name):
+        if t is None:
+            return torch.empty(nv, dtype=torch.int32, device=dev)
+        _flat(t, name)
+        if t.dtype != torch.int32 or t.shape[0] != nv:
+            raise ValueError(f"{name} must be int32 with one entry per vertex")
+        return t
+
+    levels = out_vec(levels, "levels")
+    par = None
+    if parents is not False and parents is not None:
+        par = out_vec(None if parents is True else parents, "parents")
+    if stats is None:
+        stats = torch.empty(4, dtype=torch.int64, device=dev)
+    else:
+        _flat(stats, "stats")
+        if stats.dtype != torch.int64 or stats.shape[0] != 4:
+            raise ValueError("stats must be int64 with 4 entries")
+    ne = cols.shape[0]
+    p = ctypes.byref(params) if params is not None else None
+    _check(load().lscan_bfs_with_params(row_offsets.data_ptr(), cols.data_ptr() if ne else None, nv, ne,
+                                        int(source), levels.data_ptr(), par.data_ptr() if par is not None else None,
+                                        stats.data_ptr(), p, _stream(stream)), "lscan_bfs")
+    return levels, par, stats
 
 class Server:
     """Request server (lscan_server_*): submit device arrays, poll tickets."""

@@ -12,6 +12,7 @@
 #include <new>
 #include <utility>
 
+#include "bfs_kernel.hpp"
 #include "kernel_table.hpp"
 #include "radix_kernel.hpp"
 #include "lscan.h"
@@ -71,6 +72,10 @@ struct DeviceInfo {
     // count that failed the test (0: none failed)
     int resident_ok[kNumModes][kNumOpCodes][kNumShapes];
     int resident_fail[kNumModes][kNumOpCodes][kNumShapes];
+    // the breadth-first search kernel: occupancy and co-residency results
+    int bfs_occupancy = -1;
+    int bfs_resident_ok = 0;
+    int bfs_resident_fail = 0;
 };
 
 // Flag slots, control words and (batched launches) array descriptors of one
@@ -488,11 +493,9 @@ lscan_status test_residency_locked(const KernelEntry& k, int cu_count, int group
 
 // Largest groups-per-CU count <= want whose grid is known (or now tested)
 // to be resident at once.
-lscan_status resident_groups_locked(DeviceInfo* info, int mode, int oc, int shape, const KernelEntry& k,
-                                    int want, Workspace* ws, hipStream_t stream, int* out)
+lscan_status resident_groups_core(DeviceInfo* info, const KernelEntry& k, int want, Workspace* ws,
+                                  hipStream_t stream, int& good, int& bad, int* out)
 {
-    int& good = info->resident_ok[mode][oc][shape];
-    int& bad = info->resident_fail[mode][oc][shape];
     int g = want;
     if (bad > 0 && g >= bad) g = bad - 1;
     while (g > good) {
@@ -509,6 +512,13 @@ lscan_status resident_groups_locked(DeviceInfo* info, int mode, int oc, int shap
     if (g < 1) return LSCAN_ERR_DEVICE;  // not even one workgroup per CU is resident
     *out = g;
     return LSCAN_OK;
+}
+
+lscan_status resident_groups_locked(DeviceInfo* info, int mode, int oc, int shape, const KernelEntry& k,
+                                    int want, Workspace* ws, hipStream_t stream, int* out)
+{
+    return resident_groups_core(info, k, want, ws, stream, info->resident_ok[mode][oc][shape],
+                                info->resident_fail[mode][oc][shape], out);
 }
 
 // Everything needed to enqueue one launch.
@@ -655,6 +665,45 @@ lscan_status plan_locked(const Request& r, int dev, Workspace* ws_fixed, hipStre
     return LSCAN_OK;
 }
 
+// Cross-stream ordering of one persistent launch on `stream` (see
+// DeviceOrder); *out receives the device's record, to be passed to
+// order_after_locked once the launch is enqueued.  Called with g_mu held.
+lscan_status order_before_locked(int dev, hipStream_t stream, DeviceOrder** out)
+{
+    DeviceOrder* order = &g_order[dev];
+    hipError_t e = hipSuccess;
+    // (the capture query is made only on a stream switch: it is not free)
+    if (order->any && order->last != stream && !capturing(stream)) {  // before the co-residency test, too
+        if (!order->multi) {
+            if (!order->done) {
+                e = hipEventCreateWithFlags(&order->done, hipEventDisableTiming);
+                if (e != hipSuccess) {
+                    order->done = nullptr;
+                    return device_error(e);
+                }
+            }
+            e = hipDeviceSynchronize();  // once: the previous stream's launches have no event
+            order->multi = true;
+        } else {
+            e = hipStreamWaitEvent(stream, order->done, 0);
+        }
+        if (e != hipSuccess) return device_error(e);
+    }
+    order->any = true;
+    order->last = stream;
+    *out = order;
+    return LSCAN_OK;
+}
+
+lscan_status order_after_locked(DeviceOrder* order, hipStream_t stream)
+{
+    if (order && order->multi && !capturing(stream)) {
+        const hipError_t e = hipEventRecord(order->done, stream);
+        if (e != hipSuccess) return device_error(e);
+    }
+    return LSCAN_OK;
+}
+
 lscan_status run(const Request& r, void* stream_ptr)
 {
     if (r.empty) return LSCAN_OK;
@@ -664,40 +713,193 @@ lscan_status run(const Request& r, void* stream_ptr)
     if (e != hipSuccess) return device_error(e);
     std::lock_guard<std::mutex> lock(g_mu);
     DeviceOrder* order = nullptr;
+    lscan_status st = LSCAN_OK;
     if (r.ordered) {
-        order = &g_order[dev];
-        // (the capture query is made only on a stream switch: it is not free)
-        if (order->any && order->last != stream && !capturing(stream)) {  // before the co-residency test, too
-            if (!order->multi) {
-                if (!order->done) {
-                    e = hipEventCreateWithFlags(&order->done, hipEventDisableTiming);
-                    if (e != hipSuccess) {
-                        order->done = nullptr;
-                        return device_error(e);
-                    }
-                }
-                e = hipDeviceSynchronize();  // once: the previous stream's launches have no event
-                order->multi = true;
-            } else {
-                e = hipStreamWaitEvent(stream, order->done, 0);
-            }
-            if (e != hipSuccess) return device_error(e);
-        }
-        order->any = true;
-        order->last = stream;
+        st = order_before_locked(dev, stream, &order);
+        if (st != LSCAN_OK) return st;
     }
     Plan plan;
     Workspace* ws = nullptr;
-    lscan_status st = plan_locked(r, dev, nullptr, stream, &plan, &ws);
+    st = plan_locked(r, dev, nullptr, stream, &plan, &ws);
     if (st != LSCAN_OK) return st;
     e = plan.k->launch(plan.a, plan.grid, stream);
     if (e != hipSuccess) return device_error(e);
     ws->launches++;
-    if (order && order->multi && !capturing(stream)) {
-        e = hipEventRecord(order->done, stream);
+    return order_after_locked(order, stream);
+}
+
+// ---------------------------------------------------------------------------
+// Breadth-first search (bfs_kernel.hip)
+// ---------------------------------------------------------------------------
+
+// Device state of the search on one stream, in one allocation: the flag
+// region (per-chunk words, per-workgroup arrival words, the release word and
+// the abort word; zero when allocated), per-workgroup counters, the claim
+// words and the two frontier queues, sized for the largest graph seen.
+struct BfsWorkspace {
+    char* mem = nullptr;
+    int64_t cap_v = 0;
+    int cap_grid = 0;
+    size_t flag_bytes = 0;
+    uint64_t* slots = nullptr;
+    uint64_t* arrive = nullptr;
+    uint64_t* go = nullptr;
+    uint32_t* abort_word = nullptr;
+    int64_t* partial = nullptr;
+    uint64_t* claim = nullptr;
+    int32_t* queue0 = nullptr;
+    int32_t* queue1 = nullptr;
+    uint64_t next_tag = 0;  // the next launch's tags start above this
+};
+std::map<std::pair<int, hipStream_t>, BfsWorkspace> g_bfs_ws;
+
+// Workgroups per CU the search asks for (the occupancy limit and the
+// co-residency test may lower it).
+constexpr int kBfsGroupsPerCu = 4;
+
+void free_bfs_workspace(BfsWorkspace& ws)
+{
+    if (ws.mem) (void)hipFree(ws.mem);
+    ws = BfsWorkspace();
+}
+
+lscan_status ensure_bfs_workspace(BfsWorkspace& ws, hipStream_t stream, int64_t nv, int grid)
+{
+    if (ws.mem && ws.cap_v >= nv && ws.cap_grid >= grid) return LSCAN_OK;
+    hipError_t e;
+    if (ws.mem) {
+        e = hipStreamSynchronize(stream);  // earlier searches on this stream still use it
         if (e != hipSuccess) return device_error(e);
+        free_bfs_workspace(ws);
     }
+    const int64_t v = nv;
+    const int64_t chunks = (v + kBfsChunk - 1) / kBfsChunk;
+    const size_t flag_words = size_t(chunks) + size_t(grid) + 2;  // + release word + abort word
+    const size_t bytes = flag_words * 8 + size_t(grid) * 16 + size_t(v) * 8 + size_t(v) * 8;
+    e = hipMalloc(reinterpret_cast<void**>(&ws.mem), bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        ws.mem = nullptr;
+        return LSCAN_ERR_NO_MEMORY;
+    }
+    char* p = ws.mem;
+    ws.slots = reinterpret_cast<uint64_t*>(p);
+    ws.arrive = ws.slots + chunks;
+    ws.go = ws.arrive + grid;
+    ws.abort_word = reinterpret_cast<uint32_t*>(ws.go + 1);
+    ws.flag_bytes = flag_words * 8;
+    p += ws.flag_bytes;
+    ws.partial = reinterpret_cast<int64_t*>(p);
+    p += size_t(grid) * 16;
+    ws.claim = reinterpret_cast<uint64_t*>(p);
+    p += size_t(v) * 8;
+    ws.queue0 = reinterpret_cast<int32_t*>(p);
+    ws.queue1 = ws.queue0 + v;
+    ws.cap_v = v;
+    ws.cap_grid = grid;
+    ws.next_tag = 0;
+    e = hipMemsetAsync(ws.mem, 0, ws.flag_bytes, stream);
+    if (e != hipSuccess) return device_error(e);
     return LSCAN_OK;
+}
+
+// Co-residency test of the search kernel through the scan's test driver.
+hipError_t bfs_residency_launch(const ScanArgs& sa, int grid, hipStream_t stream)
+{
+    BfsArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.ctrl = sa.ctrl;
+    a.spin_limit = sa.spin_limit;
+    a.residency_check = 1;
+    return launch_bfs(a, grid, stream);
+}
+
+lscan_status bfs_run(const int64_t* row, const int32_t* col, int64_t nv, int64_t ne, int32_t src, int32_t* level,
+                     int32_t* parent, int64_t* stats, const lscan_params* p, hipStream_t stream)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return device_error(e);
+    if (capturing(stream)) return LSCAN_ERR_UNSUPPORTED;  // each launch takes fresh tags from the host
+    std::lock_guard<std::mutex> lock(g_mu);
+    DeviceOrder* order = nullptr;
+    lscan_status st = order_before_locked(dev, stream, &order);
+    if (st != LSCAN_OK) return st;
+    DeviceInfo* info = nullptr;
+    st = device_info_locked(dev, &info);
+    if (st != LSCAN_OK) return st;
+    if (info->bfs_occupancy < 0) {
+        int v = 0;
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, bfs_kernel_func(), kBfsThreads, 0);
+        if (e != hipSuccess) return device_error(e);
+        info->bfs_occupancy = v;
+    }
+    if (info->bfs_occupancy <= 0) return LSCAN_ERR_UNSUPPORTED;
+    Workspace* ws = nullptr;
+    st = workspace_locked(dev, stream, 64, 0, &ws);  // the stream's control words (timeout flag)
+    if (st != LSCAN_OK) return st;
+    int want = (p && p->groups_per_cu > 0) ? p->groups_per_cu : kBfsGroupsPerCu;
+    want = std::min(want, info->bfs_occupancy);
+    KernelEntry k;
+    std::memset(&k, 0, sizeof(k));
+    k.func = bfs_kernel_func();
+    k.launch = bfs_residency_launch;
+    k.block_threads = kBfsThreads;
+    int groups = 0;
+    st = resident_groups_core(info, k, want, ws, stream, info->bfs_resident_ok, info->bfs_resident_fail, &groups);
+    if (st != LSCAN_OK) return st;
+    // no more workgroups than the largest frontier can keep busy
+    const int64_t chunks = (nv + kBfsChunk - 1) / kBfsChunk;
+    const int grid = int(std::max<int64_t>(1, std::min<int64_t>(int64_t(groups) * info->cu_count, chunks)));
+
+    BfsWorkspace& bw = g_bfs_ws[std::make_pair(dev, stream)];
+    st = ensure_bfs_workspace(bw, stream, nv, grid);
+    if (st != LSCAN_OK) return st;
+    // tags base + 1 .. base + nv + 2: the start barrier and at most nv levels
+    const uint64_t need = uint64_t(nv) + 3;
+    if (bw.next_tag + need >= uint64_t(UINT32_MAX)) {
+        e = hipMemsetAsync(bw.mem, 0, bw.flag_bytes, stream);
+        if (e != hipSuccess) return device_error(e);
+        bw.next_tag = 0;
+    }
+    BfsArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.row = row;
+    a.col = col;
+    a.nv = nv;
+    a.ne = ne;
+    a.src = src;
+    a.level = level;
+    a.parent = parent;
+    a.stats = stats;
+    a.claim = bw.claim;
+    a.queue0 = bw.queue0;
+    a.queue1 = bw.queue1;
+    a.slots = bw.slots;
+    a.arrive = bw.arrive;
+    a.partial = bw.partial;
+    a.go = bw.go;
+    a.abort_word = bw.abort_word;
+    a.timeout_flag = ws->ctrl + 2;
+    a.ctrl = ws->ctrl;
+    a.spin_limit = info->spin_limit;
+    a.base_tag = uint32_t(bw.next_tag);
+    a.residency_check = 0;
+    bw.next_tag += need;
+    e = launch_bfs(a, grid, stream);
+    if (e != hipSuccess) return device_error(e);
+
+    t_last_launch = lscan_launch_info{};
+    t_last_launch.n = nv;
+    t_last_launch.num_blocks = chunks;
+    t_last_launch.tile_elems = kBfsChunk;
+    t_last_launch.grid = grid;
+    t_last_launch.block_threads = kBfsThreads;
+    t_last_launch.slot_words = 1;
+    t_last_launch.vector_path = 0;
+    t_last_launch.groups_per_cu = groups;
+    t_last_launch.occupancy = info->bfs_occupancy;
+    return order_after_locked(order, stream);
 }
 
 }  // namespace
@@ -1043,6 +1245,51 @@ lscan_status lscan_radix_offsets(const void* keys, int64_t n, lscan_dtype dt, in
     return st != LSCAN_OK ? st : run(r, stream);
 }
 
+lscan_status lscan_bfs_with_params(const int64_t* row_offsets, const int32_t* cols, int64_t num_vertices,
+                                   int64_t num_edges, int32_t source, int32_t* levels, int32_t* parents,
+                                   int64_t* stats, const lscan_params* p, void* stream)
+{
+    if (num_vertices < 0 || num_vertices > int64_t(INT32_MAX) - 1 || num_edges < 0 ||
+        num_edges > (INT64_MAX / 16))
+        return LSCAN_ERR_INVALID_ARG;
+    if (p) {
+        lscan_status st = check_params(p);
+        if (st != LSCAN_OK) return st;
+        if (p->block_threads != 0 || p->vectors_per_lane != 0 || p->handoff != LSCAN_HANDOFF_WINDOW)
+            return LSCAN_ERR_UNSUPPORTED;
+    }
+    auto mis = [](const void* q, uintptr_t al) { return reinterpret_cast<uintptr_t>(q) % al != 0; };
+    if (stats && mis(stats, 8)) return LSCAN_ERR_INVALID_ARG;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (num_vertices == 0) {
+        if (stats) {
+            const hipError_t e = hipMemsetAsync(stats, 0, 4 * sizeof(int64_t), s);
+            if (e != hipSuccess) return device_error(e);
+        }
+        return LSCAN_OK;
+    }
+    if (source < 0 || int64_t(source) >= num_vertices) return LSCAN_ERR_INVALID_ARG;
+    if (!row_offsets || !levels || (num_edges > 0 && !cols)) return LSCAN_ERR_INVALID_ARG;
+    if (mis(row_offsets, 8) || mis(cols, 4) || mis(levels, 4) || mis(parents, 4)) return LSCAN_ERR_INVALID_ARG;
+    const int64_t rb = (num_vertices + 1) * 8, cb = num_edges * 4, vb = num_vertices * 4;
+    if (ranges_overlap(levels, vb, row_offsets, rb) || ranges_overlap(levels, vb, cols, cb))
+        return LSCAN_ERR_INVALID_ARG;
+    if (parents && (ranges_overlap(parents, vb, row_offsets, rb) || ranges_overlap(parents, vb, cols, cb) ||
+                    ranges_overlap(parents, vb, levels, vb)))
+        return LSCAN_ERR_INVALID_ARG;
+    if (stats && (ranges_overlap(stats, 32, row_offsets, rb) || ranges_overlap(stats, 32, cols, cb) ||
+                  ranges_overlap(stats, 32, levels, vb) || (parents && ranges_overlap(stats, 32, parents, vb))))
+        return LSCAN_ERR_INVALID_ARG;
+    return bfs_run(row_offsets, cols, num_vertices, num_edges, source, levels, parents, stats, p, s);
+}
+
+lscan_status lscan_bfs(const int64_t* row_offsets, const int32_t* cols, int64_t num_vertices, int64_t num_edges,
+                       int32_t source, int32_t* levels, int32_t* parents, int64_t* stats, void* stream)
+{
+    return lscan_bfs_with_params(row_offsets, cols, num_vertices, num_edges, source, levels, parents, stats,
+                                 nullptr, stream);
+}
+
 lscan_status lscan_last_launch(lscan_launch_info* out)
 {
     if (!out) return LSCAN_ERR_INVALID_ARG;
@@ -1089,6 +1336,14 @@ lscan_status lscan_release_workspaces(void)
         if (it->first.first == dev) {
             free_workspace(it->second);
             it = g_ws.erase(it);
+        } else {
+            ++it;
+        }
+    }
+    for (auto it = g_bfs_ws.begin(); it != g_bfs_ws.end();) {
+        if (it->first.first == dev) {
+            free_bfs_workspace(it->second);
+            it = g_bfs_ws.erase(it);
         } else {
             ++it;
         }

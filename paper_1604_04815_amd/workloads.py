@@ -127,3 +127,96 @@ def request_trace(rate_hz: float, duration_s: float, seed: int,
         })
         k += 1
     return out
+
+
+# ---------------------------------------------------------------------------
+# Graphs for the breadth-first search
+# ---------------------------------------------------------------------------
+#
+# ``rmat_edges`` draws a Kronecker (R-MAT) edge list with the quadrant
+# probabilities of the Graph500 generator (A, B, C, D = 0.57, 0.19, 0.19,
+# 0.05): each of the ``scale`` bit levels of an edge picks one quadrant; the
+# vertex labels are then permuted at random, so degree does not follow the
+# label.  ``csr_from_edges`` lays an edge list out in compressed rows
+# (optionally with every edge in both directions); self loops and repeated
+# edges are kept, as the generator makes them.
+
+RMAT_ABC = (0.57, 0.19, 0.19)
+
+
+def rmat_edges(scale: int, edge_factor: int, seed: int, abc=RMAT_ABC) -> tuple[np.ndarray, np.ndarray]:
+    """edge_factor * 2^scale directed edges (src, dst) as int32 arrays over
+    2^scale vertices."""
+    a, b, c = abc
+    g = rng(seed)
+    m = int(edge_factor) << int(scale)
+    src = np.zeros(m, dtype=np.int32)
+    dst = np.zeros(m, dtype=np.int32)
+    for level in range(int(scale)):
+        r = g.random(m, dtype=np.float32)
+        down = r >= np.float32(a + b)                                          # quadrants C, D
+        right = (r >= np.float32(a)) & ~down | (r >= np.float32(a + b + c))    # quadrants B, D
+        src |= down.astype(np.int32) << level
+        dst |= right.astype(np.int32) << level
+    perm = g.permutation(1 << int(scale)).astype(np.int32)
+    return perm[src], perm[dst]
+
+
+def csr_from_edges(src: np.ndarray, dst: np.ndarray, num_vertices: int,
+                   symmetric: bool = True) -> tuple[np.ndarray, np.ndarray]:
+    """(row_offsets int64[V + 1], cols int32[E]) of the edge list, rows in
+    vertex order, each row's columns sorted."""
+    src = np.asarray(src, dtype=np.int64)
+    dst = np.asarray(dst, dtype=np.int64)
+    if symmetric:
+        src, dst = np.concatenate([src, dst]), np.concatenate([dst, src])
+    order = np.argsort(src * int(num_vertices) + dst, kind="stable")
+    cols = dst[order].astype(np.int32)
+    counts = np.bincount(src, minlength=int(num_vertices)).astype(np.int64)
+    row = np.zeros(int(num_vertices) + 1, dtype=np.int64)
+    np.cumsum(counts, out=row[1:])
+    return row, cols
+
+
+def uniform_random_edges(num_vertices: int, num_edges: int, seed: int) -> tuple[np.ndarray, np.ndarray]:
+    """num_edges directed edges with both ends uniform over the vertices."""
+    g = rng(seed)
+    return (g.integers(0, num_vertices, num_edges, dtype=np.int32),
+            g.integers(0, num_vertices, num_edges, dtype=np.int32))
+
+
+def rmat_csr_torch(scale: int, edge_factor: int, seed: int, device="cuda", abc=RMAT_ABC):
+    """The recipe of ``rmat_edges`` + ``csr_from_edges(symmetric=True)``
+    drawn with torch's generator on ``device`` (seconds instead of minutes at
+    2^22 vertices; a different random stream than the numpy version).
+    Returns (row_offsets int64[V + 1], cols int32[E]) on ``device``."""
+    import torch
+
+    a, b, c = abc
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    m = int(edge_factor) << int(scale)
+    nv = 1 << int(scale)
+    src = torch.zeros(m, dtype=torch.int64, device=device)
+    dst = torch.zeros(m, dtype=torch.int64, device=device)
+    for level in range(int(scale)):
+        r = torch.rand(m, generator=g, device=device)
+        down = r >= (a + b)
+        right = ((r >= a) & ~down) | (r >= (a + b + c))
+        src |= down.to(torch.int64) << level
+        dst |= right.to(torch.int64) << level
+        del r, down, right
+    perm = torch.randperm(nv, generator=g, device=device)
+    src, dst = perm[src], perm[dst]
+    s2 = torch.cat([src, dst])
+    d2 = torch.cat([dst, src])
+    del src, dst
+    key = s2 * nv + d2
+    del s2, d2
+    key, _ = torch.sort(key)
+    rows = key // nv
+    cols = (key - rows * nv).to(torch.int32)
+    counts = torch.bincount(rows, minlength=nv)
+    row_offsets = torch.zeros(nv + 1, dtype=torch.int64, device=device)
+    torch.cumsum(counts, 0, out=row_offsets[1:])
+    return row_offsets, cols

@@ -270,3 +270,41 @@ def test_argscan_validation(lib):
     tab = (binding.Array * 1)(binding.Array(FAKE_X, FAKE_Y, 8))
     assert lib.lscan_batched(tab, 1, binding.I32, binding.ARGMIN, 0, None) == binding.ERR_UNSUPPORTED
 
+
+
+def test_bfs_validation(lib):
+    f = lib.lscan_bfs
+    row, col, lev, par, st = FAKE_X, FAKE_X + (1 << 16), FAKE_Y, FAKE_Y + (1 << 16), FAKE_Y + (1 << 17)
+    ok_args = dict(row=row, col=col, nv=100, ne=400, src=0, lev=lev, par=par, st=st)
+
+    def call(**kw):
+        a = dict(ok_args, **kw)
+        return f(a["row"], a["col"], a["nv"], a["ne"], a["src"], a["lev"], a["par"], a["st"], None)
+
+    assert call(nv=-1) == binding.ERR_INVALID_ARG
+    assert call(nv=1 << 31) == binding.ERR_INVALID_ARG        # vertex ids are int32
+    assert call(ne=-1) == binding.ERR_INVALID_ARG
+    assert call(src=-1) == binding.ERR_INVALID_ARG
+    assert call(src=100) == binding.ERR_INVALID_ARG
+    assert call(row=None) == binding.ERR_INVALID_ARG
+    assert call(col=None) == binding.ERR_INVALID_ARG            # edges but no columns
+    assert call(lev=None) == binding.ERR_INVALID_ARG
+    assert call(row=row + 4) == binding.ERR_INVALID_ARG          # int64 offsets: 8-byte aligned
+    assert call(col=col + 2) == binding.ERR_INVALID_ARG
+    assert call(lev=lev + 2) == binding.ERR_INVALID_ARG
+    assert call(par=par + 1) == binding.ERR_INVALID_ARG
+    assert call(st=st + 4) == binding.ERR_INVALID_ARG
+    # outputs over inputs or over each other
+    assert call(lev=row + 64) == binding.ERR_INVALID_ARG
+    assert call(lev=col + 64) == binding.ERR_INVALID_ARG
+    assert call(par=lev + 200) == binding.ERR_INVALID_ARG
+    assert call(st=lev + 8) == binding.ERR_INVALID_ARG
+    # nothing to do: no vertices and no stats
+    assert call(nv=0, ne=0, src=0, st=None) == binding.OK
+    # parameters: only groups_per_cu applies
+    g = lib.lscan_bfs_with_params
+    for p, status in ((binding.Params(256, 8, 0, 0), binding.ERR_UNSUPPORTED),
+                      (binding.Params(0, 0, 0, binding.HANDOFF_CHAIN), binding.ERR_UNSUPPORTED),
+                      (binding.Params(0, 0, -1, 0), binding.ERR_INVALID_ARG),
+                      (binding.Params(0, 0, 0, 7), binding.ERR_INVALID_ARG)):
+        assert g(row, col, 100, 400, 0, lev, par, st, ctypes.byref(p), None) == status, p

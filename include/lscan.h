@@ -299,18 +299,22 @@ lscan_status lscan_radix_offsets(const void *keys, int64_t n, lscan_dtype dt,
 /*
  * Breadth-first search on the device, the graph search that Section 6 names
  * as the next use of the paper's inter-block hand-off (Section 4.3): one
- * persistent launch, the frontier of each level cut into chunks taken
- * cyclically by a co-resident grid; each chunk claims the undiscovered
- * endpoints of its edges (compare-and-swap on a per-vertex claim word),
- * publishes how many it found in an epoch-tagged flag word, and obtains
- * where they go in the next frontier from the counts published before it
- * (the window fold of the scan) -- no shared queue-tail counter.  Levels
- * end with a grid barrier made of the same flag words.
+ * persistent launch runs the whole search.  The edges of each level's
+ * frontier are cut into equal chunks taken cyclically by a co-resident
+ * grid; each chunk claims the undiscovered endpoints of its edges
+ * (compare-and-swap on a per-vertex claim word), publishes how many
+ * vertices and edges it found in epoch-tagged flag words, and obtains where
+ * they go in the next frontier from the values published before it (the
+ * window fold of the scan) -- no shared queue-tail counter.  Levels end
+ * with a grid barrier made of the same flag words.
  *   row_offsets  device array of num_vertices + 1 int64, 8-byte aligned:
  *                the edges of vertex u are cols[row_offsets[u] ..
- *                row_offsets[u + 1]) (a directed graph in compressed rows)
+ *                row_offsets[u + 1]) (a directed graph in compressed rows);
+ *                expected non-decreasing: where it decreases anywhere the
+ *                graph is not searched (every level and parent -1, stats
+ *                {0, 0, 0, number of decreasing steps})
  *   cols         device array of num_edges int32 (may be null if
- *                num_edges == 0)
+ *                num_edges == 0); num_edges < 2^42
  *   num_vertices 0 .. 2^31 - 2; 0 does nothing (stats, if given, zeroed)
  *   source       0 .. num_vertices - 1
  *   levels       device array of num_vertices int32 (output): the number of
@@ -323,15 +327,16 @@ lscan_status lscan_radix_offsets(const void *keys, int64_t n, lscan_dtype dt,
  *                (which parent is chosen is not fixed: any valid one)
  *   stats        device array of 4 int64 (output), or null: number of levels,
  *                vertices reached, edges scanned (the out-degrees of the
- *                reached vertices), malformed entries met (a row range
- *                outside [0, num_edges] or a column outside [0,
- *                num_vertices); those are skipped, never dereferenced)
+ *                reached vertices), malformed entries met (a reached vertex
+ *                whose row range is not inside [0, num_edges], or a column
+ *                outside [0, num_vertices) in such a row; those are
+ *                skipped, never dereferenced)
  * Outputs may not overlap the inputs or each other.  The library keeps a
- * per-stream workspace of about 16 bytes per vertex.  Not capturable into a
- * HIP graph (LSCAN_ERR_UNSUPPORTED while the stream captures: each launch
- * takes fresh flag tags from the host).  A wait that outlasts the watchdog
- * stops the whole grid; the next lscan_check on the stream reports
- * LSCAN_ERR_TIMEOUT and the outputs are undefined.
+ * per-stream workspace of about 32 bytes per vertex and 24 bytes per 1024
+ * edges.  Not capturable into a HIP graph (LSCAN_ERR_UNSUPPORTED while the
+ * stream captures: each launch takes fresh flag tags from the host).  A wait
+ * that outlasts the watchdog stops the whole grid; the next lscan_check on
+ * the stream reports LSCAN_ERR_TIMEOUT and the outputs are undefined.
  * lscan_bfs_with_params honours groups_per_cu only (a tile shape or the
  * chain hand-off: LSCAN_ERR_UNSUPPORTED).
  */

@@ -5,25 +5,32 @@
 // queue-tail counter that level-synchronous GPU searches usually use.
 //
 // One launch runs the whole search, level by level (top-down expansion):
-//   * The frontier of level l is a queue of f vertices, cut into chunks of
-//     kBfsChunk vertices.  Chunk c is taken by workgroup c mod B, in
-//     increasing c (the cyclic distribution of the scan).
-//   * Per chunk, the workgroup lays the chunk's edges out flat (an exclusive
-//     scan of the degrees in LDS), walks them with one edge per thread, and
-//     claims every endpoint not yet discovered with a compare-and-swap of
-//     the vertex's claim word from "none" to the edge index.  The winners --
-//     the vertices of level l + 1 that this chunk discovered -- are counted
-//     and kept in LDS.
-//   * Where the discoveries go in the next frontier is a scan over chunks:
-//     the chunk publishes its count A(c) in its flag word at once, then
-//     obtains its offset from the counts of the B - 1 chunks before it and
-//     its own previous chunk's running total (the window fold of the scan),
-//     and writes its discoveries there.  No shared tail counter is bumped.
+//   * The frontier of a level is a queue of the vertices found at the level
+//     before that have at least one edge, with the exclusive prefix of their
+//     degrees beside it, so the level's edges have flat ranks 0 .. D - 1.
+//     The ranks are cut into chunks of kBfsChunkEdges; chunk c is taken by
+//     workgroup c mod B, in increasing c (the cyclic distribution of the
+//     scan).  Every chunk has the same number of edges, however skewed the
+//     degrees: a hub's edges spread over many chunks.
+//   * Per chunk, the workgroup loads the frontier vertices its ranks fall in
+//     (a table written while the frontier was built gives the first one),
+//     maps each rank to its vertex by a search in LDS, and claims every
+//     endpoint not yet discovered with a compare-and-swap of the vertex's
+//     claim word from "none" to the edge index.  The winners are the
+//     vertices of the next level that this chunk discovered; those with
+//     edges are kept in LDS with their degrees (a chunk discovers at most
+//     one vertex per edge, so they always fit).
+//   * Where they go in the next frontier is a scan over chunks: the chunk
+//     publishes (vertices, edges) packed in one 64-bit value in its flag
+//     words at once, obtains its offsets from its own previous chunk's
+//     running total and the values of the chunks in between (the window
+//     fold of the scan), and writes its vertices, their edge offsets and
+//     the next level's chunk table there.  No shared tail counter.
 //   * A level ends with a grid barrier built from the same flag words: each
-//     workgroup publishes (tag, vertices it placed); workgroup 0 gathers
-//     them, and publishes (tag, size of the next frontier), which every
-//     workgroup waits for.  The next frontier's writes are released before
-//     the arrival and acquired after the release word, at agent scope.
+//     workgroup publishes its sums under the level's tag, workgroup 0 adds
+//     them up and publishes the totals, which every workgroup waits for.
+//     The next frontier's writes are released before the arrival and
+//     acquired after the release word, at agent scope.
 //   * Every flag word carries the tag of its level, so nothing is cleared
 //     between levels or launches; the host hands each launch a fresh range
 //     of tags.  Every wait is bounded and honours the abort word, so a grid
@@ -39,20 +46,26 @@ namespace lscan {
 namespace {
 
 constexpr int kWaves = kBfsThreads / 64;
-constexpr int kUnroll = 4;  // edges per thread in flight at once
+constexpr int K = kBfsChunkEdges;
+constexpr int kPer = K / kBfsThreads;  // edges per thread per chunk
 constexpr uint64_t kUnclaimed = ~uint64_t(0);
+constexpr int64_t kCountMask = (int64_t(1) << kBfsCountBits) - 1;
+constexpr int kBarrierWords = 4;
 
 struct BfsShared {
-    int64_t off[kBfsChunk + 1];  // exclusive prefix of the chunk's degrees; off[n] = edges of the chunk
-    int64_t beg[kBfsChunk];      // first edge of each chunk vertex
-    int32_t u[kBfsChunk];        // the chunk's vertices
-    int32_t stage[kBfsStage];    // vertices the chunk discovered (first kBfsStage of them)
+    int64_t eo[K + 2];       // edge offsets of the chunk's vertices; eo[n] is a sentinel
+    int64_t shift[K + 1];    // row start - edge offset: edge index = rank + shift
+    int32_t u[K + 1];        // the chunk's vertices
+    int32_t stage_v[K];      // discovered vertices that have edges
+    int64_t stage_d[K];      // and their degrees
     int64_t wave_tot[kWaves];
-    uint32_t wave_cnt[kWaves];
-    uint32_t found;              // discoveries of the chunk
-    uint32_t bad;                // malformed row or column entries seen by this workgroup
-    int32_t prefix;              // the chunk's offset in the next frontier
-    int32_t result;              // a barrier's result for the whole workgroup (-1: gave up)
+    uint64_t found_e;        // edges of the staged vertices
+    uint32_t found;          // staged vertices
+    uint32_t found_all;      // vertices this workgroup discovered in the current level
+    uint32_t bad;            // malformed entries this workgroup met
+    int32_t ok;
+    int64_t p_n, p_e;        // the chunk's offsets in the next frontier
+    int64_t res[kBarrierWords];
 };
 
 __device__ __forceinline__ uint32_t lanes_before(uint64_t mask)
@@ -64,6 +77,15 @@ __device__ __forceinline__ void give_up(const BfsArgs& a, uint32_t tag)
 {
     __hip_atomic_store(a.abort_word, tag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __hip_atomic_store(a.timeout_flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Degree of v with *beg its first edge, or -1 if its row range is not
+// inside [0, E].
+__device__ __forceinline__ int64_t row_range(const BfsArgs& a, int64_t v, int64_t* beg)
+{
+    const int64_t b0 = a.row[v], b1 = a.row[v + 1];
+    *beg = b0;
+    return (b0 >= 0 && b1 >= b0 && b1 <= a.ne) ? b1 - b0 : -1;
 }
 
 // Exclusive +-scan of one int64 per thread over the workgroup; *total gets
@@ -86,13 +108,13 @@ __device__ __forceinline__ int64_t block_exclusive_sum(int64_t v, BfsShared& s, 
     return before + inc - v;
 }
 
-// The chunk vertex that owns flat edge rank r: the last k < n with off[k] <= r.
+// The chunk vertex that owns flat edge rank r: the last k < n with eo[k] <= r.
 __device__ __forceinline__ int owner_of(const BfsShared& s, int n, int64_t r)
 {
     int lo = 0, hi = n;
     while (hi - lo > 1) {
         const int mid = (lo + hi) >> 1;
-        if (s.off[mid] <= r)
+        if (s.eo[mid] <= r)
             lo = mid;
         else
             hi = mid;
@@ -100,36 +122,49 @@ __device__ __forceinline__ int owner_of(const BfsShared& s, int n, int64_t r)
     return lo;
 }
 
-// Grid barrier over flag words.  Every workgroup publishes `mine` under
-// `tag`; workgroup 0 sums the B arrivals and publishes the sum, which every
-// workgroup returns (-1 if a wait gave up).  Writes made before the call are
-// visible to every workgroup after it.
-__device__ int32_t grid_barrier(const BfsArgs& a, BfsShared& s, uint32_t tag, uint32_t mine, int64_t edges)
+// Grid barrier over flag words.  Every workgroup publishes the four 32-bit
+// values v[] (thread 0's) under `tag`; workgroup 0 adds them up over the
+// grid (word 1 and 2 are the low and high halves of one 64-bit value) and
+// publishes the sums, which every workgroup reads into s.res.  Writes made
+// before the call are visible to every workgroup after it.  Returns false
+// if a wait gave up.
+__device__ bool grid_barrier(const BfsArgs& a, BfsShared& s, uint32_t tag, const uint32_t (&v)[kBarrierWords])
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");  // this wave's frontier writes
     __syncthreads();
     if (threadIdx.x == 0) {
-        __hip_atomic_store(a.partial + 2 * blockIdx.x, edges, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(a.partial + 2 * blockIdx.x + 1, int64_t(s.bad), __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(a.partial + blockIdx.x, int64_t(s.bad), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        slot_store(a.arrive + blockIdx.x, (uint64_t(tag) << 32) | mine);
+#pragma unroll
+        for (int k = 0; k < kBarrierWords; ++k)
+            slot_store(a.arrive + kBarrierWords * blockIdx.x + k, (uint64_t(tag) << 32) | v[k]);
     }
     if (blockIdx.x == 0 && wave == 0) {
         bool ok = true;
-        uint32_t sum = 0;
+        int64_t n = 0, e = 0, found = 0;
         for (int64_t j = lane; j < int64_t(gridDim.x); j += 64) {
-            uint64_t w = slot_load(a.arrive + j);
-            w = await_word(a.arrive + j, w, tag, a.spin_limit, a.abort_word, ok);
-            sum += uint32_t(w);
+            uint64_t w[kBarrierWords];
+#pragma unroll
+            for (int k = 0; k < kBarrierWords; ++k) w[k] = slot_load(a.arrive + kBarrierWords * j + k);
+#pragma unroll
+            for (int k = 0; k < kBarrierWords; ++k)
+                w[k] = await_word(a.arrive + kBarrierWords * j + k, w[k], tag, a.spin_limit, a.abort_word, ok);
+            n += uint32_t(w[0]);
+            e += int64_t(uint64_t(uint32_t(w[1])) | (uint64_t(uint32_t(w[2])) << 32));
+            found += uint32_t(w[3]);
         }
         const bool all_ok = __ballot(!ok) == 0;
-        sum = uint32_t(read_lane(wave_inclusive_scan<AddI32>(int32_t(sum)), 63));
+        n = read_lane(wave_inclusive_scan<AddI64>(n), 63);
+        e = read_lane(wave_inclusive_scan<AddI64>(e), 63);
+        found = read_lane(wave_inclusive_scan<AddI64>(found), 63);
         if (lane == 0) {
             if (all_ok) {
                 __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
-                slot_store(a.go, (uint64_t(tag) << 32) | sum);
+                const uint32_t out[kBarrierWords] = {uint32_t(n), uint32_t(uint64_t(e)), uint32_t(uint64_t(e) >> 32),
+                                                     uint32_t(found)};
+#pragma unroll
+                for (int k = 0; k < kBarrierWords; ++k) slot_store(a.go + k, (uint64_t(tag) << 32) | out[k]);
             } else {
                 give_up(a, tag);
             }
@@ -137,14 +172,22 @@ __device__ int32_t grid_barrier(const BfsArgs& a, BfsShared& s, uint32_t tag, ui
     }
     if (threadIdx.x == 0) {
         bool ok = true;
-        uint64_t w = slot_load(a.go);
-        w = await_word(a.go, w, tag, a.spin_limit, a.abort_word, ok);
+        uint64_t w[kBarrierWords];
+#pragma unroll
+        for (int k = 0; k < kBarrierWords; ++k) {
+            w[k] = slot_load(a.go + k);
+            w[k] = await_word(a.go + k, w[k], tag, a.spin_limit, a.abort_word, ok);
+        }
         if (!ok) give_up(a, tag);
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        s.result = ok ? int32_t(uint32_t(w)) : -1;
+        s.ok = ok ? 1 : 0;
+        s.res[0] = uint32_t(w[0]);
+        s.res[1] = int64_t(uint64_t(uint32_t(w[1])) | (uint64_t(uint32_t(w[2])) << 32));
+        s.res[2] = 0;
+        s.res[3] = uint32_t(w[3]);
     }
     __syncthreads();
-    return s.result;
+    return s.ok != 0;
 }
 
 __global__ void __launch_bounds__(kBfsThreads) bfs_kernel(BfsArgs a)
@@ -159,192 +202,257 @@ __global__ void __launch_bounds__(kBfsThreads) bfs_kernel(BfsArgs a)
     const int64_t B = gridDim.x, wg = blockIdx.x;
     const int64_t V = a.nv;
 
-    // Initial state: nothing claimed but the source (whose claim names no edge).
+    // Initial state: nothing claimed but the source (whose claim names no
+    // edge); the first frontier is the source if it has edges.  Every
+    // workgroup also counts the places where the row offsets decrease: rows
+    // that overlap would break the bound of the chunk tables, so such a
+    // graph is not searched.
+    int64_t src_beg = 0;
+    const int64_t src_deg = row_range(a, a.src, &src_beg);
+    uint32_t decreasing = 0;
     for (int64_t v = wg * kBfsThreads + tid; v < V; v += B * kBfsThreads) {
         const bool is_src = (v == a.src);
         a.claim[v] = is_src ? uint64_t(a.ne) : kUnclaimed;
         a.level[v] = is_src ? 0 : -1;
         if (a.parent) a.parent[v] = is_src ? a.src : -1;
+        decreasing += (a.row[v] > a.row[v + 1]) ? 1u : 0u;
     }
-    if (wg == 0 && tid == 0) a.queue0[0] = a.src;
-    if (tid == 0) s.bad = 0;
+    const int64_t d0 = (src_deg > 0) ? src_deg : 0;
+    if (wg == 0 && tid == 0 && d0 > 0) {
+        a.queue[0][0] = a.src;
+        a.edge_off[0][0] = 0;
+    }
+    for (int64_t b = wg * kBfsThreads + tid; b * K < d0 && b < a.chunk_cap; b += B * kBfsThreads)
+        a.chunk_first[0][b] = 0;
+    if (tid == 0) {
+        s.bad = (wg == 0 && src_deg < 0) ? 1u : 0u;
+        s.found_all = 0;
+        s.found = 0;
+    }
+    __syncthreads();
+    if (decreasing) atomicAdd(&s.found, decreasing);
+    __syncthreads();
 
-    int64_t edges = 0;  // edges this workgroup scanned (thread 0's count)
     uint32_t tag = a.base_tag + 1u;
-    int32_t f = (grid_barrier(a, s, tag, 0u, 0) < 0) ? -1 : 1;
-    int64_t reached = 1;
-    int32_t lev = 0;
-
-    while (f > 0) {
-        ++tag;
-        const int32_t* cur = (lev & 1) ? a.queue1 : a.queue0;
-        int32_t* nxt = (lev & 1) ? a.queue0 : a.queue1;
-        const int64_t nc = (int64_t(f) + kBfsChunk - 1) / kBfsChunk;
-        int32_t run = 0;     // discoveries of chunks 0 .. (this workgroup's previous chunk)
-        uint32_t mine = 0;   // discoveries this workgroup placed in this level
-        bool ok = true;
-        for (int64_t c = wg; c < nc; c += B) {
-            // (a) the chunk's vertices, their edge ranges, flat edge ranks
-            const int n = int((int64_t(f) - c * kBfsChunk < kBfsChunk) ? int64_t(f) - c * kBfsChunk : kBfsChunk);
-            int64_t deg = 0, b0 = 0;
-            int32_t u = -1;
-            if (tid < n) {
-                u = cur[c * kBfsChunk + tid];
-                if (uint32_t(u) < uint32_t(V)) {
-                    b0 = a.row[u];
-                    const int64_t b1 = a.row[u + 1];
-                    if (b0 >= 0 && b1 >= b0 && b1 <= a.ne)
-                        deg = b1 - b0;
-                    else
-                        atomicAdd(&s.bad, 1u);
-                }
+    uint32_t v0[kBarrierWords] = {0u, 0u, 0u, s.found};
+    bool ok = grid_barrier(a, s, tag, v0);
+    const int64_t bad_rows = s.res[3];
+    if (ok && bad_rows > 0) {
+        // not searched: nothing reached, the decreasing steps reported
+        if (wg == 0 && tid == 0) {
+            a.level[a.src] = -1;
+            if (a.parent) a.parent[a.src] = -1;
+            if (a.stats) {
+                a.stats[0] = 0;
+                a.stats[1] = 0;
+                a.stats[2] = 0;
+                a.stats[3] = bad_rows;
             }
-            int64_t D = 0;
-            const int64_t off = block_exclusive_sum(deg, s, &D);
-            if (tid < n) {
-                s.off[tid] = off;
-                s.beg[tid] = b0;
-                s.u[tid] = u;
+        }
+        return;
+    }
+
+    int64_t f = (d0 > 0) ? 1 : 0, D = d0;
+    int64_t levels = 1, reached = 1, scanned = 0;
+    int32_t lev = 0;
+    while (ok && f > 0) {
+        ++tag;
+        const int q = lev & 1;
+        const int32_t* cur = a.queue[q];
+        const int64_t* cur_eo = a.edge_off[q];
+        const int32_t* cur_cf = a.chunk_first[q];
+        int32_t* nxt = a.queue[q ^ 1];
+        int64_t* nxt_eo = a.edge_off[q ^ 1];
+        int32_t* nxt_cf = a.chunk_first[q ^ 1];
+        const int64_t nc = (D + K - 1) / K;
+        if (nc > a.chunk_cap) break;  // cannot happen with non-decreasing rows (memory guard)
+        scanned += D;
+        int64_t run_n = 0, run_e = 0;    // offsets through this workgroup's previous chunk
+        int64_t mine_n = 0, mine_e = 0;  // what this workgroup placed in this level
+        if (tid == 0) s.found_all = 0;
+        for (int64_t c = wg; c < nc; c += B) {
+            // (a) the chunk's frontier vertices
+            const int64_t r_lo = c * K;
+            const int64_t r_hi = (D - r_lo < K) ? D : r_lo + K;
+            int64_t k0 = cur_cf[c];
+            int64_t kend = (c + 1 < nc) ? int64_t(cur_cf[c + 1]) : f - 1;
+            k0 = (k0 < 0) ? 0 : (k0 >= f ? f - 1 : k0);  // memory guards: the table is consistent
+            kend = (kend < k0) ? k0 : (kend >= f ? f - 1 : kend);
+            if (kend - k0 > K) kend = k0 + K;
+            const int n = int(kend - k0 + 1);
+            for (int j = tid; j < n; j += kBfsThreads) {
+                const int64_t eo = cur_eo[k0 + j];
+                const int32_t u = cur[k0 + j];
+                const int64_t beg = (uint32_t(u) < uint32_t(V)) ? a.row[u] : 0;
+                s.eo[j] = eo;
+                s.shift[j] = beg - eo;
+                s.u[j] = u;
             }
             if (tid == 0) {
-                s.off[n] = D;
+                s.eo[n] = INT64_MAX;
                 s.found = 0;
-                edges += D;
+                s.found_e = 0;
             }
             __syncthreads();
 
             // (b) claim every endpoint not yet discovered; stage the winners
-            for (int64_t r0 = 0; r0 < D; r0 += int64_t(kBfsThreads) * kUnroll) {
-                int k[kUnroll];
-                int64_t e[kUnroll];
-                int32_t v[kUnroll];
+            int k[kPer];
+            int64_t e[kPer];
+            int32_t v[kPer];
 #pragma unroll
-                for (int q = 0; q < kUnroll; ++q) {
-                    const int64_t r = r0 + int64_t(q) * kBfsThreads + tid;
-                    k[q] = -1;
-                    e[q] = 0;
-                    if (r < D) {
-                        k[q] = owner_of(s, n, r);
-                        e[q] = s.beg[k[q]] + (r - s.off[k[q]]);
+            for (int p = 0; p < kPer; ++p) {
+                const int64_t r = r_lo + int64_t(p) * kBfsThreads + tid;
+                k[p] = -1;
+                e[p] = 0;
+                if (r < r_hi) {
+                    const int kk = owner_of(s, n, r);
+                    const int64_t ee = r + s.shift[kk];
+                    if (ee >= 0 && ee < a.ne) {
+                        k[p] = kk;
+                        e[p] = ee;
+                    } else {
+                        atomicAdd(&s.bad, 1u);
                     }
                 }
+            }
 #pragma unroll
-                for (int q = 0; q < kUnroll; ++q) v[q] = (k[q] >= 0) ? a.col[e[q]] : -1;
-                uint64_t cl[kUnroll];
+            for (int p = 0; p < kPer; ++p) v[p] = (k[p] >= 0) ? a.col[e[p]] : -1;
+            uint64_t cl[kPer];
 #pragma unroll
-                for (int q = 0; q < kUnroll; ++q) {
-                    const bool valid = (k[q] >= 0) && uint32_t(v[q]) < uint32_t(V);
-                    if (k[q] >= 0 && !valid) atomicAdd(&s.bad, 1u);
-                    if (!valid) k[q] = -1;
-                    cl[q] = (k[q] >= 0) ? a.claim[v[q]] : 0;  // a stale "none" only costs a failed swap
+            for (int p = 0; p < kPer; ++p) {
+                if (k[p] >= 0 && uint32_t(v[p]) >= uint32_t(V)) {
+                    atomicAdd(&s.bad, 1u);
+                    k[p] = -1;
                 }
+                cl[p] = (k[p] >= 0) ? a.claim[v[p]] : 0;  // a stale "none" only costs a failed swap
+            }
+            bool win[kPer];
 #pragma unroll
-                for (int q = 0; q < kUnroll; ++q) {
-                    bool win = false;
-                    if (k[q] >= 0 && cl[q] == kUnclaimed) {
-                        win = atomicCAS(reinterpret_cast<unsigned long long*>(a.claim + v[q]),
-                                        (unsigned long long)kUnclaimed, (unsigned long long)e[q]) ==
-                              (unsigned long long)kUnclaimed;
-                        if (win) {
-                            a.level[v[q]] = lev + 1;
-                            if (a.parent) a.parent[v[q]] = s.u[k[q]];
-                        }
+            for (int p = 0; p < kPer; ++p) {
+                win[p] = false;
+                if (k[p] >= 0 && cl[p] == kUnclaimed)
+                    win[p] = atomicCAS(reinterpret_cast<unsigned long long*>(a.claim + v[p]),
+                                       (unsigned long long)kUnclaimed,
+                                       (unsigned long long)e[p]) == (unsigned long long)kUnclaimed;
+            }
+            int64_t dv[kPer];
+#pragma unroll
+            for (int p = 0; p < kPer; ++p) {
+                dv[p] = 0;
+                if (win[p]) {
+                    a.level[v[p]] = lev + 1;
+                    if (a.parent) a.parent[v[p]] = s.u[k[p]];
+                    int64_t beg;
+                    dv[p] = row_range(a, v[p], &beg);
+                    if (dv[p] < 0) {
+                        atomicAdd(&s.bad, 1u);
+                        dv[p] = 0;
                     }
-                    const uint64_t m = __ballot(win);
-                    uint32_t base = 0;
-                    if (lane == 0 && m != 0) base = atomicAdd(&s.found, uint32_t(__popcll(m)));
-                    base = __builtin_amdgcn_readlane(base, 0);
-                    const uint32_t pos = base + lanes_before(m);
-                    if (win && pos < uint32_t(kBfsStage)) s.stage[pos] = v[q];
+                }
+            }
+#pragma unroll
+            for (int p = 0; p < kPer; ++p) {
+                const bool keep = win[p] && dv[p] > 0;
+                const uint64_t m_all = __ballot(win[p]);
+                const uint64_t m = __ballot(keep);
+                uint32_t base = 0;
+                if (lane == 0) {
+                    if (m_all) atomicAdd(&s.found_all, uint32_t(__popcll(m_all)));
+                    if (m) base = atomicAdd(&s.found, uint32_t(__popcll(m)));
+                }
+                base = __builtin_amdgcn_readlane(base, 0);
+                if (keep) {
+                    const uint32_t pos = base + lanes_before(m);  // < K: one discovery per edge at most
+                    s.stage_v[pos] = v[p];
+                    s.stage_d[pos] = dv[p];
+                    atomicAdd(reinterpret_cast<unsigned long long*>(&s.found_e), (unsigned long long)dv[p]);
                 }
             }
             __syncthreads();
-            const uint32_t A = s.found;
+            const int64_t A_n = s.found;
+            const int64_t A_e = int64_t(s.found_e);
 
-            // (c) publish A(c); offset = own previous running total + the
-            //     counts of the chunks in between (window fold)
+            // (c) publish (edges, vertices) packed; offsets = own previous
+            //     running total + the values of the chunks in between
             if (wave == 0) {
-                if (lane == 0) slot_store(a.slots + c, (uint64_t(tag) << 32) | A);
+                const int64_t packed = (A_e << kBfsCountBits) | A_n;
+                publish_slot(a.slots + 2 * c, packed, tag, lane);
                 const int64_t lo = (c - B + 1 > 0) ? c - B + 1 : 0;
                 bool good = true;
-                const int32_t between = window_fold<AddI32>(a.slots, lo, c - lo, tag, a.spin_limit, a.abort_word,
-                                                            lane, good);
+                const int64_t between =
+                    window_fold<AddI64>(a.slots, lo, c - lo, tag, a.spin_limit, a.abort_word, lane, good);
                 const bool all_good = __ballot(!good) == 0;
                 if (lane == 0) {
-                    s.prefix = all_good ? run + between : -1;
+                    s.p_n = run_n + (between & kCountMask);
+                    s.p_e = run_e + (between >> kBfsCountBits);
+                    s.ok = all_good ? 1 : 0;
                     if (!all_good) give_up(a, tag);
                 }
             }
             __syncthreads();
-            const int32_t p = s.prefix;
-            if (p < 0) {
+            if (!s.ok) {
                 ok = false;
                 break;
             }
-            run = p + int32_t(A);
-            mine += A;
+            const int64_t p_n = s.p_n, p_e = s.p_e;
+            run_n = p_n + A_n;
+            run_e = p_e + A_e;
+            mine_n += A_n;
+            mine_e += A_e;
 
-            // (d) place the discoveries at p .. p + A - 1
-            if (A <= uint32_t(kBfsStage)) {
-                for (uint32_t q = tid; q < A; q += kBfsThreads)
-                    if (int64_t(p) + q < V) nxt[p + q] = s.stage[q];
-            } else {
-                // more than LDS holds: walk the edges again and emit those
-                // whose claim names them (this chunk's winners, in rank order)
-                int64_t placed = p;
-                for (int64_t r0 = 0; r0 < D; r0 += kBfsThreads) {
-                    const int64_t r = r0 + tid;
-                    bool win = false;
-                    int32_t v = -1;
-                    if (r < D) {
-                        const int k = owner_of(s, n, r);
-                        const int64_t e = s.beg[k] + (r - s.off[k]);
-                        v = a.col[e];
-                        if (uint32_t(v) < uint32_t(V))
-                            win = __hip_atomic_load(a.claim + v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ==
-                                  uint64_t(e);
-                    }
-                    const uint64_t m = __ballot(win);
-                    if (lane == 0) s.wave_cnt[wave] = uint32_t(__popcll(m));
-                    __syncthreads();
-                    uint32_t before = 0, all = 0;
+            // (d) place the staged vertices at p_n ..: queue entry, edge
+            //     offset, and the next level's chunk table entries that fall
+            //     in their edge ranges
+            int64_t dl[kPer];
+            int64_t dsum = 0;
 #pragma unroll
-                    for (int w = 0; w < kWaves; ++w) {
-                        const uint32_t t = s.wave_cnt[w];
-                        before += (w < wave) ? t : 0;
-                        all += t;
+            for (int t = 0; t < kPer; ++t) {
+                const int j = tid * kPer + t;
+                dl[t] = (j < A_n) ? s.stage_d[j] : 0;
+                dsum += dl[t];
+            }
+            int64_t tot = 0;
+            int64_t eoff = p_e + block_exclusive_sum(dsum, s, &tot);
+#pragma unroll
+            for (int t = 0; t < kPer; ++t) {
+                const int j = tid * kPer + t;
+                if (j < A_n) {
+                    const int64_t pos = p_n + j;
+                    if (pos < V) {
+                        nxt[pos] = s.stage_v[j];
+                        nxt_eo[pos] = eoff;
+                        for (int64_t b = (eoff + K - 1) / K; b * K < eoff + dl[t] && b < a.chunk_cap; ++b)
+                            nxt_cf[b] = int32_t(pos);
                     }
-                    const int64_t pos = placed + before + lanes_before(m);
-                    if (win && pos < V) nxt[pos] = v;
-                    placed += all;
-                    __syncthreads();
+                    eoff += dl[t];
                 }
             }
             __syncthreads();  // LDS is reused by the next chunk
         }
-        if (!ok) {
-            f = -1;
-            break;
-        }
-        // (e) the level barrier: the next frontier's size
-        f = grid_barrier(a, s, tag, mine, edges);
-        if (f > 0) {
-            if (int64_t(f) > V) f = int32_t(V);  // cannot happen: each vertex is claimed once
-            reached += f;
+        if (!ok) break;
+        // (e) the level barrier: the next frontier's size and edges
+        const uint32_t vb[kBarrierWords] = {uint32_t(mine_n), uint32_t(uint64_t(mine_e)),
+                                            uint32_t(uint64_t(mine_e) >> 32), s.found_all};
+        ok = grid_barrier(a, s, tag, vb);
+        if (!ok) break;
+        f = s.res[0];
+        D = s.res[1];
+        if (f > V) f = V;  // cannot happen: each vertex is claimed once (memory guard)
+        if (s.res[3] > 0) {
+            ++levels;
+            reached += s.res[3];
         }
         ++lev;
     }
 
-    if (f == 0 && wg == 0 && tid == 0 && a.stats) {
-        int64_t all_edges = 0, all_bad = 0;
-        for (int64_t j = 0; j < B; ++j) {
-            all_edges += __hip_atomic_load(a.partial + 2 * j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            all_bad += __hip_atomic_load(a.partial + 2 * j + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-        a.stats[0] = lev;
+    if (ok && wg == 0 && tid == 0 && a.stats) {
+        int64_t bad = 0;
+        for (int64_t j = 0; j < B; ++j)
+            bad += __hip_atomic_load(a.partial + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        a.stats[0] = levels;
         a.stats[1] = reached;
-        a.stats[2] = all_edges;
-        a.stats[3] = all_bad;
+        a.stats[2] = scanned;
+        a.stats[3] = bad;
     }
 }
 

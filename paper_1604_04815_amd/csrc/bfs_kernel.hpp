@@ -8,29 +8,35 @@
 
 namespace lscan {
 
-// Vertices of the frontier taken by one workgroup at a time (one per thread).
 constexpr int kBfsThreads = 256;
-constexpr int kBfsChunk = kBfsThreads;
-// Vertices a chunk may discover and still keep in LDS; more are found again
-// by a second walk over the chunk's edges.
-constexpr int kBfsStage = 2048;
+// Edges of the frontier taken by one workgroup at a time (four per thread).
+// A chunk discovers at most this many vertices, so its discoveries always
+// fit in LDS.
+constexpr int kBfsChunkEdges = 4 * kBfsThreads;
+// Largest grid: a window of grid - 1 chunk counts (at most kBfsChunkEdges
+// each) must fit the 21-bit count field of a packed flag value.
+constexpr int kBfsMaxGrid = 2048;
+constexpr int kBfsCountBits = 21;
 
 struct BfsArgs {
     const int64_t* row;      // V + 1 row offsets (compressed rows)
     const int32_t* col;      // E column indices
     int64_t nv;              // V (< 2^31)
-    int64_t ne;              // E
+    int64_t ne;              // E (< 2^42)
     int32_t src;             // source vertex
     int32_t* level;          // V: level of each vertex, -1 unreached
     int32_t* parent;         // V or null: a BFS-tree parent (src for src, -1 unreached)
     int64_t* stats;          // 4 or null: levels, vertices reached, edges scanned, bad entries
     uint64_t* claim;         // V: edge index that discovered the vertex (all ones: not yet)
-    int32_t* queue0;         // V: frontier of even levels
-    int32_t* queue1;         // V: frontier of odd levels
-    uint64_t* slots;         // ceil(V / chunk) flag words: per-chunk discovery counts
-    uint64_t* arrive;        // grid words: level barrier arrivals (tag | vertices found)
-    int64_t* partial;        // grid entries: edges scanned by each workgroup so far
-    uint64_t* go;            // 1 word: barrier release (tag | next frontier size)
+    int32_t* queue[2];       // V each: frontier vertices (those with at least one edge)
+    int64_t* edge_off[2];    // V each: exclusive prefix of the frontier's degrees
+    int32_t* chunk_first[2]; // ceil(E / chunk) + 1 each: frontier index holding each chunk's first edge
+    int64_t chunk_cap;       // entries of each chunk_first array (ceil(E / chunk) + 1)
+    uint64_t* slots;         // 2 * chunk_cap flag words: packed per-chunk (edges << 21 | vertices)
+    uint64_t* arrive;        // 4 * grid words: level barrier arrivals
+                             // (vertices queued, their edges lo, hi, vertices found)
+    int64_t* partial;        // grid: malformed entries seen by each workgroup
+    uint64_t* go;            // 4 words: barrier release (the four sums)
     uint32_t* abort_word;    // tag of a wait that gave up (every waiter stops)
     uint32_t* timeout_flag;  // raised to 1 when a wait gives up
     uint32_t* ctrl;          // co-residency test words [4..6]

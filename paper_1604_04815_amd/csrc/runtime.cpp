@@ -739,6 +739,7 @@ lscan_status run(const Request& r, void* stream_ptr)
 struct BfsWorkspace {
     char* mem = nullptr;
     int64_t cap_v = 0;
+    int64_t cap_chunks = 0;  // entries of each chunk table
     int cap_grid = 0;
     size_t flag_bytes = 0;
     uint64_t* slots = nullptr;
@@ -747,8 +748,9 @@ struct BfsWorkspace {
     uint32_t* abort_word = nullptr;
     int64_t* partial = nullptr;
     uint64_t* claim = nullptr;
-    int32_t* queue0 = nullptr;
-    int32_t* queue1 = nullptr;
+    int64_t* edge_off[2] = {nullptr, nullptr};
+    int32_t* queue[2] = {nullptr, nullptr};
+    int32_t* chunk_first[2] = {nullptr, nullptr};
     uint64_t next_tag = 0;  // the next launch's tags start above this
 };
 std::map<std::pair<int, hipStream_t>, BfsWorkspace> g_bfs_ws;
@@ -763,39 +765,44 @@ void free_bfs_workspace(BfsWorkspace& ws)
     ws = BfsWorkspace();
 }
 
-lscan_status ensure_bfs_workspace(BfsWorkspace& ws, hipStream_t stream, int64_t nv, int grid)
+lscan_status ensure_bfs_workspace(BfsWorkspace& ws, hipStream_t stream, int64_t nv, int64_t chunks, int grid)
 {
-    if (ws.mem && ws.cap_v >= nv && ws.cap_grid >= grid) return LSCAN_OK;
+    if (ws.mem && ws.cap_v >= nv && ws.cap_chunks >= chunks && ws.cap_grid >= grid) return LSCAN_OK;
     hipError_t e;
     if (ws.mem) {
         e = hipStreamSynchronize(stream);  // earlier searches on this stream still use it
         if (e != hipSuccess) return device_error(e);
+        nv = std::max(nv, ws.cap_v);
+        chunks = std::max(chunks, ws.cap_chunks);
+        grid = std::max(grid, ws.cap_grid);
         free_bfs_workspace(ws);
     }
-    const int64_t v = nv;
-    const int64_t chunks = (v + kBfsChunk - 1) / kBfsChunk;
-    const size_t flag_words = size_t(chunks) + size_t(grid) + 2;  // + release word + abort word
-    const size_t bytes = flag_words * 8 + size_t(grid) * 16 + size_t(v) * 8 + size_t(v) * 8;
+    // flag region first (zeroed), then 8-byte arrays, then 4-byte arrays
+    const size_t flag_words = 2 * size_t(chunks) + 4 * size_t(grid) + 4 + 1;
+    const size_t bytes = flag_words * 8 + size_t(grid) * 8 + size_t(nv) * 8 * 3 + size_t(nv) * 4 * 2 +
+                         size_t(chunks) * 4 * 2;
     e = hipMalloc(reinterpret_cast<void**>(&ws.mem), bytes);
     if (e != hipSuccess) {
         (void)hipGetLastError();
         ws.mem = nullptr;
         return LSCAN_ERR_NO_MEMORY;
     }
-    char* p = ws.mem;
-    ws.slots = reinterpret_cast<uint64_t*>(p);
-    ws.arrive = ws.slots + chunks;
-    ws.go = ws.arrive + grid;
-    ws.abort_word = reinterpret_cast<uint32_t*>(ws.go + 1);
+    uint64_t* w = reinterpret_cast<uint64_t*>(ws.mem);
+    ws.slots = w;
+    ws.arrive = ws.slots + 2 * chunks;
+    ws.go = ws.arrive + 4 * size_t(grid);
+    ws.abort_word = reinterpret_cast<uint32_t*>(ws.go + 4);
     ws.flag_bytes = flag_words * 8;
-    p += ws.flag_bytes;
-    ws.partial = reinterpret_cast<int64_t*>(p);
-    p += size_t(grid) * 16;
-    ws.claim = reinterpret_cast<uint64_t*>(p);
-    p += size_t(v) * 8;
-    ws.queue0 = reinterpret_cast<int32_t*>(p);
-    ws.queue1 = ws.queue0 + v;
-    ws.cap_v = v;
+    ws.partial = reinterpret_cast<int64_t*>(w + flag_words);
+    ws.claim = reinterpret_cast<uint64_t*>(ws.partial + grid);
+    ws.edge_off[0] = reinterpret_cast<int64_t*>(ws.claim + nv);
+    ws.edge_off[1] = ws.edge_off[0] + nv;
+    ws.queue[0] = reinterpret_cast<int32_t*>(ws.edge_off[1] + nv);
+    ws.queue[1] = ws.queue[0] + nv;
+    ws.chunk_first[0] = ws.queue[1] + nv;
+    ws.chunk_first[1] = ws.chunk_first[0] + chunks;
+    ws.cap_v = nv;
+    ws.cap_chunks = chunks;
     ws.cap_grid = grid;
     ws.next_tag = 0;
     e = hipMemsetAsync(ws.mem, 0, ws.flag_bytes, stream);
@@ -848,12 +855,13 @@ lscan_status bfs_run(const int64_t* row, const int32_t* col, int64_t nv, int64_t
     int groups = 0;
     st = resident_groups_core(info, k, want, ws, stream, info->bfs_resident_ok, info->bfs_resident_fail, &groups);
     if (st != LSCAN_OK) return st;
-    // no more workgroups than the largest frontier can keep busy
-    const int64_t chunks = (nv + kBfsChunk - 1) / kBfsChunk;
-    const int grid = int(std::max<int64_t>(1, std::min<int64_t>(int64_t(groups) * info->cu_count, chunks)));
+    // no more workgroups than the edges of the largest level can keep busy
+    const int64_t chunks = (ne + kBfsChunkEdges - 1) / kBfsChunkEdges + 1;
+    const int grid = int(std::max<int64_t>(
+        1, std::min<int64_t>({int64_t(groups) * info->cu_count, chunks, int64_t(kBfsMaxGrid)})));
 
     BfsWorkspace& bw = g_bfs_ws[std::make_pair(dev, stream)];
-    st = ensure_bfs_workspace(bw, stream, nv, grid);
+    st = ensure_bfs_workspace(bw, stream, nv, chunks, grid);
     if (st != LSCAN_OK) return st;
     // tags base + 1 .. base + nv + 2: the start barrier and at most nv levels
     const uint64_t need = uint64_t(nv) + 3;
@@ -873,8 +881,12 @@ lscan_status bfs_run(const int64_t* row, const int32_t* col, int64_t nv, int64_t
     a.parent = parent;
     a.stats = stats;
     a.claim = bw.claim;
-    a.queue0 = bw.queue0;
-    a.queue1 = bw.queue1;
+    for (int k = 0; k < 2; ++k) {
+        a.queue[k] = bw.queue[k];
+        a.edge_off[k] = bw.edge_off[k];
+        a.chunk_first[k] = bw.chunk_first[k];
+    }
+    a.chunk_cap = bw.cap_chunks;
     a.slots = bw.slots;
     a.arrive = bw.arrive;
     a.partial = bw.partial;
@@ -892,7 +904,7 @@ lscan_status bfs_run(const int64_t* row, const int32_t* col, int64_t nv, int64_t
     t_last_launch = lscan_launch_info{};
     t_last_launch.n = nv;
     t_last_launch.num_blocks = chunks;
-    t_last_launch.tile_elems = kBfsChunk;
+    t_last_launch.tile_elems = kBfsChunkEdges;
     t_last_launch.grid = grid;
     t_last_launch.block_threads = kBfsThreads;
     t_last_launch.slot_words = 1;
@@ -1250,7 +1262,7 @@ lscan_status lscan_bfs_with_params(const int64_t* row_offsets, const int32_t* co
                                    int64_t* stats, const lscan_params* p, void* stream)
 {
     if (num_vertices < 0 || num_vertices > int64_t(INT32_MAX) - 1 || num_edges < 0 ||
-        num_edges > (INT64_MAX / 16))
+        num_edges >= (int64_t(1) << 42))
         return LSCAN_ERR_INVALID_ARG;
     if (p) {
         lscan_status st = check_params(p);

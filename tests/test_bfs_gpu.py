@@ -202,6 +202,18 @@ def test_malformed_entries_are_skipped(gpu_lib):
     check(row2, col2, 0, levels, parents, stats2, "malformed")
 
 
+def test_decreasing_row_offsets_are_refused(gpu_lib):
+    nv = 500
+    s, d = w.uniform_random_edges(nv, 3000, seed=8)
+    row, col = csr(s, d, nv)
+    bad_row = row.copy()
+    bad_row[100] = bad_row[102] + 1   # row[99] <= row[100] > row[101]: one decreasing step
+    bad_row[300] = -1                 # row[299] > row[300]: another
+    levels, parents, stats = run(gpu_lib, bad_row, col, 0)
+    assert np.all(levels == -1) and np.all(parents == -1)
+    assert stats.tolist() == [0, 0, 0, 2]
+
+
 @pytest.mark.parametrize("groups", [1, 2, 8])
 def test_groups_per_cu(gpu_lib, groups):
     s, d = w.rmat_edges(15, 16, w.seed_for(9, 2))

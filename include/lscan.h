@@ -301,8 +301,9 @@ lscan_status lscan_radix_offsets(const void *keys, int64_t n, lscan_dtype dt,
  * as the next use of the paper's inter-block hand-off (Section 4.3): one
  * persistent launch runs the whole search.  The edges of each level's
  * frontier are cut into equal chunks taken cyclically by a co-resident
- * grid; each chunk claims the undiscovered endpoints of its edges
- * (compare-and-swap on a per-vertex claim word), publishes how many
+ * grid; each chunk claims the undiscovered endpoints of its edges (an
+ * atomic or on a visited bitmap: the lane that sets a vertex's bit finds
+ * it), publishes how many
  * vertices and edges it found in epoch-tagged flag words, and obtains where
  * they go in the next frontier from the values published before it (the
  * window fold of the scan) -- no shared queue-tail counter.  Levels end
@@ -332,7 +333,7 @@ lscan_status lscan_radix_offsets(const void *keys, int64_t n, lscan_dtype dt,
  *                outside [0, num_vertices) in such a row; those are
  *                skipped, never dereferenced)
  * Outputs may not overlap the inputs or each other.  The library keeps a
- * per-stream workspace of about 32 bytes per vertex and 24 bytes per 1024
+ * per-stream workspace of about 40 bytes per vertex and 24 bytes per 1024
  * edges.  Not capturable into a HIP graph (LSCAN_ERR_UNSUPPORTED while the
  * stream captures: each launch takes fresh flag tags from the host).  A wait
  * that outlasts the watchdog stops the whole grid; the next lscan_check on

@@ -15,8 +15,8 @@
 //   * Per chunk, the workgroup loads the frontier vertices its ranks fall in
 //     (a table written while the frontier was built gives the first one),
 //     maps each rank to its vertex by a search in LDS, and claims every
-//     endpoint not yet discovered with a compare-and-swap of the vertex's
-//     claim word from "none" to the edge index.  The winners are the
+//     endpoint not yet discovered by setting its bit in the visited bitmap
+//     with an atomic or: the lane that flips the bit wins.  The winners are the
 //     vertices of the next level that this chunk discovered; those with
 //     edges are kept in LDS with their degrees (a chunk discovers at most
 //     one vertex per edge, so they always fit).
@@ -48,16 +48,30 @@ namespace {
 constexpr int kWaves = kBfsThreads / 64;
 constexpr int K = kBfsChunkEdges;
 constexpr int kPer = K / kBfsThreads;  // edges per thread per chunk
-constexpr uint64_t kUnclaimed = ~uint64_t(0);
 constexpr int64_t kCountMask = (int64_t(1) << kBfsCountBits) - 1;
 constexpr int kBarrierWords = 4;
+constexpr int kGatherPer = kBfsMaxGrid / kBfsThreads;  // arrivals gathered per thread of workgroup 0
+constexpr int kGatherBatch = 1;
+constexpr int kFoldBatch = 1;  // chunk values in flight per thread in the window sum
 
-struct BfsShared {
+// The chunk's frontier vertices are needed only until each lane has mapped
+// its ranks to edges; the discoveries reuse that memory.
+struct ChunkVertices {
     int64_t eo[K + 2];       // edge offsets of the chunk's vertices; eo[n] is a sentinel
     int64_t shift[K + 1];    // row start - edge offset: edge index = rank + shift
     int32_t u[K + 1];        // the chunk's vertices
-    int32_t stage_v[K];      // discovered vertices that have edges
-    int64_t stage_d[K];      // and their degrees
+};
+struct ChunkFinds {
+    int64_t d[K];            // degrees of the discovered vertices that have edges
+    int64_t beg[K];          // their first edges
+    int32_t v[K];            // the vertices
+};
+
+struct BfsShared {
+    union {
+        ChunkVertices cv;
+        ChunkFinds cf;
+    };
     int64_t wave_tot[kWaves];
     uint64_t found_e;        // edges of the staged vertices
     uint32_t found;          // staged vertices
@@ -66,6 +80,7 @@ struct BfsShared {
     int32_t ok;
     int64_t p_n, p_e;        // the chunk's offsets in the next frontier
     int64_t res[kBarrierWords];
+    int64_t gather[kWaves][4];
 };
 
 __device__ __forceinline__ uint32_t lanes_before(uint64_t mask)
@@ -114,12 +129,62 @@ __device__ __forceinline__ int owner_of(const BfsShared& s, int n, int64_t r)
     int lo = 0, hi = n;
     while (hi - lo > 1) {
         const int mid = (lo + hi) >> 1;
-        if (s.eo[mid] <= r)
+        if (s.cv.eo[mid] <= r)
             lo = mid;
         else
             hi = mid;
     }
     return lo;
+}
+
+// Sum of the packed values of chunks [lo, lo + cnt) (cnt < kBfsMaxGrid),
+// read by the whole workgroup: every load in flight before the first wait,
+// so the window costs one round trip.  Integer sums, so the order of the
+// additions does not matter.  `ok` (every thread's) turns false if a wait
+// gave up.  Ends with the workgroup synchronised.
+__device__ __forceinline__ int64_t block_window_sum(const BfsArgs& a, BfsShared& s, int64_t lo, int64_t cnt,
+                                                    uint32_t tag, bool& ok)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int64_t sum = 0;
+    for (int i0 = 0; i0 < kGatherPer; i0 += kFoldBatch) {
+        if (threadIdx.x + int64_t(i0) * kBfsThreads >= cnt) break;
+        uint64_t w[kFoldBatch][2];
+#pragma unroll
+        for (int i = 0; i < kFoldBatch; ++i) {
+            const int64_t j = threadIdx.x + int64_t(i0 + i) * kBfsThreads;
+#pragma unroll
+            for (int k = 0; k < 2; ++k)
+                w[i][k] = (j < cnt) ? slot_load(a.slots + 2 * (lo + j) + k) : (uint64_t(tag) << 32);
+        }
+#pragma unroll
+        for (int i = 0; i < kFoldBatch; ++i) {
+            const int64_t j = threadIdx.x + int64_t(i0 + i) * kBfsThreads;
+            if (j < cnt) {
+#pragma unroll
+                for (int k = 0; k < 2; ++k)
+                    w[i][k] = await_word(a.slots + 2 * (lo + j) + k, w[i][k], tag, a.spin_limit, a.abort_word, ok);
+                sum += int64_t(uint64_t(uint32_t(w[i][0])) | (uint64_t(uint32_t(w[i][1])) << 32));
+            }
+        }
+    }
+    const bool wave_ok = __ballot(!ok) == 0;
+    sum = read_lane(wave_inclusive_scan<AddI64>(sum), 63);
+    if (lane == 0) {
+        s.gather[wave][0] = sum;
+        s.gather[wave][3] = wave_ok ? 1 : 0;
+    }
+    __syncthreads();
+    int64_t all = 0;
+    bool all_ok = true;
+#pragma unroll
+    for (int k = 0; k < kWaves; ++k) {
+        all += s.gather[k][0];
+        all_ok = all_ok && s.gather[k][3] != 0;
+    }
+    ok = all_ok;
+    __syncthreads();
+    return all;
 }
 
 // Grid barrier over flag words.  Every workgroup publishes the four 32-bit
@@ -131,7 +196,10 @@ __device__ __forceinline__ int owner_of(const BfsShared& s, int n, int64_t r)
 __device__ bool grid_barrier(const BfsArgs& a, BfsShared& s, uint32_t tag, const uint32_t (&v)[kBarrierWords])
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");  // this wave's frontier writes
+    static_assert(kGatherPer * kBfsThreads >= kBfsMaxGrid, "workgroup 0 gathers the whole grid");
+    // The workgroup barrier orders every wave's frontier writes before
+    // thread 0's agent-scope release below, which makes them visible to the
+    // whole device (a release is cumulative over what happens before it).
     __syncthreads();
     if (threadIdx.x == 0) {
         __hip_atomic_store(a.partial + blockIdx.x, int64_t(s.bad), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -140,25 +208,58 @@ __device__ bool grid_barrier(const BfsArgs& a, BfsShared& s, uint32_t tag, const
         for (int k = 0; k < kBarrierWords; ++k)
             slot_store(a.arrive + kBarrierWords * blockIdx.x + k, (uint64_t(tag) << 32) | v[k]);
     }
-    if (blockIdx.x == 0 && wave == 0) {
+    if (blockIdx.x == 0) {
+        // every thread of workgroup 0 gathers up to kGatherPer workgroups'
+        // arrivals, kGatherBatch of them in flight before the first wait
         bool ok = true;
         int64_t n = 0, e = 0, found = 0;
-        for (int64_t j = lane; j < int64_t(gridDim.x); j += 64) {
-            uint64_t w[kBarrierWords];
+        for (int i0 = 0; i0 < kGatherPer; i0 += kGatherBatch) {
+            if (threadIdx.x + int64_t(i0) * kBfsThreads >= int64_t(gridDim.x)) break;
+            uint64_t w[kGatherBatch][kBarrierWords];
 #pragma unroll
-            for (int k = 0; k < kBarrierWords; ++k) w[k] = slot_load(a.arrive + kBarrierWords * j + k);
+            for (int i = 0; i < kGatherBatch; ++i) {
+                const int64_t j = threadIdx.x + int64_t(i0 + i) * kBfsThreads;
 #pragma unroll
-            for (int k = 0; k < kBarrierWords; ++k)
-                w[k] = await_word(a.arrive + kBarrierWords * j + k, w[k], tag, a.spin_limit, a.abort_word, ok);
-            n += uint32_t(w[0]);
-            e += int64_t(uint64_t(uint32_t(w[1])) | (uint64_t(uint32_t(w[2])) << 32));
-            found += uint32_t(w[3]);
+                for (int k = 0; k < kBarrierWords; ++k)
+                    w[i][k] = (j < int64_t(gridDim.x)) ? slot_load(a.arrive + kBarrierWords * j + k)
+                                                       : (uint64_t(tag) << 32);
+            }
+#pragma unroll
+            for (int i = 0; i < kGatherBatch; ++i) {
+                const int64_t j = threadIdx.x + int64_t(i0 + i) * kBfsThreads;
+                if (j < int64_t(gridDim.x)) {
+#pragma unroll
+                    for (int k = 0; k < kBarrierWords; ++k)
+                        w[i][k] = await_word(a.arrive + kBarrierWords * j + k, w[i][k], tag, a.spin_limit,
+                                             a.abort_word, ok);
+                }
+                n += uint32_t(w[i][0]);
+                e += int64_t(uint64_t(uint32_t(w[i][1])) | (uint64_t(uint32_t(w[i][2])) << 32));
+                found += uint32_t(w[i][3]);
+            }
         }
-        const bool all_ok = __ballot(!ok) == 0;
+        // workgroup sums: waves through LDS
+        const bool wave_ok = __ballot(!ok) == 0;
         n = read_lane(wave_inclusive_scan<AddI64>(n), 63);
         e = read_lane(wave_inclusive_scan<AddI64>(e), 63);
         found = read_lane(wave_inclusive_scan<AddI64>(found), 63);
         if (lane == 0) {
+            s.gather[wave][0] = n;
+            s.gather[wave][1] = e;
+            s.gather[wave][2] = found;
+            s.gather[wave][3] = wave_ok ? 1 : 0;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            bool all_ok = true;
+            n = e = found = 0;
+#pragma unroll
+            for (int k = 0; k < kWaves; ++k) {
+                n += s.gather[k][0];
+                e += s.gather[k][1];
+                found += s.gather[k][2];
+                all_ok = all_ok && s.gather[k][3] != 0;
+            }
             if (all_ok) {
                 __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
                 const uint32_t out[kBarrierWords] = {uint32_t(n), uint32_t(uint64_t(e)), uint32_t(uint64_t(e) >> 32),
@@ -202,8 +303,8 @@ __global__ void __launch_bounds__(kBfsThreads) bfs_kernel(BfsArgs a)
     const int64_t B = gridDim.x, wg = blockIdx.x;
     const int64_t V = a.nv;
 
-    // Initial state: nothing claimed but the source (whose claim names no
-    // edge); the first frontier is the source if it has edges.  Every
+    // Initial state: nothing visited but the source; the first frontier is
+    // the source if it has edges.  Every
     // workgroup also counts the places where the row offsets decrease: rows
     // that overlap would break the bound of the chunk tables, so such a
     // graph is not searched.
@@ -212,7 +313,7 @@ __global__ void __launch_bounds__(kBfsThreads) bfs_kernel(BfsArgs a)
     uint32_t decreasing = 0;
     for (int64_t v = wg * kBfsThreads + tid; v < V; v += B * kBfsThreads) {
         const bool is_src = (v == a.src);
-        a.claim[v] = is_src ? uint64_t(a.ne) : kUnclaimed;
+        if ((v & 31) == 0) a.visited[v >> 5] = ((a.src >> 5) == (v >> 5)) ? (1u << (a.src & 31)) : 0u;
         a.level[v] = is_src ? 0 : -1;
         if (a.parent) a.parent[v] = is_src ? a.src : -1;
         decreasing += (a.row[v] > a.row[v + 1]) ? 1u : 0u;
@@ -221,6 +322,7 @@ __global__ void __launch_bounds__(kBfsThreads) bfs_kernel(BfsArgs a)
     if (wg == 0 && tid == 0 && d0 > 0) {
         a.queue[0][0] = a.src;
         a.edge_off[0][0] = 0;
+        a.edge_shift[0][0] = src_beg;
     }
     for (int64_t b = wg * kBfsThreads + tid; b * K < d0 && b < a.chunk_cap; b += B * kBfsThreads)
         a.chunk_first[0][b] = 0;
@@ -260,9 +362,11 @@ __global__ void __launch_bounds__(kBfsThreads) bfs_kernel(BfsArgs a)
         const int q = lev & 1;
         const int32_t* cur = a.queue[q];
         const int64_t* cur_eo = a.edge_off[q];
+        const int64_t* cur_sh = a.edge_shift[q];
         const int32_t* cur_cf = a.chunk_first[q];
         int32_t* nxt = a.queue[q ^ 1];
         int64_t* nxt_eo = a.edge_off[q ^ 1];
+        int64_t* nxt_sh = a.edge_shift[q ^ 1];
         int32_t* nxt_cf = a.chunk_first[q ^ 1];
         const int64_t nc = (D + K - 1) / K;
         if (nc > a.chunk_cap) break;  // cannot happen with non-decreasing rows (memory guard)
@@ -282,68 +386,66 @@ __global__ void __launch_bounds__(kBfsThreads) bfs_kernel(BfsArgs a)
             const int n = int(kend - k0 + 1);
             for (int j = tid; j < n; j += kBfsThreads) {
                 const int64_t eo = cur_eo[k0 + j];
-                const int32_t u = cur[k0 + j];
-                const int64_t beg = (uint32_t(u) < uint32_t(V)) ? a.row[u] : 0;
-                s.eo[j] = eo;
-                s.shift[j] = beg - eo;
-                s.u[j] = u;
+                s.cv.eo[j] = eo;
+                s.cv.shift[j] = cur_sh[k0 + j];
+                s.cv.u[j] = cur[k0 + j];
             }
             if (tid == 0) {
-                s.eo[n] = INT64_MAX;
+                s.cv.eo[n] = INT64_MAX;
                 s.found = 0;
                 s.found_e = 0;
             }
             __syncthreads();
 
-            // (b) claim every endpoint not yet discovered; stage the winners
-            int k[kPer];
+            // (b) map each rank to its edge and vertex, then claim every
+            //     endpoint not yet visited; stage the winners that have edges
             int64_t e[kPer];
-            int32_t v[kPer];
+            int32_t u[kPer];
+            bool act[kPer];
 #pragma unroll
             for (int p = 0; p < kPer; ++p) {
                 const int64_t r = r_lo + int64_t(p) * kBfsThreads + tid;
-                k[p] = -1;
+                act[p] = false;
                 e[p] = 0;
+                u[p] = -1;
                 if (r < r_hi) {
                     const int kk = owner_of(s, n, r);
-                    const int64_t ee = r + s.shift[kk];
-                    if (ee >= 0 && ee < a.ne) {
-                        k[p] = kk;
-                        e[p] = ee;
-                    } else {
-                        atomicAdd(&s.bad, 1u);
-                    }
+                    e[p] = r + s.cv.shift[kk];
+                    u[p] = s.cv.u[kk];
+                    act[p] = (e[p] >= 0 && e[p] < a.ne);
+                    if (!act[p]) atomicAdd(&s.bad, 1u);
                 }
             }
+            __syncthreads();  // the chunk's vertex table is dead: its memory holds the finds
+            int32_t v[kPer];
 #pragma unroll
-            for (int p = 0; p < kPer; ++p) v[p] = (k[p] >= 0) ? a.col[e[p]] : -1;
-            uint64_t cl[kPer];
+            for (int p = 0; p < kPer; ++p) v[p] = act[p] ? a.col[e[p]] : -1;
+            uint32_t bits[kPer];
 #pragma unroll
             for (int p = 0; p < kPer; ++p) {
-                if (k[p] >= 0 && uint32_t(v[p]) >= uint32_t(V)) {
+                if (act[p] && uint32_t(v[p]) >= uint32_t(V)) {
                     atomicAdd(&s.bad, 1u);
-                    k[p] = -1;
+                    act[p] = false;
                 }
-                cl[p] = (k[p] >= 0) ? a.claim[v[p]] : 0;  // a stale "none" only costs a failed swap
+                bits[p] = act[p] ? a.visited[v[p] >> 5] : ~0u;  // a stale clear bit only costs an atomic
             }
             bool win[kPer];
 #pragma unroll
             for (int p = 0; p < kPer; ++p) {
+                const uint32_t mask = 1u << (v[p] & 31);
                 win[p] = false;
-                if (k[p] >= 0 && cl[p] == kUnclaimed)
-                    win[p] = atomicCAS(reinterpret_cast<unsigned long long*>(a.claim + v[p]),
-                                       (unsigned long long)kUnclaimed,
-                                       (unsigned long long)e[p]) == (unsigned long long)kUnclaimed;
+                if (act[p] && !(bits[p] & mask))
+                    win[p] = !(atomicOr(a.visited + (v[p] >> 5), mask) & mask);
             }
-            int64_t dv[kPer];
+            int64_t dv[kPer], bv[kPer];
 #pragma unroll
             for (int p = 0; p < kPer; ++p) {
                 dv[p] = 0;
+                bv[p] = 0;
                 if (win[p]) {
                     a.level[v[p]] = lev + 1;
-                    if (a.parent) a.parent[v[p]] = s.u[k[p]];
-                    int64_t beg;
-                    dv[p] = row_range(a, v[p], &beg);
+                    if (a.parent) a.parent[v[p]] = u[p];
+                    dv[p] = row_range(a, v[p], &bv[p]);
                     if (dv[p] < 0) {
                         atomicAdd(&s.bad, 1u);
                         dv[p] = 0;
@@ -363,8 +465,9 @@ __global__ void __launch_bounds__(kBfsThreads) bfs_kernel(BfsArgs a)
                 base = __builtin_amdgcn_readlane(base, 0);
                 if (keep) {
                     const uint32_t pos = base + lanes_before(m);  // < K: one discovery per edge at most
-                    s.stage_v[pos] = v[p];
-                    s.stage_d[pos] = dv[p];
+                    s.cf.v[pos] = v[p];
+                    s.cf.d[pos] = dv[p];
+                    s.cf.beg[pos] = bv[p];
                     atomicAdd(reinterpret_cast<unsigned long long*>(&s.found_e), (unsigned long long)dv[p]);
                 }
             }
@@ -377,16 +480,16 @@ __global__ void __launch_bounds__(kBfsThreads) bfs_kernel(BfsArgs a)
             if (wave == 0) {
                 const int64_t packed = (A_e << kBfsCountBits) | A_n;
                 publish_slot(a.slots + 2 * c, packed, tag, lane);
+            }
+            {
                 const int64_t lo = (c - B + 1 > 0) ? c - B + 1 : 0;
                 bool good = true;
-                const int64_t between =
-                    window_fold<AddI64>(a.slots, lo, c - lo, tag, a.spin_limit, a.abort_word, lane, good);
-                const bool all_good = __ballot(!good) == 0;
-                if (lane == 0) {
+                const int64_t between = block_window_sum(a, s, lo, c - lo, tag, good);
+                if (tid == 0) {
                     s.p_n = run_n + (between & kCountMask);
                     s.p_e = run_e + (between >> kBfsCountBits);
-                    s.ok = all_good ? 1 : 0;
-                    if (!all_good) give_up(a, tag);
+                    s.ok = good ? 1 : 0;
+                    if (!good) give_up(a, tag);
                 }
             }
             __syncthreads();
@@ -408,7 +511,7 @@ __global__ void __launch_bounds__(kBfsThreads) bfs_kernel(BfsArgs a)
 #pragma unroll
             for (int t = 0; t < kPer; ++t) {
                 const int j = tid * kPer + t;
-                dl[t] = (j < A_n) ? s.stage_d[j] : 0;
+                dl[t] = (j < A_n) ? s.cf.d[j] : 0;
                 dsum += dl[t];
             }
             int64_t tot = 0;
@@ -419,8 +522,9 @@ __global__ void __launch_bounds__(kBfsThreads) bfs_kernel(BfsArgs a)
                 if (j < A_n) {
                     const int64_t pos = p_n + j;
                     if (pos < V) {
-                        nxt[pos] = s.stage_v[j];
+                        nxt[pos] = s.cf.v[j];
                         nxt_eo[pos] = eoff;
+                        nxt_sh[pos] = s.cf.beg[j] - eoff;
                         for (int64_t b = (eoff + K - 1) / K; b * K < eoff + dl[t] && b < a.chunk_cap; ++b)
                             nxt_cf[b] = int32_t(pos);
                     }

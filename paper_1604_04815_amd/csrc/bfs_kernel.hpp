@@ -27,9 +27,10 @@ struct BfsArgs {
     int32_t* level;          // V: level of each vertex, -1 unreached
     int32_t* parent;         // V or null: a BFS-tree parent (src for src, -1 unreached)
     int64_t* stats;          // 4 or null: levels, vertices reached, edges scanned, bad entries
-    uint64_t* claim;         // V: edge index that discovered the vertex (all ones: not yet)
+    uint32_t* visited;       // ceil(V / 32): one bit per vertex, set by the vertex's claim
     int32_t* queue[2];       // V each: frontier vertices (those with at least one edge)
     int64_t* edge_off[2];    // V each: exclusive prefix of the frontier's degrees
+    int64_t* edge_shift[2];  // V each: first edge of the vertex minus its edge offset
     int32_t* chunk_first[2]; // ceil(E / chunk) + 1 each: frontier index holding each chunk's first edge
     int64_t chunk_cap;       // entries of each chunk_first array (ceil(E / chunk) + 1)
     uint64_t* slots;         // 2 * chunk_cap flag words: packed per-chunk (edges << 21 | vertices)

@@ -747,8 +747,9 @@ struct BfsWorkspace {
     uint64_t* go = nullptr;
     uint32_t* abort_word = nullptr;
     int64_t* partial = nullptr;
-    uint64_t* claim = nullptr;
+    uint32_t* visited = nullptr;
     int64_t* edge_off[2] = {nullptr, nullptr};
+    int64_t* edge_shift[2] = {nullptr, nullptr};
     int32_t* queue[2] = {nullptr, nullptr};
     int32_t* chunk_first[2] = {nullptr, nullptr};
     uint64_t next_tag = 0;  // the next launch's tags start above this
@@ -779,8 +780,8 @@ lscan_status ensure_bfs_workspace(BfsWorkspace& ws, hipStream_t stream, int64_t 
     }
     // flag region first (zeroed), then 8-byte arrays, then 4-byte arrays
     const size_t flag_words = 2 * size_t(chunks) + 4 * size_t(grid) + 4 + 1;
-    const size_t bytes = flag_words * 8 + size_t(grid) * 8 + size_t(nv) * 8 * 3 + size_t(nv) * 4 * 2 +
-                         size_t(chunks) * 4 * 2;
+    const size_t bytes = flag_words * 8 + size_t(grid) * 8 + size_t(nv) * 8 * 4 + size_t(nv) * 4 * 2 +
+                         size_t(chunks) * 4 * 2 + size_t((nv + 31) / 32) * 4;
     e = hipMalloc(reinterpret_cast<void**>(&ws.mem), bytes);
     if (e != hipSuccess) {
         (void)hipGetLastError();
@@ -794,13 +795,15 @@ lscan_status ensure_bfs_workspace(BfsWorkspace& ws, hipStream_t stream, int64_t 
     ws.abort_word = reinterpret_cast<uint32_t*>(ws.go + 4);
     ws.flag_bytes = flag_words * 8;
     ws.partial = reinterpret_cast<int64_t*>(w + flag_words);
-    ws.claim = reinterpret_cast<uint64_t*>(ws.partial + grid);
-    ws.edge_off[0] = reinterpret_cast<int64_t*>(ws.claim + nv);
+    ws.edge_off[0] = ws.partial + grid;
     ws.edge_off[1] = ws.edge_off[0] + nv;
-    ws.queue[0] = reinterpret_cast<int32_t*>(ws.edge_off[1] + nv);
+    ws.edge_shift[0] = ws.edge_off[1] + nv;
+    ws.edge_shift[1] = ws.edge_shift[0] + nv;
+    ws.queue[0] = reinterpret_cast<int32_t*>(ws.edge_shift[1] + nv);
     ws.queue[1] = ws.queue[0] + nv;
     ws.chunk_first[0] = ws.queue[1] + nv;
     ws.chunk_first[1] = ws.chunk_first[0] + chunks;
+    ws.visited = reinterpret_cast<uint32_t*>(ws.chunk_first[1] + chunks);
     ws.cap_v = nv;
     ws.cap_chunks = chunks;
     ws.cap_grid = grid;
@@ -880,10 +883,11 @@ lscan_status bfs_run(const int64_t* row, const int32_t* col, int64_t nv, int64_t
     a.level = level;
     a.parent = parent;
     a.stats = stats;
-    a.claim = bw.claim;
+    a.visited = bw.visited;
     for (int k = 0; k < 2; ++k) {
         a.queue[k] = bw.queue[k];
         a.edge_off[k] = bw.edge_off[k];
+        a.edge_shift[k] = bw.edge_shift[k];
         a.chunk_first[k] = bw.chunk_first[k];
     }
     a.chunk_cap = bw.cap_chunks;

@@ -54,24 +54,12 @@ constexpr int kGatherPer = kBfsMaxGrid / kBfsThreads;  // arrivals gathered per 
 constexpr int kGatherBatch = 1;
 constexpr int kFoldBatch = 1;  // chunk values in flight per thread in the window sum
 
-// The chunk's frontier vertices are needed only until each lane has mapped
-// its ranks to edges; the discoveries reuse that memory.
-struct ChunkVertices {
+struct BfsShared {
     int64_t eo[K + 2];       // edge offsets of the chunk's vertices; eo[n] is a sentinel
     int64_t shift[K + 1];    // row start - edge offset: edge index = rank + shift
     int32_t u[K + 1];        // the chunk's vertices
-};
-struct ChunkFinds {
-    int64_t d[K];            // degrees of the discovered vertices that have edges
-    int64_t beg[K];          // their first edges
-    int32_t v[K];            // the vertices
-};
-
-struct BfsShared {
-    union {
-        ChunkVertices cv;
-        ChunkFinds cf;
-    };
+    int32_t stage[2][K];     // discovered vertices that have edges: the chunk being
+                             // claimed and the one waiting to be placed
     int64_t wave_tot[kWaves];
     uint64_t found_e;        // edges of the staged vertices
     uint32_t found;          // staged vertices
@@ -129,7 +117,7 @@ __device__ __forceinline__ int owner_of(const BfsShared& s, int n, int64_t r)
     int lo = 0, hi = n;
     while (hi - lo > 1) {
         const int mid = (lo + hi) >> 1;
-        if (s.cv.eo[mid] <= r)
+        if (s.eo[mid] <= r)
             lo = mid;
         else
             hi = mid;
@@ -374,164 +362,183 @@ __global__ void __launch_bounds__(kBfsThreads) bfs_kernel(BfsArgs a)
         int64_t run_n = 0, run_e = 0;    // offsets through this workgroup's previous chunk
         int64_t mine_n = 0, mine_e = 0;  // what this workgroup placed in this level
         if (tid == 0) s.found_all = 0;
-        for (int64_t c = wg; c < nc; c += B) {
-            // (a) the chunk's frontier vertices
-            const int64_t r_lo = c * K;
-            const int64_t r_hi = (D - r_lo < K) ? D : r_lo + K;
-            int64_t k0 = cur_cf[c];
-            int64_t kend = (c + 1 < nc) ? int64_t(cur_cf[c + 1]) : f - 1;
-            k0 = (k0 < 0) ? 0 : (k0 >= f ? f - 1 : k0);  // memory guards: the table is consistent
-            kend = (kend < k0) ? k0 : (kend >= f ? f - 1 : kend);
-            if (kend - k0 > K) kend = k0 + K;
-            const int n = int(kend - k0 + 1);
-            for (int j = tid; j < n; j += kBfsThreads) {
-                const int64_t eo = cur_eo[k0 + j];
-                s.cv.eo[j] = eo;
-                s.cv.shift[j] = cur_sh[k0 + j];
-                s.cv.u[j] = cur[k0 + j];
-            }
-            if (tid == 0) {
-                s.cv.eo[n] = INT64_MAX;
-                s.found = 0;
-                s.found_e = 0;
-            }
-            __syncthreads();
-
-            // (b) map each rank to its edge and vertex, then claim every
-            //     endpoint not yet visited; stage the winners that have edges
-            int64_t e[kPer];
-            int32_t u[kPer];
-            bool act[kPer];
-#pragma unroll
-            for (int p = 0; p < kPer; ++p) {
-                const int64_t r = r_lo + int64_t(p) * kBfsThreads + tid;
-                act[p] = false;
-                e[p] = 0;
-                u[p] = -1;
-                if (r < r_hi) {
-                    const int kk = owner_of(s, n, r);
-                    e[p] = r + s.cv.shift[kk];
-                    u[p] = s.cv.u[kk];
-                    act[p] = (e[p] >= 0 && e[p] < a.ne);
-                    if (!act[p]) atomicAdd(&s.bad, 1u);
+        // Software pipeline: the iteration that claims chunk c places this
+        // workgroup's previous chunk c - B, whose window of counts was
+        // published about a round earlier, so placing rarely waits.
+        int64_t prev_c = -1, prev_n = 0, prev_e = 0;
+        int sb = 0;  // stage buffer of the chunk being claimed
+        for (int64_t c = wg;; c += B) {
+            const bool have = c < nc;
+            int64_t A_n = 0, A_e = 0;  // the claimed chunk's staged vertices and their edges
+            if (have) {
+                // (a) the chunk's frontier vertices
+                const int64_t r_lo = c * K;
+                const int64_t r_hi = (D - r_lo < K) ? D : r_lo + K;
+                int64_t k0 = cur_cf[c];
+                int64_t kend = (c + 1 < nc) ? int64_t(cur_cf[c + 1]) : f - 1;
+                k0 = (k0 < 0) ? 0 : (k0 >= f ? f - 1 : k0);  // memory guards: the table is consistent
+                kend = (kend < k0) ? k0 : (kend >= f ? f - 1 : kend);
+                if (kend - k0 > K) kend = k0 + K;
+                const int n = int(kend - k0 + 1);
+                for (int j = tid; j < n; j += kBfsThreads) {
+                    s.eo[j] = cur_eo[k0 + j];
+                    s.shift[j] = cur_sh[k0 + j];
+                    s.u[j] = cur[k0 + j];
                 }
-            }
-            __syncthreads();  // the chunk's vertex table is dead: its memory holds the finds
-            int32_t v[kPer];
-#pragma unroll
-            for (int p = 0; p < kPer; ++p) v[p] = act[p] ? a.col[e[p]] : -1;
-            uint32_t bits[kPer];
-#pragma unroll
-            for (int p = 0; p < kPer; ++p) {
-                if (act[p] && uint32_t(v[p]) >= uint32_t(V)) {
-                    atomicAdd(&s.bad, 1u);
-                    act[p] = false;
-                }
-                bits[p] = act[p] ? a.visited[v[p] >> 5] : ~0u;  // a stale clear bit only costs an atomic
-            }
-            bool win[kPer];
-#pragma unroll
-            for (int p = 0; p < kPer; ++p) {
-                const uint32_t mask = 1u << (v[p] & 31);
-                win[p] = false;
-                if (act[p] && !(bits[p] & mask))
-                    win[p] = !(atomicOr(a.visited + (v[p] >> 5), mask) & mask);
-            }
-            int64_t dv[kPer], bv[kPer];
-#pragma unroll
-            for (int p = 0; p < kPer; ++p) {
-                dv[p] = 0;
-                bv[p] = 0;
-                if (win[p]) {
-                    a.level[v[p]] = lev + 1;
-                    if (a.parent) a.parent[v[p]] = u[p];
-                    dv[p] = row_range(a, v[p], &bv[p]);
-                    if (dv[p] < 0) {
-                        atomicAdd(&s.bad, 1u);
-                        dv[p] = 0;
-                    }
-                }
-            }
-#pragma unroll
-            for (int p = 0; p < kPer; ++p) {
-                const bool keep = win[p] && dv[p] > 0;
-                const uint64_t m_all = __ballot(win[p]);
-                const uint64_t m = __ballot(keep);
-                uint32_t base = 0;
-                if (lane == 0) {
-                    if (m_all) atomicAdd(&s.found_all, uint32_t(__popcll(m_all)));
-                    if (m) base = atomicAdd(&s.found, uint32_t(__popcll(m)));
-                }
-                base = __builtin_amdgcn_readlane(base, 0);
-                if (keep) {
-                    const uint32_t pos = base + lanes_before(m);  // < K: one discovery per edge at most
-                    s.cf.v[pos] = v[p];
-                    s.cf.d[pos] = dv[p];
-                    s.cf.beg[pos] = bv[p];
-                    atomicAdd(reinterpret_cast<unsigned long long*>(&s.found_e), (unsigned long long)dv[p]);
-                }
-            }
-            __syncthreads();
-            const int64_t A_n = s.found;
-            const int64_t A_e = int64_t(s.found_e);
-
-            // (c) publish (edges, vertices) packed; offsets = own previous
-            //     running total + the values of the chunks in between
-            if (wave == 0) {
-                const int64_t packed = (A_e << kBfsCountBits) | A_n;
-                publish_slot(a.slots + 2 * c, packed, tag, lane);
-            }
-            {
-                const int64_t lo = (c - B + 1 > 0) ? c - B + 1 : 0;
-                bool good = true;
-                const int64_t between = block_window_sum(a, s, lo, c - lo, tag, good);
                 if (tid == 0) {
-                    s.p_n = run_n + (between & kCountMask);
-                    s.p_e = run_e + (between >> kBfsCountBits);
-                    s.ok = good ? 1 : 0;
-                    if (!good) give_up(a, tag);
+                    s.eo[n] = INT64_MAX;
+                    s.found = 0;
+                    s.found_e = 0;
                 }
-            }
-            __syncthreads();
-            if (!s.ok) {
-                ok = false;
-                break;
-            }
-            const int64_t p_n = s.p_n, p_e = s.p_e;
-            run_n = p_n + A_n;
-            run_e = p_e + A_e;
-            mine_n += A_n;
-            mine_e += A_e;
+                __syncthreads();
 
-            // (d) place the staged vertices at p_n ..: queue entry, edge
-            //     offset, and the next level's chunk table entries that fall
-            //     in their edge ranges
-            int64_t dl[kPer];
-            int64_t dsum = 0;
+                // (b) map each rank to its edge and vertex, then claim every
+                //     endpoint not yet visited; stage the winners that have edges
+                int64_t e[kPer];
+                int32_t u[kPer];
+                bool act[kPer];
 #pragma unroll
-            for (int t = 0; t < kPer; ++t) {
-                const int j = tid * kPer + t;
-                dl[t] = (j < A_n) ? s.cf.d[j] : 0;
-                dsum += dl[t];
-            }
-            int64_t tot = 0;
-            int64_t eoff = p_e + block_exclusive_sum(dsum, s, &tot);
-#pragma unroll
-            for (int t = 0; t < kPer; ++t) {
-                const int j = tid * kPer + t;
-                if (j < A_n) {
-                    const int64_t pos = p_n + j;
-                    if (pos < V) {
-                        nxt[pos] = s.cf.v[j];
-                        nxt_eo[pos] = eoff;
-                        nxt_sh[pos] = s.cf.beg[j] - eoff;
-                        for (int64_t b = (eoff + K - 1) / K; b * K < eoff + dl[t] && b < a.chunk_cap; ++b)
-                            nxt_cf[b] = int32_t(pos);
+                for (int p = 0; p < kPer; ++p) {
+                    const int64_t r = r_lo + int64_t(p) * kBfsThreads + tid;
+                    act[p] = false;
+                    e[p] = 0;
+                    u[p] = -1;
+                    if (r < r_hi) {
+                        const int kk = owner_of(s, n, r);
+                        e[p] = r + s.shift[kk];
+                        u[p] = s.u[kk];
+                        act[p] = (e[p] >= 0 && e[p] < a.ne);
+                        if (!act[p]) atomicAdd(&s.bad, 1u);
                     }
-                    eoff += dl[t];
+                }
+                int32_t v[kPer];
+#pragma unroll
+                for (int p = 0; p < kPer; ++p) v[p] = act[p] ? a.col[e[p]] : -1;
+                uint32_t bits[kPer];
+#pragma unroll
+                for (int p = 0; p < kPer; ++p) {
+                    if (act[p] && uint32_t(v[p]) >= uint32_t(V)) {
+                        atomicAdd(&s.bad, 1u);
+                        act[p] = false;
+                    }
+                    bits[p] = act[p] ? a.visited[v[p] >> 5] : ~0u;  // a stale clear bit only costs an atomic
+                }
+                bool win[kPer];
+#pragma unroll
+                for (int p = 0; p < kPer; ++p) {
+                    const uint32_t mask = 1u << (v[p] & 31);
+                    win[p] = false;
+                    if (act[p] && !(bits[p] & mask))
+                        win[p] = !(atomicOr(a.visited + (v[p] >> 5), mask) & mask);
+                }
+                int64_t dv[kPer];
+#pragma unroll
+                for (int p = 0; p < kPer; ++p) {
+                    dv[p] = 0;
+                    if (win[p]) {
+                        a.level[v[p]] = lev + 1;
+                        if (a.parent) a.parent[v[p]] = u[p];
+                        int64_t beg;
+                        dv[p] = row_range(a, v[p], &beg);
+                        if (dv[p] < 0) {
+                            atomicAdd(&s.bad, 1u);
+                            dv[p] = 0;
+                        }
+                    }
+                }
+#pragma unroll
+                for (int p = 0; p < kPer; ++p) {
+                    const bool keep = win[p] && dv[p] > 0;
+                    const uint64_t m_all = __ballot(win[p]);
+                    const uint64_t m = __ballot(keep);
+                    uint32_t base = 0;
+                    if (lane == 0) {
+                        if (m_all) atomicAdd(&s.found_all, uint32_t(__popcll(m_all)));
+                        if (m) base = atomicAdd(&s.found, uint32_t(__popcll(m)));
+                    }
+                    base = __builtin_amdgcn_readlane(base, 0);
+                    if (keep) {
+                        const uint32_t pos = base + lanes_before(m);  // < K: one discovery per edge at most
+                        s.stage[sb][pos] = v[p];
+                        atomicAdd(reinterpret_cast<unsigned long long*>(&s.found_e), (unsigned long long)dv[p]);
+                    }
+                }
+                __syncthreads();
+                A_n = s.found;
+                A_e = int64_t(s.found_e);
+
+                // (c) publish (edges, vertices) packed, at once
+                if (wave == 0) publish_slot(a.slots + 2 * c, (A_e << kBfsCountBits) | A_n, tag, lane);
+                mine_n += A_n;
+                mine_e += A_e;
+                if (prev_c < 0) {
+                    prev_c = c;
+                    prev_n = A_n;
+                    prev_e = A_e;
+                    sb ^= 1;
+                    continue;
                 }
             }
-            __syncthreads();  // LDS is reused by the next chunk
+            if (prev_c < 0) break;  // no chunks in this level
+
+            // (d) place the previous chunk: offsets = own running total + the
+            //     values of the chunks in between; then its vertices, their
+            //     edge offsets and first edges, and the next level's chunk
+            //     table entries that fall in their edge ranges
+            {
+                const int32_t* st = s.stage[sb ^ 1];  // where the previous chunk was staged
+                int32_t vl[kPer];
+                int64_t bl[kPer], dl[kPer];
+                int64_t dsum = 0;
+#pragma unroll
+                for (int t = 0; t < kPer; ++t) {  // loads in flight during the window wait
+                    const int j = tid * kPer + t;
+                    vl[t] = -1;
+                    bl[t] = 0;
+                    dl[t] = 0;
+                    if (j < prev_n) {
+                        vl[t] = st[j];
+                        bl[t] = a.row[vl[t]];
+                        dl[t] = a.row[vl[t] + 1] - bl[t];
+                    }
+                }
+                const int64_t lo = (prev_c - B + 1 > 0) ? prev_c - B + 1 : 0;
+                bool good = true;
+                const int64_t between = block_window_sum(a, s, lo, prev_c - lo, tag, good);
+                if (!good) {
+                    if (tid == 0) give_up(a, tag);
+                    ok = false;
+                    break;
+                }
+                const int64_t p_n = run_n + (between & kCountMask);
+                const int64_t p_e = run_e + (between >> kBfsCountBits);
+                run_n = p_n + prev_n;
+                run_e = p_e + prev_e;
+#pragma unroll
+                for (int t = 0; t < kPer; ++t) dsum += dl[t];
+                int64_t tot = 0;
+                int64_t eoff = p_e + block_exclusive_sum(dsum, s, &tot);
+#pragma unroll
+                for (int t = 0; t < kPer; ++t) {
+                    const int j = tid * kPer + t;
+                    if (j < prev_n) {
+                        const int64_t pos = p_n + j;
+                        if (pos < V) {
+                            nxt[pos] = vl[t];
+                            nxt_eo[pos] = eoff;
+                            nxt_sh[pos] = bl[t] - eoff;
+                            for (int64_t b = (eoff + K - 1) / K; b * K < eoff + dl[t] && b < a.chunk_cap; ++b)
+                                nxt_cf[b] = int32_t(pos);
+                        }
+                        eoff += dl[t];
+                    }
+                }
+            }
+            if (!have) break;
+            prev_c = c;
+            prev_n = A_n;
+            prev_e = A_e;
+            sb ^= 1;
         }
         if (!ok) break;
         // (e) the level barrier: the next frontier's size and edges

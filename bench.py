@@ -328,10 +328,11 @@ def bench_bfs(binding, workloads, steps, warmup, num_sources=8):
     num_sources seeded sources that have at least one edge.  Rate: edges
     scanned per second (the out-degrees of the reached vertices over the
     search time; Graph500 counts each undirected edge once, half of that).
-    Algorithmic bytes per search: 16 per vertex (claim, level, parent set
-    up), 40 per reached vertex (row offsets 16, frontier write and read 8,
-    claim swap 8, level and parent 8), 12 per scanned edge (column 4, claim
-    read 8).  Every search is validated on the device: levels of both ends of
+    Algorithmic bytes per search: 16 per vertex (row offsets read once for
+    the monotonicity check, level and parent set up), 64 per reached vertex
+    (row offsets 16, level and parent 8, frontier entry -- vertex, edge
+    offset, first edge, 20 bytes -- written and read), 8 per scanned edge
+    (column 4, visited word 4).  Every search is validated on the device: levels of both ends of
     every edge differ by at most one where the tail is reached, every reached
     vertex other than the source has a parent one level up with an edge to
     it."""
@@ -373,7 +374,7 @@ def bench_bfs(binding, workloads, steps, warmup, num_sources=8):
             ok &= bool((keys[i] == q).all().item())
         ok &= int(deg[reached].sum().item()) == st[2] and st[3] == 0
         valid &= ok
-        nbytes = 16 * nv + 40 * st[1] + 12 * st[2]
+        nbytes = 16 * nv + 64 * st[1] + 8 * st[2]
         runs.append({"source": int(src), "ms": round(ms, 4), "launch_ms_mean": round(statistics.mean(per), 4),
                      "levels": st[0], "reached": st[1], "edges_scanned": st[2],
                      "gteps_scanned": round(st[2] / (ms * 1e-3) / 1e9, 3), "bytes": nbytes,
@@ -644,7 +645,8 @@ def main(argv=None) -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--only", default="", help="'1a': only the headline scan and a same-size copy; 'serve': only the serving trace")
+    ap.add_argument("--only", default="", help="'1a': only the headline scan and a same-size copy; 'serve': only the serving trace; "
+                    "'bfs': only the breadth-first search line")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--serve-seconds", type=float, default=5.0,
@@ -678,6 +680,10 @@ def main(argv=None) -> int:
     dev = torch.cuda.get_device_properties(0)
     log(f"device {dev.name}, {dev.multi_processor_count} CUs")
 
+    if args.only == "bfs":
+        bf = bench_bfs(binding, workloads, max(3, args.steps // 2), 1)
+        print(json.dumps({"bfs_rmat22": bf}), flush=True)
+        return 0
     if args.only == "serve":
         sv = bench_serving(binding, workloads, args.serve_seconds, args.serve_rate)
         hv = bench_serving(binding, workloads, args.serve_heavy_seconds, args.serve_heavy_rate)

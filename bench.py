@@ -395,6 +395,37 @@ def bench_bfs(binding, workloads, steps, warmup, num_sources=8):
     return e
 
 
+def bench_custom_affine(binding, steps, warmup):
+    """A scan with a user-defined operator built outside the library
+    (include/lscan_custom.hpp): composition of affine maps mod 2^32 over 2^27
+    maps, 8 bytes in and 8 bytes out each, for each example tile shape."""
+    import numpy as np
+    import torch
+
+    n = 1 << 27
+    g = np.random.default_rng(1604 + 1100)
+    ab = g.integers(0, 1 << 32, (n, 2), dtype=np.uint64).astype(np.uint32)
+    x = torch.from_numpy(ab.view(np.int32).reshape(-1)).to("cuda")
+    y = torch.empty_like(x)
+    del ab
+    kernels = binding.affine_example_kernels()
+    shapes = {}
+    for name in ("default", "small", "wide"):
+        k = kernels[name]
+        ms, per = time_steps(lambda: binding.scan_custom(k, x, n, out=y), steps, warmup)
+        binding.lscan_check(torch.cuda.current_stream().cuda_stream)
+        info = binding.lscan_last_launch()
+        e = rate_entry(16 * n, n, ms, per)
+        e.update({"block_threads": info.block_threads, "tile_elems": info.tile_elems, "grid": info.grid})
+        shapes[name] = e
+    best = max(shapes, key=lambda k: shapes[k]["gbs"])
+    out = dict(shapes[best])
+    out.update({"n": n, "bytes": 16 * n, "best_shape": best, "shapes": shapes})
+    del x, y
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_parallel_scan(x, repeats: int = 3):
     """Context, not the oracle: a two-pass chunked scan over all host cores
     (per-chunk totals, a scan of the totals, per-chunk scans with their
@@ -646,7 +677,7 @@ def main(argv=None) -> int:
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--only", default="", help="'1a': only the headline scan and a same-size copy; 'serve': only the serving trace; "
-                    "'bfs': only the breadth-first search line")
+                    "'bfs': only the breadth-first search line; 'custom': only the user-operator line")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--serve-seconds", type=float, default=5.0,
@@ -680,6 +711,9 @@ def main(argv=None) -> int:
     dev = torch.cuda.get_device_properties(0)
     log(f"device {dev.name}, {dev.multi_processor_count} CUs")
 
+    if args.only == "custom":
+        print(json.dumps({"custom_affine_2p27": bench_custom_affine(binding, args.steps, args.warmup)}), flush=True)
+        return 0
     if args.only == "bfs":
         bf = bench_bfs(binding, workloads, max(3, args.steps // 2), 1)
         print(json.dumps({"bfs_rmat22": bf}), flush=True)
@@ -763,6 +797,9 @@ def main(argv=None) -> int:
         bf = configs["bfs_rmat22"]
         log(f"  {bf['gteps_scanned_hmean']} G edges scanned/s (harmonic mean), median {bf['ms_median']} ms, "
             f"valid={bf['all_valid']}")
+        log("user-defined operator: affine maps mod 2^32, 2^27 maps")
+        configs["custom_affine_2p27"] = bench_custom_affine(binding, args.steps, args.warmup)
+        log(f"  {configs['custom_affine_2p27']['gbs']} GB/s ({configs['custom_affine_2p27']['best_shape']})")
         log("the paper's prefix chain: int32 add N=2^20 and N=2^28")
         configs["int32_add_2p20_chain"] = bench_chain(
             binding, workloads.uniform_int(1 << 20, -1000, 1000, workloads.seed_for(0)), 10)

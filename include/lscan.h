@@ -297,6 +297,35 @@ lscan_status lscan_radix_offsets(const void *keys, int64_t n, lscan_dtype dt,
                                  void *stream);
 
 /*
+ * Scan with a user-defined associative operator.  The paper writes its
+ * method as templates over the element type and operator and supports only
+ * built-in scalar types (Section 6); here any trivially copyable value type
+ * works.  The kernel is the library's persistent
+ * single-pass scan instantiated for the caller's operator in the caller's own
+ * HIP translation unit through include/lscan_custom.hpp, which returns a
+ * handle (a pointer to a static description of the kernel; it stays valid
+ * while that code object is loaded).  The library runs it like its own
+ * kernels: per-stream flag workspace, co-residency test per (kernel, grid),
+ * ordering across streams, the window or chain hand-off.
+ *   kernel  handle from lscan_custom::kernel<Op, T, R>(); the operator must
+ *           be associative; it need not be commutative (the earlier operand
+ *           is always on the left)
+ *   x, y    device arrays of n elements of the operator's In and Out types;
+ *           aligned to min(sizeof, 16) bytes; y == x allowed when In and Out
+ *           have the same size, other overlaps are invalid
+ *   flags   0, LSCAN_F_EXCLUSIVE and/or LSCAN_F_DETERMINISTIC
+ *   p       null or groups_per_cu / handoff (a tile shape: the kernel fixes
+ *           it, LSCAN_ERR_UNSUPPORTED)
+ * A handle built against a different version of the headers is undefined
+ * behaviour; a null or malformed handle is LSCAN_ERR_INVALID_ARG.
+ */
+typedef struct lscan_custom_kernel lscan_custom_kernel;
+lscan_status lscan_scan_custom(const lscan_custom_kernel *kernel,
+                               const void *x, void *y, int64_t n,
+                               uint32_t flags, const lscan_params *p,
+                               void *stream);
+
+/*
  * Breadth-first search on the device, the graph search that Section 6 names
  * as the next use of the paper's inter-block hand-off (Section 4.3): one
  * persistent launch runs the whole search.  The edges of each level's

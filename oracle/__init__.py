@@ -97,6 +97,8 @@ class Oracle:
         lib.oracle_radix_offsets.restype = i64
         lib.oracle_argscan.argtypes = [vp, vp, i64, i32, i32, i32]
         lib.oracle_argscan.restype = i32
+        lib.oracle_affine_scan.argtypes = [vp, vp, i64, i32]
+        lib.oracle_affine_scan.restype = i32
         lib.oracle_bfs_levels.argtypes = [vp, vp, i64, i64, vp, vp]
         lib.oracle_bfs_levels.restype = i64
         self.lib = lib
@@ -189,6 +191,18 @@ class Oracle:
         return y
 
 
+    def affine_scan(self, ab, exclusive=False):
+        """Scan of affine maps x -> a*x + b mod 2^32 under composition (the
+        earlier map first); ``ab`` is a uint32 array of shape (n, 2) holding
+        (a, b) per map; returns the composed prefixes in the same shape."""
+        ab = np.ascontiguousarray(ab, dtype=np.uint32).reshape(-1, 2)
+        out = np.empty_like(ab)
+        rc = self.lib.oracle_affine_scan(ab.ctypes.data, out.ctypes.data, ab.shape[0], int(bool(exclusive)))
+        if rc != 0:
+            raise ValueError(f"oracle_affine_scan rejected its arguments (rc={rc})")
+        return out
+
+
     def bfs_levels(self, row_ptr, col, src):
         """BFS levels from ``src`` over a CSR graph (int64 row_ptr, int32
         col): int32 array, -1 for unreachable vertices."""
@@ -237,6 +251,10 @@ def radix_offsets(keys, shift, bits, block_items):
 
 def argscan(x, dtype="int32", op="argmax", exclusive=False):
     return default().argscan(x, dtype, op, exclusive)
+
+
+def affine_scan(ab, exclusive=False):
+    return default().affine_scan(ab, exclusive)
 
 
 def bfs_levels(row_ptr, col, src):

@@ -388,6 +388,41 @@ int oracle_argscan(const void *x, int64_t *y, int64_t n, int dtype,
 }
 
 /* ------------------------------------------------------------------ */
+/* a non-commutative operator: composition of affine maps mod 2^32     */
+/* ------------------------------------------------------------------ */
+
+/*
+ * oracle_affine_scan: the scan of Section 1 with (+) the composition of
+ * affine maps x -> a*x + b over 32-bit unsigned integers (mod 2^32), the
+ * earlier map applied first:
+ *     (a1, b1) (+) (a2, b2) = (a2 * a1, a2 * b1 + b2),   e = (1, 0).
+ * Maps are stored as interleaved pairs ab[2j] = a_j, ab[2j + 1] = b_j; the
+ * output holds the composed prefixes in the same layout.  Its b half is the
+ * linear recurrence h_j = a_j * h_{j-1} + b_j with h_{-1} = 0.  One left fold.
+ */
+int oracle_affine_scan(const uint32_t *ab, uint32_t *out, int64_t n,
+                       int exclusive)
+{
+    if (n < 0)
+        return OR_BAD_ARG;
+    uint32_t pa = 1u, pb = 0u; /* the identity map */
+    for (int64_t j = 0; j < n; ++j) {
+        const uint32_t a = ab[2 * j], b = ab[2 * j + 1];
+        if (exclusive) {
+            out[2 * j] = pa;
+            out[2 * j + 1] = pb;
+        }
+        pb = a * pb + b; /* apply the prefix, then map j */
+        pa = a * pa;
+        if (!exclusive) {
+            out[2 * j] = pa;
+            out[2 * j + 1] = pb;
+        }
+    }
+    return OR_OK;
+}
+
+/* ------------------------------------------------------------------ */
 /* breadth-first search levels (device-level messaging between blocks) */
 /* ------------------------------------------------------------------ */
 

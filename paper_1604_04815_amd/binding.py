@@ -99,6 +99,7 @@ SIGNATURES = {
     "lscan_compact": ([_vp, _vp, _vp, _vp, _i64, _i32, _vp], _i32),
     "lscan_radix_offsets": ([_vp, _i64, _i32, _i32, _i32, _i64, _vp, _vp], _i32),
     "lscan_compact_with_params": ([_vp, _vp, _vp, _vp, _i64, _i32, ctypes.POINTER(Params), _vp], _i32),
+    "lscan_scan_custom": ([_vp, _vp, _vp, _i64, _u32, ctypes.POINTER(Params), _vp], _i32),
     "lscan_bfs": ([_vp, _vp, _i64, _i64, _i32, _vp, _vp, _vp, _vp], _i32),
     "lscan_bfs_with_params": ([_vp, _vp, _i64, _i64, _i32, _vp, _vp, _vp, ctypes.POINTER(Params), _vp], _i32),
     "lscan_graph_create_segmented": ([_vp, _vp, _i64, _vp, _i64, _i32, _i32, _u32, ctypes.POINTER(Params),
@@ -457,6 +458,47 @@ def radix_offsets(keys, shift, bits, block_items, out=None, stream=None):
                                       out.data_ptr(), _stream(stream)), "lscan_radix_offsets")
     return out.view(1 << bits, m)
 
+
+def scan_custom(kernel, x, n, out=None, exclusive=False, stream=None, params: Params | None = None):
+    """Scan n elements of a user operator's In type held in the device
+    tensor ``x`` with the kernel handle ``kernel`` (made in the user's own
+    library with include/lscan_custom.hpp); ``out`` (default: a tensor like
+    ``x``) receives n elements of its Out type.  Returns ``out``."""
+    import torch
+
+    _flat(x, "x")
+    if out is None:
+        out = torch.empty_like(x)
+    else:
+        _flat(out, "out")
+    flags = F_EXCLUSIVE if exclusive else 0
+    p = ctypes.byref(params) if params is not None else None
+    _check(load().lscan_scan_custom(ctypes.c_void_p(kernel), x.data_ptr(), out.data_ptr(), int(n), flags, p,
+                                    _stream(stream)), "lscan_scan_custom")
+    return out
+
+
+# The example library of a user operator (composition of affine maps mod
+# 2^32), built beside the package by the build step.
+AFFINE_EXAMPLE_LIB = os.path.join(os.path.dirname(os.path.abspath(__file__)), "custom", "libaffine_scan.so")
+
+
+def affine_example_kernels(path: str | None = None) -> dict:
+    """Handles of the example affine-map scan kernels: 'default' (256 x 8),
+    'small' (64 x 1) and 'wide' (1024 x 2)."""
+    p = path or AFFINE_EXAMPLE_LIB
+    if not os.path.exists(p):
+        raise RuntimeError(f"{p} is not built: run __graft_entry__.build()")
+    lib = ctypes.CDLL(p)
+    out = {}
+    for name, sym in (("default", "lscan_affine_kernel"), ("small", "lscan_affine_kernel_small"),
+                      ("wide", "lscan_affine_kernel_wide")):
+        f = getattr(lib, sym)
+        f.argtypes = []
+        f.restype = ctypes.c_void_p
+        out[name] = f()
+    out["_lib"] = lib  # keeps the code object loaded
+    return out
 
 def bfs(row_offsets, cols, source, levels=None, parents=True, stats=None, stream=None,
         params: Params | None = None):

@@ -18,6 +18,10 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "liblscan.so")
+# A user-operator scan built, as a user would, from include/lscan_custom.hpp
+# into a library of its own (run through lscan_scan_custom).
+CUSTOM_SRC = os.path.join(PKG, "custom", "affine_scan.hip")
+CUSTOM_LIB = os.path.join(PKG, "custom", "libaffine_scan.so")
 INCLUDE = os.path.join(ROOT, "include")
 
 ARCH = "gfx950"
@@ -50,21 +54,27 @@ def sources() -> list[str]:
     return sorted(glob.glob(os.path.join(CSRC, "*.hip"))) + sorted(glob.glob(os.path.join(CSRC, "*.cpp")))
 
 
-def build(jobs: int | None = None, verbose: bool = False) -> str:
-    """Compile every unit and link the shared library; returns its path."""
-    os.makedirs(BUILD, exist_ok=True)
-    srcs = sources()
-    jobs = jobs or min(16, os.cpu_count() or 4, len(srcs))
-    with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
-        objs = list(ex.map(_compile, srcs))
-    tmp = LIB + ".tmp"
+def _link(objs: list[str], out: str) -> None:
+    tmp = out + ".tmp"
     r = subprocess.run([HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp, *objs],
                        capture_output=True, text=True)
     if r.returncode != 0:
-        raise RuntimeError(f"link failed:\n{r.stderr}")
-    os.replace(tmp, LIB)
+        raise RuntimeError(f"link failed for {out}:\n{r.stderr}")
+    os.replace(tmp, out)
+
+
+def build(jobs: int | None = None, verbose: bool = False) -> str:
+    """Compile every unit and link the shared library (and the user-operator
+    example library); returns the main library's path."""
+    os.makedirs(BUILD, exist_ok=True)
+    srcs = sources()
+    jobs = jobs or min(16, os.cpu_count() or 4, len(srcs) + 1)
+    with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
+        objs = list(ex.map(_compile, srcs + [CUSTOM_SRC]))
+    _link(objs[:-1], LIB)
+    _link(objs[-1:], CUSTOM_LIB)
     if verbose:
-        print(f"built {LIB} from {len(srcs)} units", flush=True)
+        print(f"built {LIB} from {len(srcs)} units and {CUSTOM_LIB}", flush=True)
     return LIB
 
 

@@ -58,6 +58,9 @@ constexpr double kSpinLimitSeconds = 2.0;
 
 // A co-residency test waits this long for the whole grid to arrive.
 constexpr double kResidencyWaitSeconds = 0.02;
+// Workgroups per CU a kernel built for a user operator asks for by default
+// (the co-residency test may lower it).
+constexpr int kCustomGroupsPerCu = 2;
 
 // Tags are 32-bit and 0 marks a never-written slot: reset a workspace well
 // before its tag counter could wrap.
@@ -76,6 +79,14 @@ struct DeviceInfo {
     int bfs_occupancy = -1;
     int bfs_resident_ok = 0;
     int bfs_resident_fail = 0;
+    // kernels built for user operators, by entry: occupancy, groups proven
+    // resident, smallest failing count
+    struct Custom {
+        int occupancy = -1;
+        int ok = 0;
+        int fail = 0;
+    };
+    std::map<const void*, Custom> custom;
 };
 
 // Flag slots, control words and (batched launches) array descriptors of one
@@ -250,6 +261,7 @@ struct Request {
     uint32_t* status_host = nullptr;     // optional host-visible timeout word
     const uint8_t* keep = nullptr;       // compaction: keep flags (may be null)
     int64_t* count = nullptr;            // compaction: device count of kept items
+    const KernelEntry* custom = nullptr; // a plain scan kernel built for a user operator
 };
 
 lscan_status make_request(int mode, const void* x, void* y, int64_t n, const int64_t* offsets, int64_t num_segments,
@@ -538,18 +550,19 @@ lscan_status plan_locked(const Request& r, int dev, Workspace* ws_fixed, hipStre
                          Workspace** ws_used)
 {
     init_params_locked();
-    Params prm = g_params[r.mode][r.oc];
-    if (r.p && (r.p->block_threads != 0 || r.p->vectors_per_lane != 0))
+    Params prm = r.custom ? Params{0, kCustomGroupsPerCu, LSCAN_HANDOFF_WINDOW} : g_params[r.mode][r.oc];
+    if (!r.custom && r.p && (r.p->block_threads != 0 || r.p->vectors_per_lane != 0))
         prm.shape = shape_index(r.p->block_threads, r.p->vectors_per_lane);
     if (r.p && r.p->groups_per_cu > 0) prm.groups_per_cu = r.p->groups_per_cu;
     if (r.p) prm.handoff = r.p->handoff;
-    const KernelEntry& k = table()[r.mode][r.oc][prm.shape];
+    const KernelEntry& k = r.custom ? *r.custom : table()[r.mode][r.oc][prm.shape];
     if (!k.func) return LSCAN_ERR_UNSUPPORTED;  // no kernel of this kind for the operator
 
     DeviceInfo* info = nullptr;
     lscan_status st = device_info_locked(dev, &info);
     if (st != LSCAN_OK) return st;
-    int& occ = info->occupancy[r.mode][r.oc][prm.shape];
+    DeviceInfo::Custom* cu = r.custom ? &info->custom[k.func] : nullptr;
+    int& occ = cu ? cu->occupancy : info->occupancy[r.mode][r.oc][prm.shape];
     if (occ < 0) {
         int v = 0;
         hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, k.func, k.block_threads, 0);
@@ -582,7 +595,10 @@ lscan_status plan_locked(const Request& r, int dev, Workspace* ws_fixed, hipStre
     const int64_t need = (M + info->cu_count - 1) / info->cu_count;
     if (need < want) want = int(need);
     int groups = 0;
-    st = resident_groups_locked(info, r.mode, r.oc, prm.shape, k, want, ws, stream, &groups);
+    if (cu)
+        st = resident_groups_core(info, k, want, ws, stream, cu->ok, cu->fail, &groups);
+    else
+        st = resident_groups_locked(info, r.mode, r.oc, prm.shape, k, want, ws, stream, &groups);
     if (st != LSCAN_OK) return st;
     const int64_t B = std::max<int64_t>(1, std::min<int64_t>(M, int64_t(groups) * info->cu_count));
 
@@ -1304,6 +1320,42 @@ lscan_status lscan_bfs(const int64_t* row_offsets, const int32_t* cols, int64_t 
 {
     return lscan_bfs_with_params(row_offsets, cols, num_vertices, num_edges, source, levels, parents, stats,
                                  nullptr, stream);
+}
+
+lscan_status lscan_scan_custom(const lscan_custom_kernel* kernel, const void* x, void* y, int64_t n,
+                               uint32_t flags, const lscan_params* p, void* stream)
+{
+    const KernelEntry* k = reinterpret_cast<const KernelEntry*>(kernel);
+    if (!k || !k->func || !k->launch) return LSCAN_ERR_INVALID_ARG;
+    if (k->block_threads < 64 || k->block_threads > 1024 || k->block_threads % 64 != 0 || k->vectors_per_lane < 1 ||
+        k->elems_per_vec < 1 || k->in_bytes < 1 || k->out_bytes < 1 || k->slot_words < 1 ||
+        k->tile_elems != int64_t(k->block_threads) * k->vectors_per_lane * k->elems_per_vec)
+        return LSCAN_ERR_INVALID_ARG;  // not an entry made by lscan_custom.hpp
+    if (flags & ~(LSCAN_F_EXCLUSIVE | LSCAN_F_DETERMINISTIC)) return LSCAN_ERR_INVALID_ARG;
+    lscan_status st = check_params(p);
+    if (st != LSCAN_OK) return st;
+    if (p && (p->block_threads != 0 || p->vectors_per_lane != 0)) return LSCAN_ERR_UNSUPPORTED;  // fixed by the kernel
+    if (n < 0) return LSCAN_ERR_INVALID_ARG;
+    if (n > 0) {
+        if (!x || !y) return LSCAN_ERR_INVALID_ARG;
+        const uintptr_t ax = uintptr_t(std::min(k->in_bytes, 16)), ay = uintptr_t(std::min(k->out_bytes, 16));
+        if (reinterpret_cast<uintptr_t>(x) % ax || reinterpret_cast<uintptr_t>(y) % ay) return LSCAN_ERR_INVALID_ARG;
+        if (x == y) {
+            if (k->in_bytes != k->out_bytes) return LSCAN_ERR_INVALID_ARG;
+        } else if (ranges_overlap(x, n * k->in_bytes, y, n * k->out_bytes)) {
+            return LSCAN_ERR_INVALID_ARG;
+        }
+    }
+    Request r;
+    r.mode = kModePlain;
+    r.custom = k;
+    r.x = x;
+    r.y = y;
+    r.n = n;
+    r.exclusive = (flags & LSCAN_F_EXCLUSIVE) != 0;
+    r.p = p;
+    r.empty = (n == 0);
+    return run(r, stream);
 }
 
 lscan_status lscan_last_launch(lscan_launch_info* out)

@@ -401,6 +401,45 @@ def check_argscan(orc, seed=23):
     assert np.array_equal(idx[:300], first)
 
 
+def check_affine(orc, seed=29):
+    """Composition of affine maps mod 2^32: the special cases that reduce to
+    numpy's running sum and product, the linear recurrence evaluated by brute
+    force with Python integers (which pins the order of composition: the
+    operator is not commutative), and the exclusive shift."""
+    g = np.random.default_rng(seed)
+    M = 1 << 32
+    n = 3000
+    # a = 1: x -> x + b, the prefixes are running sums of b
+    ab = np.stack([np.ones(n, np.uint32), g.integers(0, M, n, dtype=np.uint64).astype(np.uint32)], 1)
+    out = orc.affine_scan(ab)
+    assert np.all(out[:, 0] == 1)
+    assert np.array_equal(out[:, 1], np.cumsum(ab[:, 1].astype(np.uint64)).astype(np.uint32))
+    # b = 0: x -> a * x, the prefixes are running products of a
+    ab = np.stack([g.integers(0, M, n, dtype=np.uint64).astype(np.uint32), np.zeros(n, np.uint32)], 1)
+    out = orc.affine_scan(ab)
+    assert np.all(out[:, 1] == 0)
+    prod, want = 1, []
+    for a in ab[:, 0].tolist():
+        prod = (prod * a) % M
+        want.append(prod)
+    assert out[:, 0].tolist() == want
+    # general maps: prefix j applied to x equals the recurrence run from x
+    n = 60
+    ab = g.integers(0, M, (n, 2), dtype=np.uint64).astype(np.uint32)
+    ab[::7, 0] = 0              # maps that forget their argument
+    ab[3::11, 0] = 0xFFFFFFFF   # -1 mod 2^32
+    out = orc.affine_scan(ab)
+    excl = orc.affine_scan(ab, exclusive=True)
+    for x0 in (0, 1, 12345, M - 1):
+        h = x0
+        for j in range(n):
+            h = (int(ab[j, 0]) * h + int(ab[j, 1])) % M
+            assert (int(out[j, 0]) * x0 + int(out[j, 1])) % M == h, (x0, j)
+    assert excl[0].tolist() == [1, 0]
+    assert np.array_equal(excl[1:], out[:-1])
+    assert orc.affine_scan(np.zeros((0, 2), np.uint32)).shape == (0, 2)
+
+
 def _csr(n, edges):
     edges = sorted(edges)
     row_ptr = np.zeros(n + 1, np.int64)
@@ -447,7 +486,7 @@ def check_bfs(orc, seed=29):
 
 ALL_CHECKS = (check_golden, check_closed_forms, check_brute_force, check_invariants,
               check_cancellation, check_segmented, check_compact, check_radix_offsets, check_argscan,
-              check_bfs)
+              check_affine, check_bfs)
 
 
 def failing_checks(orc):

@@ -308,3 +308,25 @@ def test_bfs_validation(lib):
                       (binding.Params(0, 0, -1, 0), binding.ERR_INVALID_ARG),
                       (binding.Params(0, 0, 0, 7), binding.ERR_INVALID_ARG)):
         assert g(row, col, 100, 400, 0, lev, par, st, ctypes.byref(p), None) == status, p
+
+
+def test_custom_scan_validation(lib):
+    kernels = binding.affine_example_kernels()
+    k = kernels["default"]
+    f = lib.lscan_scan_custom
+    assert f(None, FAKE_X, FAKE_Y, 8, 0, None, None) == binding.ERR_INVALID_ARG
+    bogus = (ctypes.c_char * 256)()       # not an entry made by lscan_custom.hpp
+    assert f(ctypes.addressof(bogus), FAKE_X, FAKE_Y, 8, 0, None, None) == binding.ERR_INVALID_ARG
+    assert f(k, FAKE_X, FAKE_Y, -1, 0, None, None) == binding.ERR_INVALID_ARG
+    assert f(k, FAKE_X, FAKE_Y, 8, binding.F_COMPENSATED, None, None) == binding.ERR_INVALID_ARG
+    assert f(k, None, FAKE_Y, 8, 0, None, None) == binding.ERR_INVALID_ARG
+    assert f(k, FAKE_X + 4, FAKE_Y, 8, 0, None, None) == binding.ERR_INVALID_ARG   # 8-byte elements
+    assert f(k, FAKE_X, FAKE_Y + 4, 8, 0, None, None) == binding.ERR_INVALID_ARG
+    assert f(k, FAKE_X, FAKE_X + 8, 8, 0, None, None) == binding.ERR_INVALID_ARG   # partial overlap
+    p = binding.Params(256, 8, 0, 0)
+    assert f(k, FAKE_X, FAKE_Y, 8, 0, ctypes.byref(p), None) == binding.ERR_UNSUPPORTED
+    p = binding.Params(0, 0, -1, 0)
+    assert f(k, FAKE_X, FAKE_Y, 8, 0, ctypes.byref(p), None) == binding.ERR_INVALID_ARG
+    assert f(k, None, None, 0, 0, None, None) == binding.OK                        # nothing to do
+    # the three example shapes are distinct kernels
+    assert len({kernels["default"], kernels["small"], kernels["wide"]}) == 3

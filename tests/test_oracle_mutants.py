@@ -46,6 +46,9 @@ MUTANTS = [
     ("argscan_i64_inverted", "better = want_max ? (v > b) : (v < b);\n        } else {", "better = want_max ? (v < b) : (v > b);\n        } else {", 0),
     ("argscan_float_zero_order", "better = want_max ? total_less(b, v) : total_less(v, b);", "better = want_max ? (v > b) : (v < b);", 0),
     ("argscan_excl_after", "if (exclusive) y[j] = best;\n        int better;", "int better;", 0),
+    ("affine_swapped_composition", "pb = a * pb + b; /* apply the prefix, then map j */", "pb = pa * b + pb;", 0),
+    ("affine_identity_zero", "uint32_t pa = 1u, pb = 0u; /* the identity map */", "uint32_t pa = 0u, pb = 0u;", 0),
+    ("affine_dropped_offset", "pb = a * pb + b; /* apply the prefix, then map j */", "pb = a * pb;", 0),
     ("bfs_level_not_incremented", "level[v] = level[u] + 1;", "level[v] = level[u];", 0),
     ("bfs_stack_order", "int32_t u = queue[head++];", "int32_t u = queue[--tail];", 0),
     ("bfs_source_level_one", "level[src] = 0;", "level[src] = 1;", 0),

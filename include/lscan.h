@@ -492,6 +492,20 @@ lscan_status lscan_wait(lscan_server *s, uint64_t ticket, lscan_result *out);
 lscan_status lscan_server_get_stats(lscan_server *s, lscan_server_stats *out);
 lscan_status lscan_server_destroy(lscan_server *s);
 
+/*
+ * Watchdog of every wait between workgroups (scan prefixes, compaction
+ * counts, search offsets and level barriers): a wait that lasts longer than
+ * `us` microseconds of the device's constant clock gives up, the grid stops
+ * (each waiter sees the abort word) and the next lscan_check on the stream
+ * reports LSCAN_ERR_TIMEOUT; the outputs of that launch are undefined.
+ * Applies to launches made after the call, on every device (a captured
+ * graph keeps the value it was captured with).  Default 2,000,000 (2 s).
+ * 0 gives up at the first wait not already satisfied -- a way to exercise
+ * the timeout path.  us outside [0, 3.6e9]: LSCAN_ERR_INVALID_ARG.
+ */
+lscan_status lscan_set_watchdog_us(int64_t us);
+int64_t lscan_get_watchdog_us(void);
+
 /* Shape of the last launch made by the calling thread. */
 typedef struct {
     int64_t n;             /* elements */

@@ -116,6 +116,8 @@ SIGNATURES = {
     "lscan_wait": ([_vp, ctypes.c_uint64, ctypes.POINTER(Result)], _i32),
     "lscan_server_get_stats": ([_vp, ctypes.POINTER(ServerStats)], _i32),
     "lscan_server_destroy": ([_vp], _i32),
+    "lscan_set_watchdog_us": ([_i64], _i32),
+    "lscan_get_watchdog_us": ([], _i64),
     "lscan_last_launch": ([ctypes.POINTER(LaunchInfo)], _i32),
     "lscan_check": ([_vp], _i32),
     "lscan_release_workspaces": ([], _i32),

@@ -56,6 +56,9 @@ thread_local lscan_launch_info t_last_launch = {};
 // the grid is not making progress (e.g. not all workgroups are resident).
 constexpr double kSpinLimitSeconds = 2.0;
 
+// The watchdog of the launches made from now on (lscan_set_watchdog_us).
+int64_t g_watchdog_us = int64_t(kSpinLimitSeconds * 1e6);
+
 // A co-residency test waits this long for the whole grid to arrive.
 constexpr double kResidencyWaitSeconds = 0.02;
 // Workgroups per CU a kernel built for a user operator asks for by default
@@ -70,6 +73,7 @@ struct DeviceInfo {
     int cu_count = 0;
     uint64_t spin_limit = 0;
     uint64_t residency_limit = 0;
+    uint64_t wall_khz = 0;
     int occupancy[kNumModes][kNumOpCodes][kNumShapes];
     // groups per CU proven resident together (0: none yet) and the smallest
     // count that failed the test (0: none failed)
@@ -367,7 +371,8 @@ lscan_status device_info_locked(int dev, DeviceInfo** out)
         int wall_khz = 0;
         e = hipDeviceGetAttribute(&wall_khz, hipDeviceAttributeWallClockRate, dev);
         if (e != hipSuccess || wall_khz <= 0) wall_khz = 100000;  // 100 MHz constant clock
-        info.spin_limit = uint64_t(double(wall_khz) * 1000.0 * kSpinLimitSeconds);
+        info.wall_khz = uint64_t(wall_khz);
+        info.spin_limit = uint64_t(double(wall_khz) * double(g_watchdog_us) / 1000.0);
         info.residency_limit = uint64_t(double(wall_khz) * 1000.0 * kResidencyWaitSeconds);
         for (int s = 0; s < kNumModes; ++s)
             for (int o = 0; o < kNumOpCodes; ++o)
@@ -1356,6 +1361,21 @@ lscan_status lscan_scan_custom(const lscan_custom_kernel* kernel, const void* x,
     r.p = p;
     r.empty = (n == 0);
     return run(r, stream);
+}
+
+lscan_status lscan_set_watchdog_us(int64_t us)
+{
+    if (us < 0 || us > int64_t(3600) * 1000000) return LSCAN_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lock(g_mu);
+    g_watchdog_us = us;
+    for (auto& kv : g_dev) kv.second.spin_limit = uint64_t(double(kv.second.wall_khz) * double(us) / 1000.0);
+    return LSCAN_OK;
+}
+
+int64_t lscan_get_watchdog_us(void)
+{
+    std::lock_guard<std::mutex> lock(g_mu);
+    return g_watchdog_us;
 }
 
 lscan_status lscan_last_launch(lscan_launch_info* out)

@@ -330,3 +330,14 @@ def test_custom_scan_validation(lib):
     assert f(k, None, None, 0, 0, None, None) == binding.OK                        # nothing to do
     # the three example shapes are distinct kernels
     assert len({kernels["default"], kernels["small"], kernels["wide"]}) == 3
+
+
+def test_watchdog_setter(lib):
+    default = lib.lscan_get_watchdog_us()
+    assert default == 2_000_000
+    assert lib.lscan_set_watchdog_us(-5) == binding.ERR_INVALID_ARG
+    assert lib.lscan_set_watchdog_us(3_600_000_001) == binding.ERR_INVALID_ARG
+    assert lib.lscan_set_watchdog_us(1234) == binding.OK
+    assert lib.lscan_get_watchdog_us() == 1234
+    assert lib.lscan_set_watchdog_us(default) == binding.OK
+    assert lib.lscan_get_watchdog_us() == default

@@ -68,11 +68,14 @@ enum OpCode : int {
     kF32Add, kF32AddComp, kF32Max, kF32Min,
     kBF16Add, kBF16AddComp, kBF16Max, kBF16Min,
     kI32ArgMax, kI32ArgMin, kI64ArgMax, kI64ArgMin, kF32ArgMax, kF32ArgMin,  // plain scans only
+    // the same with a 32-bit index, for arrays of fewer than 2^31 elements
+    kI32ArgMaxS, kI32ArgMinS, kI64ArgMaxS, kI64ArgMinS, kF32ArgMaxS, kF32ArgMinS,
     kNumOpCodes
 };
 
 // Compiled tile shapes (T, vectors per lane).
 constexpr int kNumShapes = 10;
+constexpr int kArgShortOffset = 6;  // kI32ArgMaxS - kI32ArgMax
 constexpr int kShapeThreads[kNumShapes] = {256, 512, 512, 256, 1024, 1024, 512, 256, 256, 1024};
 constexpr int kShapeVectors[kNumShapes] = {8, 8, 4, 16, 4, 2, 2, 4, 2, 1};
 
@@ -93,5 +96,6 @@ void register_f32_batch_kernels(KernelTable& t);
 void register_bf16_batch_kernels(KernelTable& t);
 void register_compact_kernels(KernelTable& t);
 void register_arg_kernels(KernelTable& t);
+void register_arg_short_kernels(KernelTable& t);
 
 }  // namespace lscan

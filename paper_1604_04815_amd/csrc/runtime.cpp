@@ -41,6 +41,7 @@ void init_table()
     register_bf16_batch_kernels(g_table);
     register_compact_kernels(g_table);
     register_arg_kernels(g_table);
+    register_arg_short_kernels(g_table);
 }
 
 const KernelTable& table()
@@ -171,8 +172,11 @@ void init_params_locked()
     g_params[kModePlain][kBF16AddComp] = t1024x4;
     g_params[kModePlain][kBF16Max] = t256x16g2;
     g_params[kModePlain][kBF16Min] = t256x16g2;
-    const Params t1024x2{5, 1};
+    const Params t1024x2{5, 1}, t256x8g2{0, 2};
     for (int o = kI32ArgMax; o <= kF32ArgMin; ++o) g_params[kModePlain][o] = t1024x2;
+    for (int o = kI32ArgMaxS; o <= kF32ArgMinS; ++o) g_params[kModePlain][o] = t256x8g2;
+    g_params[kModePlain][kI64ArgMaxS] = t1024x4;
+    g_params[kModePlain][kI64ArgMinS] = t1024x4;
     for (int o = 0; o < kNumOpCodes; ++o) {
         g_params[kModeSegmented][o] = t512x8;
         g_params[kModeBatched][o] = g_params[kModePlain][o];
@@ -281,7 +285,8 @@ lscan_status make_request(int mode, const void* x, void* y, int64_t n, const int
     lscan_status st = check_params(p);
     if (st != LSCAN_OK) return st;
     r->mode = mode;
-    r->oc = oc;
+    // running argmax / argmin of fewer than 2^31 elements: the 32-bit index kernels
+    r->oc = (is_arg_op(op) && n <= int64_t(INT32_MAX)) ? oc + kArgShortOffset : oc;
     r->exclusive = exclusive;
     r->p = p;
     if (mode == kModeBatched) {
@@ -1198,7 +1203,8 @@ lscan_status lscan_get_params(lscan_dtype dt, lscan_op op, uint32_t flags, int32
     if (oc == -2) return LSCAN_ERR_UNSUPPORTED;
     std::lock_guard<std::mutex> lock(g_mu);
     init_params_locked();
-    const Params& p = g_params[kind][oc];
+    // running argmax / argmin: the 32-bit index row (what arrays below 2^31 elements use)
+    const Params& p = g_params[kind][is_arg_op(op) && kind != kModeCompact ? oc + kArgShortOffset : oc];
     out->block_threads = kShapeThreads[p.shape];
     out->vectors_per_lane = kShapeVectors[p.shape];
     out->groups_per_cu = p.groups_per_cu;
@@ -1220,6 +1226,7 @@ lscan_status lscan_set_params(lscan_dtype dt, lscan_op op, uint32_t flags, int32
     std::lock_guard<std::mutex> lock(g_mu);
     init_params_locked();
     g_params[kind][oc] = Params{s, p->groups_per_cu, p->handoff};
+    if (is_arg_op(op) && kind != kModeCompact) g_params[kind][oc + kArgShortOffset] = g_params[kind][oc];  // both index widths
     return LSCAN_OK;
 }
 

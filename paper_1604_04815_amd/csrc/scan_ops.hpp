@@ -285,6 +285,70 @@ using ArgMinI64 = ArgOp<int64_t, int64_t, false, false>;
 using ArgMaxF32 = ArgOp<uint32_t, int32_t, true, true>;
 using ArgMinF32 = ArgOp<uint32_t, int32_t, false, true>;
 
+// Arrays of fewer than 2^31 elements carry the index in one 32-bit word: a
+// 32-bit key then makes a two-word value, a 64-bit key three words (kept
+// as two halves so the value has no padding).  idx < 0 marks the identity.
+template <class KeyT>
+struct ArgValueS;
+template <>
+struct ArgValueS<int32_t> {
+    int32_t k;
+    int32_t idx;
+    __device__ int32_t key() const { return k; }
+    __device__ void set_key(int32_t v) { k = v; }
+};
+template <>
+struct ArgValueS<int64_t> {
+    uint32_t klo, khi;
+    int32_t idx;
+    __device__ int64_t key() const { return int64_t((uint64_t(khi) << 32) | klo); }
+    __device__ void set_key(int64_t v)
+    {
+        klo = uint32_t(uint64_t(v));
+        khi = uint32_t(uint64_t(v) >> 32);
+    }
+};
+
+template <class In_, class KeyT, bool MAX, bool FLOAT_KEY>
+struct ArgOpS {
+    using In = In_; using V = ArgValueS<KeyT>; using Out = int64_t;
+    static constexpr int E = 16 / int(sizeof(In));
+    static constexpr bool kIndexed = true;
+    __device__ static V identity()
+    {
+        V v;
+        v.set_key(0);
+        v.idx = -1;
+        return v;
+    }
+    __device__ static V combine(V a, V b)
+    {
+        const KeyT ka = a.key(), kb = b.key();
+        const bool take_b = a.idx < 0 || (b.idx >= 0 && (MAX ? (kb > ka) : (kb < ka)));
+        V r;
+        r.set_key(take_b ? kb : ka);
+        r.idx = take_b ? b.idx : a.idx;
+        return r;
+    }
+    __device__ static V lift_at(In x, int64_t i)
+    {
+        V v;
+        if constexpr (FLOAT_KEY)
+            v.set_key(order_key(x));
+        else
+            v.set_key(KeyT(x));
+        v.idx = int32_t(i);
+        return v;
+    }
+    __device__ static Out lower(const V& v) { return int64_t(v.idx); }
+};
+using ArgMaxI32S = ArgOpS<int32_t, int32_t, true, false>;
+using ArgMinI32S = ArgOpS<int32_t, int32_t, false, false>;
+using ArgMaxI64S = ArgOpS<int64_t, int64_t, true, false>;
+using ArgMinI64S = ArgOpS<int64_t, int64_t, false, false>;
+using ArgMaxF32S = ArgOpS<uint32_t, int32_t, true, true>;
+using ArgMinF32S = ArgOpS<uint32_t, int32_t, false, true>;
+
 // Element lift for operators with (kIndexed) or without the element index.
 template <class Op, class = void>
 struct is_indexed_op : std::false_type {};

@@ -49,6 +49,14 @@
  * and the first switch to a second stream synchronizes the device once).
  * Graph replays and the request server's launches are not part of this
  * order: do not run them on a device at the same time as other scans.
+ *
+ * Besides the scans (plain, exclusive, segmented, batched, graph-captured,
+ * served), the same persistent machinery gives: stream compaction
+ * (lscan_compact), radix-sort digit offsets (lscan_radix_offsets),
+ * breadth-first search with workgroups handing frontier offsets to each
+ * other (lscan_bfs), and scans with a caller's own operator built from
+ * lscan_custom.hpp (lscan_scan_custom).  These take part in the same
+ * cross-stream order and honour the same watchdog (lscan_set_watchdog_us).
  */
 #ifndef LSCAN_H
 #define LSCAN_H

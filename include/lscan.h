@@ -96,6 +96,12 @@ typedef enum {
  * order, so one tile shape and grid give the same bits on every run. */
 #define LSCAN_F_DETERMINISTIC 0x2u
 #define LSCAN_F_EXCLUSIVE 0x4u   /* lscan_segmented only: exclusive scan */
+/* LSCAN_F_INDEX64: running argmax / argmin only -- run the kernels that
+ * carry a 64-bit index whatever n is.  Arrays of fewer than 2^31 elements
+ * normally take kernels with a 32-bit index (smaller values, faster), larger
+ * ones always take the 64-bit kernels; the result is the same.  With any
+ * other operator: LSCAN_ERR_INVALID_ARG. */
+#define LSCAN_F_INDEX64 0x8u
 
 typedef int32_t lscan_status;
 #define LSCAN_OK 0

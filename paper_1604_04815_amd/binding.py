@@ -22,6 +22,7 @@ ADD, MAX, MIN = 0, 1, 2
 F_COMPENSATED = 0x1
 F_DETERMINISTIC = 0x2
 F_EXCLUSIVE = 0x4
+F_INDEX64 = 0x8
 
 OK, PENDING = 0, 1
 ERR_INVALID_ARG, ERR_UNSUPPORTED, ERR_NO_MEMORY, ERR_DEVICE = -1, -2, -3, -4
@@ -342,12 +343,13 @@ def _out_for(x, out, op="add"):
     return out
 
 
-def inclusive(x, op="add", compensated=False, out=None, stream=None, params: Params | None = None):
+def inclusive(x, op="add", compensated=False, out=None, stream=None, params: Params | None = None,
+              index64=False):
     """y_j = x_0 (+) ... (+) x_j on the device; returns y (for argmax /
     argmin the int64 index of the best element of each prefix)."""
     _flat(x, "x")
     y = _out_for(x, out, op)
-    flags = F_COMPENSATED if compensated else 0
+    flags = (F_COMPENSATED if compensated else 0) | (F_INDEX64 if index64 else 0)
     if params is None:
         lscan_inclusive(x.data_ptr(), y.data_ptr(), x.shape[0], dtype_code(x), OPS[op], flags, _stream(stream))
     else:
@@ -356,11 +358,12 @@ def inclusive(x, op="add", compensated=False, out=None, stream=None, params: Par
     return y
 
 
-def exclusive(x, op="add", compensated=False, out=None, stream=None, params: Params | None = None):
+def exclusive(x, op="add", compensated=False, out=None, stream=None, params: Params | None = None,
+              index64=False):
     """y_0 = e, y_j = x_0 (+) ... (+) x_{j-1} on the device; returns y."""
     _flat(x, "x")
     y = _out_for(x, out, op)
-    flags = F_COMPENSATED if compensated else 0
+    flags = (F_COMPENSATED if compensated else 0) | (F_INDEX64 if index64 else 0)
     if params is None:
         lscan_exclusive(x.data_ptr(), y.data_ptr(), x.shape[0], dtype_code(x), OPS[op], flags, _stream(stream))
     else:

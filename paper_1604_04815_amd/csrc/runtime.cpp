@@ -276,8 +276,10 @@ lscan_status make_request(int mode, const void* x, void* y, int64_t n, const int
                           const lscan_array* arrays, int64_t num_arrays, int dt, int op, uint32_t flags,
                           bool exclusive, const lscan_params* p, Request* r)
 {
-    const uint32_t allowed = LSCAN_F_COMPENSATED | LSCAN_F_DETERMINISTIC | (mode == kModePlain ? 0u : LSCAN_F_EXCLUSIVE);
+    const uint32_t allowed = LSCAN_F_COMPENSATED | LSCAN_F_DETERMINISTIC |
+                             (mode == kModePlain ? LSCAN_F_INDEX64 : LSCAN_F_EXCLUSIVE);
     if (flags & ~allowed) return LSCAN_ERR_INVALID_ARG;
+    if ((flags & LSCAN_F_INDEX64) && !is_arg_op(op)) return LSCAN_ERR_INVALID_ARG;
     const int oc = opcode_of(dt, op, flags);
     if (oc == -1) return LSCAN_ERR_INVALID_ARG;
     if (oc == -2) return LSCAN_ERR_UNSUPPORTED;
@@ -286,7 +288,7 @@ lscan_status make_request(int mode, const void* x, void* y, int64_t n, const int
     if (st != LSCAN_OK) return st;
     r->mode = mode;
     // running argmax / argmin of fewer than 2^31 elements: the 32-bit index kernels
-    r->oc = (is_arg_op(op) && n <= int64_t(INT32_MAX)) ? oc + kArgShortOffset : oc;
+    r->oc = (is_arg_op(op) && n <= int64_t(INT32_MAX) && !(flags & LSCAN_F_INDEX64)) ? oc + kArgShortOffset : oc;
     r->exclusive = exclusive;
     r->p = p;
     if (mode == kModeBatched) {

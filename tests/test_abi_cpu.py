@@ -341,3 +341,15 @@ def test_watchdog_setter(lib):
     assert lib.lscan_get_watchdog_us() == 1234
     assert lib.lscan_set_watchdog_us(default) == binding.OK
     assert lib.lscan_get_watchdog_us() == default
+
+
+def test_index64_flag_validation(lib):
+    f = lib.lscan_inclusive
+    # only the running argmax / argmin take it
+    assert f(FAKE_X, FAKE_Y, 8, binding.I32, binding.ADD, binding.F_INDEX64, None) == binding.ERR_INVALID_ARG
+    assert f(FAKE_X, FAKE_Y, 8, binding.F32, binding.MAX, binding.F_INDEX64, None) == binding.ERR_INVALID_ARG
+    # not for segmented scans
+    assert lib.lscan_segmented(FAKE_X, FAKE_Y, 8, FAKE_X, 1, binding.I32, binding.ARGMAX, binding.F_INDEX64,
+                               None) == binding.ERR_INVALID_ARG
+    # an argmax with the flag and nothing to do is accepted
+    assert f(None, None, 0, binding.I32, binding.ARGMAX, binding.F_INDEX64, None) == binding.OK

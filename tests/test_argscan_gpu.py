@@ -23,10 +23,10 @@ def keys(dtype, n, seed, spread):
     return g.integers(-(2 ** 31), 2 ** 31, n, dtype=np.int64).astype(NP[dtype])
 
 
-def run(gpu_lib, x, dtype, op, exclusive, params=None):
+def run(gpu_lib, x, dtype, op, exclusive, params=None, index64=False):
     xd = torch.from_numpy(x).to("cuda")
     fn = gpu_lib.exclusive if exclusive else gpu_lib.inclusive
-    y = fn(xd, op, params=params)
+    y = fn(xd, op, params=params, index64=index64)
     gpu_lib.lscan_check(torch.cuda.current_stream().cuda_stream)
     assert y.dtype == torch.int64
     return y.cpu().numpy()
@@ -40,27 +40,33 @@ def check(got, x, dtype, op, exclusive, what):
                              f"got {got[bad[:4]].tolist()} want {want[bad[:4]].tolist()}")
 
 
+# both kernel families: 32-bit index (what arrays below 2^31 elements use)
+# and 64-bit index (forced with LSCAN_F_INDEX64; used by itself from 2^31 on)
+@pytest.mark.parametrize("index64", [False, True], ids=["idx32", "idx64"])
 @pytest.mark.parametrize("dtype", ["int32", "int64", "float32"])
 @pytest.mark.parametrize("op", ["argmax", "argmin"])
-def test_argscan(gpu_lib, dtype, op):
+def test_argscan(gpu_lib, dtype, op, index64):
     xd = torch.zeros(1 << 16, dtype=TORCH[dtype], device="cuda")
-    gpu_lib.inclusive(xd, op)
+    gpu_lib.inclusive(xd, op, index64=index64)
     L = int(gpu_lib.lscan_last_launch().tile_elems)
     for spread in ("ties", "wide"):
         for n in (1, 63, L - 1, L + 1, 3 * L + 5, 1_000_003):
             x = keys(dtype, n, seed=n + len(spread), spread=spread)
             for excl in (False, True):
-                check(run(gpu_lib, x, dtype, op, excl), x, dtype, op, excl, f"{dtype} {op} {spread} n={n} excl={excl}")
-    log(f"[argscan] {dtype} {op} ok (L={L})")
+                check(run(gpu_lib, x, dtype, op, excl, index64=index64), x, dtype, op, excl,
+                      f"{dtype} {op} {spread} n={n} excl={excl} index64={index64}")
+    log(f"[argscan] {dtype} {op} index64={index64} ok (L={L})")
 
 
+@pytest.mark.parametrize("index64", [False, True], ids=["idx32", "idx64"])
 @pytest.mark.parametrize("shape", range(10))
-def test_argscan_every_shape(gpu_lib, shape):
+def test_argscan_every_shape(gpu_lib, shape, index64):
     t, r = gpu_lib.lscan_tile_shapes()[shape]
-    x = keys("int32", 777_777, seed=30 + shape, spread="ties")
-    for groups in (1, 2):
-        got = run(gpu_lib, x, "int32", "argmax", False, params=gpu_lib.Params(t, r, groups, 0))
-        check(got, x, "int32", "argmax", False, f"T={t} R={r} g={groups}")
+    for dtype, op in (("int32", "argmax"), ("int64", "argmin"), ("float32", "argmax")):
+        x = keys(dtype, 777_777, seed=30 + shape, spread="ties")
+        for groups in (1, 2):
+            got = run(gpu_lib, x, dtype, op, False, params=gpu_lib.Params(t, r, groups, 0), index64=index64)
+            check(got, x, dtype, op, False, f"{dtype} {op} T={t} R={r} g={groups} index64={index64}")
 
 
 def test_argscan_full_size(gpu_lib):

@@ -45,9 +45,15 @@ struct ScanArgs {
     uint32_t* status_host;    // optional host-visible word that also receives the timeout flag
     const uint8_t* keep;      // compaction: one keep byte per item (null: keep non-zero items)
     int64_t* count;           // compaction: receives the number of kept items (device)
+    const int64_t* seg_first; // segmented: M + 1 entries, the first segment whose offset is at
+                              // or past block i's start (null: the kernel searches the offsets)
 };
 
 using LaunchFn = hipError_t (*)(const ScanArgs&, int grid, hipStream_t);
+
+// Segmented scans: fill a.seg_first (M + 1 entries) from the offsets for
+// blocks of tile_elems elements, before the scan on the same stream.
+hipError_t launch_segment_table(const ScanArgs& a, int64_t tile_elems, hipStream_t stream);
 
 struct KernelEntry {
     const void* func;         // the __global__ function (occupancy queries)

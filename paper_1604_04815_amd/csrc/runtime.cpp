@@ -106,6 +106,8 @@ struct Workspace {
     BatchArray* desc_host = nullptr;   // pinned staging copy
     hipEvent_t desc_copied = nullptr;  // recorded after each upload from desc_host
     bool desc_pending = false;
+    int64_t* seg_first = nullptr;      // segmented scans: first segment of every block
+    size_t seg_cap = 0;
 };
 
 struct Params {
@@ -159,7 +161,7 @@ void init_params_locked()
 {
     if (g_params_init) return;
     // measured on MI355X (shape x groups/CU sweep of the persistent scan)
-    const Params t512x8{1, 1}, t512x8g2{1, 2}, t1024x4{4, 1}, t256x16g2{3, 2};
+    const Params t512x8g2{1, 2}, t1024x4{4, 1}, t256x16g2{3, 2};
     g_params[kModePlain][kI32Add] = t256x16g2;
     g_params[kModePlain][kI32Max] = t512x8g2;
     g_params[kModePlain][kI32Min] = t512x8g2;
@@ -178,7 +180,7 @@ void init_params_locked()
     g_params[kModePlain][kI64ArgMaxS] = t1024x4;
     g_params[kModePlain][kI64ArgMinS] = t1024x4;
     for (int o = 0; o < kNumOpCodes; ++o) {
-        g_params[kModeSegmented][o] = t512x8;
+        g_params[kModeSegmented][o] = t1024x4;  // with the per-block segment table (measured)
         g_params[kModeBatched][o] = g_params[kModePlain][o];
         g_params[kModeCompact][o] = t1024x4;
     }
@@ -401,7 +403,33 @@ void free_workspace(Workspace& ws)
     if (ws.desc) (void)hipFree(ws.desc);
     if (ws.desc_host) (void)hipHostFree(ws.desc_host);
     if (ws.desc_copied) (void)hipEventDestroy(ws.desc_copied);
+    if (ws.seg_first) (void)hipFree(ws.seg_first);
     ws = Workspace();
+}
+
+// Make ws hold a segment table of at least `entries` entries.
+lscan_status ensure_segment_table(Workspace& ws, hipStream_t stream, size_t entries)
+{
+    if (ws.seg_cap >= entries) return LSCAN_OK;
+    if (capturing(stream)) return LSCAN_ERR_UNSUPPORTED;  // size the workspace with an eager call first
+    hipError_t e;
+    if (ws.seg_first) {
+        e = hipStreamSynchronize(stream);  // an earlier scan on this stream may still read it
+        if (e != hipSuccess) return device_error(e);
+        e = hipFree(ws.seg_first);
+        if (e != hipSuccess) return device_error(e);
+        ws.seg_first = nullptr;
+        ws.seg_cap = 0;
+    }
+    const size_t cap = std::max<size_t>(entries, std::max<size_t>(2 * ws.seg_cap, 1024));
+    e = hipMalloc(reinterpret_cast<void**>(&ws.seg_first), cap * sizeof(int64_t));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        ws.seg_first = nullptr;
+        return LSCAN_ERR_NO_MEMORY;
+    }
+    ws.seg_cap = cap;
+    return LSCAN_OK;
 }
 
 // Make ws hold at least `words` flag words and `desc_entries` descriptors.
@@ -660,6 +688,11 @@ lscan_status plan_locked(const Request& r, int dev, Workspace* ws_fixed, hipStre
         a.num_segments = r.num_segments;
         a.vec_ok = (reinterpret_cast<uintptr_t>(r.x) % uintptr_t(vec_bytes) == 0 &&
                     reinterpret_cast<uintptr_t>(r.y) % 16 == 0) ? 1 : 0;
+        if (r.mode == kModeSegmented) {  // the first segment of every block, written before the scan
+            st = ensure_segment_table(*ws, stream, size_t(M) + 1);
+            if (st != LSCAN_OK) return st;
+            a.seg_first = ws->seg_first;
+        }
     }
     a.num_blocks = M;
     a.slots = ws->slots;
@@ -750,6 +783,10 @@ lscan_status run(const Request& r, void* stream_ptr)
     Workspace* ws = nullptr;
     st = plan_locked(r, dev, nullptr, stream, &plan, &ws);
     if (st != LSCAN_OK) return st;
+    if (plan.a.seg_first) {
+        e = launch_segment_table(plan.a, plan.k->tile_elems, stream);
+        if (e != hipSuccess) return device_error(e);
+    }
     e = plan.k->launch(plan.a, plan.grid, stream);
     if (e != hipSuccess) return device_error(e);
     ws->launches++;
@@ -1041,7 +1078,8 @@ lscan_status graph_create(const Request& r, lscan_graph** out)
     if (e != hipSuccess) return fail(device_error(e));
     e = hipStreamBeginCapture(g->prep, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return fail(device_error(e));
-    e = plan.k->launch(plan.a, plan.grid, g->prep);
+    if (plan.a.seg_first) e = launch_segment_table(plan.a, plan.k->tile_elems, g->prep);  // part of every replay
+    if (e == hipSuccess) e = plan.k->launch(plan.a, plan.grid, g->prep);
     hipGraph_t graph = nullptr;
     hipError_t e2 = hipStreamEndCapture(g->prep, &graph);
     g->graph = graph;

@@ -395,26 +395,35 @@ __global__ void __launch_bounds__(T) scan_kernel(ScanArgs a)
             }
             if constexpr (MODE == kModeSegmented) {  // segment heads inside this lane's vectors
                 // Found while the data loads are in flight.  The block's range
-                // of offsets comes from two interleaved wave-uniform binary
-                // searches through the scalar cache (the offsets are read-only
-                // during the launch); a few heads are then matched against
-                // every lane's vectors, many by a per-lane search.
+                // of offsets comes from the table of first segments per block
+                // that a small kernel writes before the scan (else from two
+                // interleaved wave-uniform binary searches through the scalar
+                // cache); a few heads are then matched against every lane's
+                // vectors, many by a per-lane search.
                 const CInt64* off = (const CInt64*)(a.offsets);
                 const int64_t S = a.num_segments;
-                int64_t lo1 = 0, hi1 = S, lo2 = 0, hi2 = S;
-                while (lo1 < hi1 || lo2 < hi2) {
-                    const bool a1 = lo1 < hi1, a2 = lo2 < hi2;
-                    const int64_t m1 = a1 ? lo1 + ((hi1 - lo1) >> 1) : 0;
-                    const int64_t m2 = a2 ? lo2 + ((hi2 - lo2) >> 1) : 0;
-                    const int64_t v1 = off[m1], v2 = off[m2];
-                    if (a1) {
-                        if (v1 < tile0) lo1 = m1 + 1; else hi1 = m1;
+                int64_t s_lo, s_hi;
+                if (a.seg_first) {  // the table written just before this launch: two scalar loads
+                    const CInt64* first = (const CInt64*)(a.seg_first);
+                    s_lo = first[i];
+                    s_hi = first[i + 1];
+                } else {
+                    int64_t lo1 = 0, hi1 = S, lo2 = 0, hi2 = S;
+                    while (lo1 < hi1 || lo2 < hi2) {
+                        const bool a1 = lo1 < hi1, a2 = lo2 < hi2;
+                        const int64_t m1 = a1 ? lo1 + ((hi1 - lo1) >> 1) : 0;
+                        const int64_t m2 = a2 ? lo2 + ((hi2 - lo2) >> 1) : 0;
+                        const int64_t v1 = off[m1], v2 = off[m2];
+                        if (a1) {
+                            if (v1 < tile0) lo1 = m1 + 1; else hi1 = m1;
+                        }
+                        if (a2) {
+                            if (v2 < tile0 + L) lo2 = m2 + 1; else hi2 = m2;
+                        }
                     }
-                    if (a2) {
-                        if (v2 < tile0 + L) lo2 = m2 + 1; else hi2 = m2;
-                    }
+                    s_lo = lo1;
+                    s_hi = lo2;
                 }
-                const int64_t s_lo = lo1, s_hi = lo2;
                 if (s_hi - s_lo <= kFewHeads) {
                     for (int64_t k = s_lo; k < s_hi; ++k) {
                         const int64_t rel = off[k] - lane0;

@@ -234,7 +234,11 @@ lscan_status lscan_tile_shape(int32_t idx, lscan_params *out);
 #define LSCAN_KIND_COMPACT 3
 
 /* Default parameters for (dt, op, flags & LSCAN_F_COMPENSATED) and a kernel
- * kind; set replaces them (e.g. from an autotuner). */
+ * kind; set replaces them (e.g. from an autotuner).  The defaults are those
+ * of large arrays: while an operator's parameters are the library's own,
+ * plain add / max / min scans of at most 32 MiB of input run smaller tiles of
+ * 1024- or 512-thread workgroups (they finish sooner when the array cannot
+ * fill the device); other parameters, once set, apply to every size. */
 lscan_status lscan_get_params(lscan_dtype dt, lscan_op op, uint32_t flags,
                               int32_t kind, lscan_params *out);
 lscan_status lscan_set_params(lscan_dtype dt, lscan_op op, uint32_t flags,

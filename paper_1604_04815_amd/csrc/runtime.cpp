@@ -138,7 +138,21 @@ struct DeviceOrder {
 };
 std::map<int, DeviceOrder> g_order;
 Params g_params[kNumModes][kNumOpCodes];
+Params g_default_params[kNumModes][kNumOpCodes];  // the library's own, before any lscan_set_params
 bool g_params_init = false;
+
+// Plain scans of small arrays: the large-array tiles leave most of the
+// device idle, and 1024-thread workgroups with fewer vectors per lane
+// finish sooner (MI355X, int32 add, device time per launch: 2^16 6.7 against
+// 8.3 us, 2^18 7.2 / 8.4, 2^20 8.3 / 9.1, 2^22 11.4 / 12.5).  Shape index
+// for an input of `bytes`, or -1 for the large-array default.
+int small_array_shape(int64_t bytes)
+{
+    if (bytes <= (int64_t(512) << 10)) return 6;  // 512 x 2
+    if (bytes <= (int64_t(2) << 20)) return 5;    // 1024 x 2
+    if (bytes <= (int64_t(32) << 20)) return 4;   // 1024 x 4
+    return -1;
+}
 
 lscan_status device_error(hipError_t e)
 {
@@ -184,6 +198,8 @@ void init_params_locked()
         g_params[kModeBatched][o] = g_params[kModePlain][o];
         g_params[kModeCompact][o] = t1024x4;
     }
+    for (int m = 0; m < kNumModes; ++m)
+        for (int o = 0; o < kNumOpCodes; ++o) g_default_params[m][o] = g_params[m][o];
     g_params_init = true;
 }
 
@@ -591,6 +607,16 @@ lscan_status plan_locked(const Request& r, int dev, Workspace* ws_fixed, hipStre
 {
     init_params_locked();
     Params prm = r.custom ? Params{0, kCustomGroupsPerCu, LSCAN_HANDOFF_WINDOW} : g_params[r.mode][r.oc];
+    const Params& dflt = g_default_params[r.mode][r.oc];
+    const bool library_default = prm.shape == dflt.shape && prm.groups_per_cu == dflt.groups_per_cu &&
+                                 prm.handoff == dflt.handoff;
+    if (!r.custom && r.mode == kModePlain && r.oc < kI32ArgMax && library_default) {
+        const int s = small_array_shape(r.n * int64_t(table()[r.mode][r.oc][prm.shape].in_bytes));
+        if (s >= 0) {
+            prm.shape = s;
+            prm.groups_per_cu = 2;
+        }
+    }
     if (!r.custom && r.p && (r.p->block_threads != 0 || r.p->vectors_per_lane != 0))
         prm.shape = shape_index(r.p->block_threads, r.p->vectors_per_lane);
     if (r.p && r.p->groups_per_cu > 0) prm.groups_per_cu = r.p->groups_per_cu;

@@ -18,16 +18,19 @@ CASES = [
 
 
 def sizes_for(gpu_lib, dtype, op, comp):
-    """Edge sizes around the tile length L and the grid span B*L of the default launch."""
-    import ctypes
-    x = torch.zeros(1 << 16, dtype={"int32": torch.int32, "int64": torch.int64, "float32": torch.float32,
+    """Edge sizes around the tile length L and the grid span B*L of the
+    large-array launch (arrays of at most 32 MiB take smaller tiles, so the
+    small sizes below run those)."""
+    x = torch.zeros(1 << 26, dtype={"int32": torch.int32, "int64": torch.int64, "float32": torch.float32,
                                     "bfloat16": torch.bfloat16}[dtype], device="cuda")
     fn = gpu_lib.inclusive
     fn(x, op, comp)
     info = gpu_lib.lscan_last_launch()
     L = int(info.tile_elems)
+    tdtype = x.dtype
+    del x
     # grid of a launch with many blocks
-    big = torch.zeros(L * 2048, dtype=x.dtype, device="cuda")
+    big = torch.zeros(L * 2048, dtype=tdtype, device="cuda")
     fn(big, op, comp)
     B = int(gpu_lib.lscan_last_launch().grid)
     del big
@@ -202,3 +205,19 @@ def test_scans_alternating_on_two_streams_without_sync(gpu_lib):
         gpu_lib.lscan_check(s.cuda_stream)
     for y in ys:
         assert torch.equal(y, want)
+
+
+def test_small_arrays_take_small_tiles(gpu_lib):
+    # plain add / max / min of at most 32 MiB run 512 x 2, 1024 x 2 or 1024 x 4;
+    # larger arrays the large-array default; both exact
+    for n, want_t in ((1 << 16, 512), (1 << 19, 1024), (1 << 23, 1024), (1 << 24, None)):
+        x = make_input("int32", "add", n, seed=n)
+        y = gpu_lib.inclusive(to_device(x, "int32"), "add")
+        gpu_lib.lscan_check(torch.cuda.current_stream().cuda_stream)
+        info = gpu_lib.lscan_last_launch()
+        if want_t is not None:
+            assert info.block_threads == want_t, (n, info.block_threads)
+        else:
+            d = gpu_lib.lscan_get_params(gpu_lib.I32, gpu_lib.ADD)
+            assert info.block_threads == d.block_threads, (n, info.block_threads)
+        compare(to_host(y), x, "int32", "add", False, what=f"small-array shapes n={n}")

@@ -331,7 +331,35 @@ __global__ void __launch_bounds__(T) scan_kernel(ScanArgs a)
     VB carry = BOp::identity();         // wave 0: P(j - B) for the pending block j
 
     int parity = 0;
-    int64_t arr_lo = 0;  // batched scans: the array of this workgroup's last block
+    // Batched scans: the array of a block is found by a wave-uniform search
+    // through the scalar cache (the table is read-only during the launch)
+    // from this workgroup's previous array (a workgroup's blocks only move
+    // forward), one step ahead, so the data loads never wait for it.
+    int64_t arr_lo = 0;
+    BatchArray next_d;
+    next_d.x = nullptr;
+    next_d.y = nullptr;
+    next_d.n = 0;
+    next_d.first_block = 0;
+    auto find_array = [&](int64_t blk) {
+        const CBatchArray* arr = (const CBatchArray*)(a.arrays);
+        int64_t lo = arr_lo, hi = a.num_arrays;
+        while (hi - lo > 1) {
+            const int64_t mid = (lo + hi) >> 1;
+            if (arr[mid].first_block <= blk)
+                lo = mid;
+            else
+                hi = mid;
+        }
+        arr_lo = lo;
+        next_d.x = arr[lo].x;  // field by field: no copy constructor binds the constant address space
+        next_d.y = arr[lo].y;
+        next_d.n = arr[lo].n;
+        next_d.first_block = arr[lo].first_block;
+    };
+    if constexpr (MODE == kModeBatched) {
+        if (int64_t(blockIdx.x) < a.num_blocks) find_array(blockIdx.x);
+    }
     // One pipeline step: load and scan block i (when have_new) while the pending
     // block is resolved and stored.  The step that only drains the last
     // pending block is a separate instantiation, so inside the main loop every
@@ -354,25 +382,8 @@ __global__ void __launch_bounds__(T) scan_kernel(ScanArgs a)
         if (have_new) {
             bool vec_ok;
             if constexpr (MODE == kModeBatched) {
-                // last array with first_block <= i: a wave-uniform search through
-                // the scalar cache (the table is read-only during the launch),
-                // starting from this workgroup's previous array, since a
-                // workgroup's blocks only move forward
-                const CBatchArray* arr = (const CBatchArray*)(a.arrays);
-                int64_t lo = arr_lo, hi = a.num_arrays;
-                while (hi - lo > 1) {
-                    const int64_t mid = (lo + hi) >> 1;
-                    if (arr[mid].first_block <= i)
-                        lo = mid;
-                    else
-                        hi = mid;
-                }
-                arr_lo = lo;
-                BatchArray d;  // field by field: no copy constructor binds the constant address space
-                d.x = arr[lo].x;
-                d.y = arr[lo].y;
-                d.n = arr[lo].n;
-                d.first_block = arr[lo].first_block;
+                // the array of block i was looked up one step ahead (next_d)
+                const BatchArray d = next_d;
                 x = static_cast<const In*>(d.x);
                 y = static_cast<Out*>(d.y);
                 n = d.n;
@@ -392,6 +403,9 @@ __global__ void __launch_bounds__(T) scan_kernel(ScanArgs a)
             if (full) {
 #pragma unroll
                 for (int r = 0; r < R; ++r) load_vector<In, E>(x + lane0 + int64_t(r) * ROW, raw[r]);
+            }
+            if constexpr (MODE == kModeBatched) {  // while the loads are in flight: the next block's array
+                if (i + B < a.num_blocks) find_array(i + B);
             }
             if constexpr (MODE == kModeSegmented) {  // segment heads inside this lane's vectors
                 // Found while the data loads are in flight.  The block's range

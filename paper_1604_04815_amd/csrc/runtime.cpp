@@ -637,12 +637,31 @@ lscan_status plan_locked(const Request& r, int dev, Workspace* ws_fixed, hipStre
     }
     if (occ <= 0) return LSCAN_ERR_UNSUPPORTED;
 
+    // Plain scans whose x sits `phase` elements past a vector boundary, with
+    // y at the same element phase, shift the block grid back by `phase`: the
+    // vector accesses of every full tile are then aligned again, and the
+    // blocks cover n + phase positions, the first `phase` of them empty.
+    int32_t phase = 0;
+    bool vec_ok = false;
+    if (r.mode != kModeBatched && r.mode != kModeCompact) {
+        const uintptr_t xa = reinterpret_cast<uintptr_t>(r.x), ya = reinterpret_cast<uintptr_t>(r.y);
+        const uintptr_t vec_bytes = uintptr_t(k.in_bytes) * uintptr_t(k.elems_per_vec);
+        vec_ok = xa % vec_bytes == 0 && ya % 16 == 0;
+        if (!vec_ok && r.mode == kModePlain && xa % uintptr_t(k.in_bytes) == 0) {
+            const uintptr_t ph = (xa % vec_bytes) / uintptr_t(k.in_bytes);
+            if (ya % 16 == (ph * uintptr_t(k.out_bytes)) % 16) {
+                vec_ok = true;
+                phase = int32_t(ph);
+            }
+        }
+    }
+
     const int64_t L = k.tile_elems;
     int64_t M = 0;
     if (r.mode == kModeBatched) {
         for (int64_t i = 0; i < r.num_arrays; ++i) M += (r.arrays[i].n + L - 1) / L;
     } else {
-        M = (r.n + L - 1) / L;
+        M = (r.n + phase + L - 1) / L;
     }
     const size_t desc_entries = (r.mode == kModeBatched) ? size_t(r.num_arrays) + 1 : 0;
 
@@ -706,14 +725,13 @@ lscan_status plan_locked(const Request& r, int dev, Workspace* ws_fixed, hipStre
         a.vec_ok = (reinterpret_cast<uintptr_t>(r.x) % 16 == 0 &&
                     reinterpret_cast<uintptr_t>(r.keep) % 16 == 0) ? 1 : 0;
     } else {
-        const int vec_bytes = k.in_bytes * k.elems_per_vec;
         a.x = r.x;
         a.y = r.y;
         a.n = r.n;
         a.offsets = r.offsets;
         a.num_segments = r.num_segments;
-        a.vec_ok = (reinterpret_cast<uintptr_t>(r.x) % uintptr_t(vec_bytes) == 0 &&
-                    reinterpret_cast<uintptr_t>(r.y) % 16 == 0) ? 1 : 0;
+        a.vec_ok = vec_ok ? 1 : 0;
+        a.phase = phase;
         if (r.mode == kModeSegmented) {  // the first segment of every block, written before the scan
             st = ensure_segment_table(*ws, stream, size_t(M) + 1);
             if (st != LSCAN_OK) return st;

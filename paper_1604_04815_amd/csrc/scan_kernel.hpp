@@ -308,6 +308,7 @@ __global__ void __launch_bounds__(T) scan_kernel(ScanArgs a)
     const int wave = threadIdx.x >> 6;
     const int64_t B = gridDim.x;
     const uint32_t tag = __hip_atomic_load(a.ctrl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1u;
+    const int64_t ph = (MODE == kModePlain) ? int64_t(a.phase) : 0;  // alignment phase (plain scans)
 
     // The block scanned in the previous iteration waits, in registers, for
     // its prefix: it is resolved (window fold) and stored one iteration
@@ -392,14 +393,18 @@ __global__ void __launch_bounds__(T) scan_kernel(ScanArgs a)
                 vec_ok = (reinterpret_cast<uintptr_t>(d.x) % uintptr_t(kVecBytes) == 0) &&
                          (reinterpret_cast<uintptr_t>(d.y) % 16 == 0);
             } else {
-                x = static_cast<const In*>(a.x);
-                y = static_cast<Out*>(a.y);
-                n = a.n;
+                // plain scans of arrays that start ph elements past a vector
+                // boundary run in virtual positions v = index + ph, so that
+                // every block but the first (whose first ph positions hold
+                // nothing) is read and written with whole vectors
+                x = static_cast<const In*>(a.x) - ph;
+                y = static_cast<Out*>(a.y) - ph;
+                n = a.n + ph;
                 tile0 = i * L;
                 vec_ok = a.vec_ok != 0;
             }
             lane0 = tile0 + int64_t(wave) * (R * ROW) + int64_t(lane) * E;
-            full = vec_ok && (tile0 + L <= n);
+            full = vec_ok && (tile0 + L <= n) && (tile0 >= ph);
             if (full) {
 #pragma unroll
                 for (int r = 0; r < R; ++r) load_vector<In, E>(x + lane0 + int64_t(r) * ROW, raw[r]);
@@ -507,7 +512,7 @@ __global__ void __launch_bounds__(T) scan_kernel(ScanArgs a)
                             e[r][k] = EOp::make(lift_elem<BaseOp>(raw[r][k], lane0 + int64_t(r) * ROW + k),
                                                 (head[r] >> k) & 1u);
                         else
-                            e[r][k] = lift_elem<BaseOp>(raw[r][k], lane0 + int64_t(r) * ROW + k);
+                            e[r][k] = lift_elem<BaseOp>(raw[r][k], lane0 + int64_t(r) * ROW + k - ph);
                     }
             } else {
 #pragma unroll
@@ -515,11 +520,11 @@ __global__ void __launch_bounds__(T) scan_kernel(ScanArgs a)
 #pragma unroll
                     for (int k = 0; k < E; ++k) {
                         const int64_t p = lane0 + int64_t(r) * ROW + k;
-                        if (p < n) {
+                        if (p < n && p >= ph) {
                             if constexpr (MODE == kModeSegmented)
                                 e[r][k] = EOp::make(lift_elem<BaseOp>(x[p], p), (head[r] >> k) & 1u);
                             else
-                                e[r][k] = lift_elem<BaseOp>(x[p], p);
+                                e[r][k] = lift_elem<BaseOp>(x[p], p - ph);
                         } else {
                             e[r][k] = EOp::identity();
                         }
@@ -604,7 +609,7 @@ __global__ void __launch_bounds__(T) scan_kernel(ScanArgs a)
                 } else {
 #pragma unroll
                     for (int k = 0; k < E; ++k)
-                        if (p + k < p_n) p_y[p + k] = out[k];
+                        if (p + k < p_n && p + k >= ph) p_y[p + k] = out[k];
                 }
             }
         }

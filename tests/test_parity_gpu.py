@@ -2,6 +2,8 @@
 element, on seeded inputs at sizes that span several tiles, several rounds of
 the persistent grid and ragged tails."""
 import numpy as np
+
+import oracle
 import pytest
 import torch
 
@@ -127,17 +129,37 @@ def test_in_place(gpu_lib):
         compare(to_host(xd), x, dtype, op, True, what=f"in-place excl {dtype}/{op}")
 
 
+NP_OF = {"int32": np.int32, "int64": np.int64, "float32": np.float32}
+
+
 def test_unaligned_pointers(gpu_lib):
-    for dtype, op in (("int32", "add"), ("int64", "add"), ("float32", "min"), ("bfloat16", "add")):
-        n = 2_000_003
-        x = make_input(dtype, op, n + 1, seed=9)
-        base = to_device(x, dtype)
-        xd = base[1:]
-        y_base = torch.empty(n + 1, dtype=gpu_lib.out_dtype(base), device="cuda")
-        y = gpu_lib.inclusive(xd, op, out=y_base[1:])
-        info = gpu_lib.lscan_last_launch()
-        assert info.vector_path == 0
-        compare(to_host(y), x[1:], dtype, op, False, what=f"unaligned {dtype}/{op}")
+    # x and y a few elements past a 16-byte boundary: with the same phase the
+    # block grid is shifted and vectors are used; with different phases the
+    # element path runs; both exact, inclusive and exclusive, a few sizes
+    for dtype, op in (("int32", "add"), ("int64", "add"), ("float32", "min"), ("bfloat16", "add"),
+                      ("int32", "argmax"), ("float32", "add")):
+        out_el = 8 if op == "argmax" else (4 if dtype == "bfloat16" else np.dtype(NP_OF.get(dtype, np.float32)).itemsize)
+        in_el = 2 if dtype == "bfloat16" else np.dtype(NP_OF.get(dtype, np.float32)).itemsize
+        for n in (2_000_003, 70_001, 5):
+            for xo, yo in ((1, 1), (3, 3), (1, 2), (2, 0)):
+                x = make_input(dtype, "max" if op == "argmax" else op, n + 4, seed=9 + xo)
+                base = to_device(x, dtype)
+                xd = base[xo:xo + n]
+                y_base = torch.empty(n + 4, dtype=gpu_lib.out_dtype(base, op), device="cuda")
+                for excl in (False, True):
+                    fn = gpu_lib.exclusive if excl else gpu_lib.inclusive
+                    y = fn(xd, op, out=y_base[yo:yo + n])
+                    gpu_lib.lscan_check(torch.cuda.current_stream().cuda_stream)
+                    info = gpu_lib.lscan_last_launch()
+                    vec_in = 8 if dtype == "bfloat16" else 16
+                    same_phase = ((xo * in_el) % vec_in) // in_el * out_el % 16 == (yo * out_el) % 16
+                    assert info.vector_path == (1 if same_phase else 0), (dtype, op, xo, yo, info.vector_path)
+                    what = f"unaligned {dtype}/{op} n={n} x+{xo} y+{yo} excl={excl}"
+                    if op == "argmax":
+                        want = oracle.argscan(x[xo:xo + n], dtype, "argmax", excl)
+                        assert np.array_equal(to_host(y), want), what
+                    else:
+                        compare(to_host(y), x[xo:xo + n], dtype, op, excl, what=what)
 
 
 def test_repeated_launches_reuse_flags(gpu_lib):

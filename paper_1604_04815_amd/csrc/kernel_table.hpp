@@ -8,13 +8,15 @@
 namespace lscan {
 
 // One array of a batched launch (device-side descriptor).  Array r owns data
-// blocks [first_block, first_block + ceil(n / L)); the table ends with a
+// blocks [first_block, first_block + ceil((n + max(phase, 0)) / L)); the table ends with a
 // sentinel whose first_block is the total block count M.
 struct BatchArray {
     const void* x;
     void* y;
     int64_t n;
     int64_t first_block;
+    int64_t phase;  // -1: element path; else x and y sit this many elements past a vector
+                    // boundary and the array's blocks cover n + phase positions
 };
 
 // Kernel flavours: one array; one array cut into segments by offsets (heads

@@ -598,6 +598,26 @@ struct Plan {
     int occupancy = 0;
 };
 
+// Where full tiles of x (and y) can use the kernel's vectors: 0 when x sits
+// on a vector boundary and y on 16 bytes; ph > 0 when both sit ph elements
+// past such a boundary (the block grid is then shifted back by ph); -1
+// otherwise (the element-by-element path).
+int64_t alignment_phase(const KernelEntry& k, const void* x, const void* y)
+{
+    const uintptr_t xa = reinterpret_cast<uintptr_t>(x), ya = reinterpret_cast<uintptr_t>(y);
+    const uintptr_t vec_bytes = uintptr_t(k.in_bytes) * uintptr_t(k.elems_per_vec);
+    if (xa % uintptr_t(k.in_bytes) != 0) return -1;
+    const uintptr_t ph = (xa % vec_bytes) / uintptr_t(k.in_bytes);
+    return ya % 16 == (ph * uintptr_t(k.out_bytes)) % 16 ? int64_t(ph) : -1;
+}
+
+// Blocks of one array of a batch: its n elements after its alignment phase.
+int64_t batch_blocks(const KernelEntry& k, const lscan_array& arr, int64_t L)
+{
+    if (arr.n <= 0) return 0;
+    return (arr.n + std::max<int64_t>(alignment_phase(k, arr.x, arr.y), 0) + L - 1) / L;
+}
+
 // Choose the kernel and grid, size the workspace, run the co-residency test
 // if this shape is new, upload batched descriptors, and fill the kernel
 // arguments.  Called with g_mu held.  ws_fixed is a workspace owned by a
@@ -637,29 +657,25 @@ lscan_status plan_locked(const Request& r, int dev, Workspace* ws_fixed, hipStre
     }
     if (occ <= 0) return LSCAN_ERR_UNSUPPORTED;
 
-    // Plain scans whose x sits `phase` elements past a vector boundary, with
-    // y at the same element phase, shift the block grid back by `phase`: the
-    // vector accesses of every full tile are then aligned again, and the
-    // blocks cover n + phase positions, the first `phase` of them empty.
+    // Plain and batched scans whose x sits `phase` elements past a vector
+    // boundary, with y at the same element phase, shift the block grid back
+    // by `phase`: the vector accesses of every full tile are then aligned
+    // again, and the blocks cover n + phase positions, the first `phase` of
+    // them empty.
     int32_t phase = 0;
     bool vec_ok = false;
-    if (r.mode != kModeBatched && r.mode != kModeCompact) {
-        const uintptr_t xa = reinterpret_cast<uintptr_t>(r.x), ya = reinterpret_cast<uintptr_t>(r.y);
-        const uintptr_t vec_bytes = uintptr_t(k.in_bytes) * uintptr_t(k.elems_per_vec);
-        vec_ok = xa % vec_bytes == 0 && ya % 16 == 0;
-        if (!vec_ok && r.mode == kModePlain && xa % uintptr_t(k.in_bytes) == 0) {
-            const uintptr_t ph = (xa % vec_bytes) / uintptr_t(k.in_bytes);
-            if (ya % 16 == (ph * uintptr_t(k.out_bytes)) % 16) {
-                vec_ok = true;
-                phase = int32_t(ph);
-            }
-        }
+    if (r.mode == kModePlain) {
+        phase = int32_t(alignment_phase(k, r.x, r.y));
+        vec_ok = phase >= 0;
+        if (phase < 0) phase = 0;
+    } else if (r.mode == kModeSegmented) {
+        vec_ok = alignment_phase(k, r.x, r.y) == 0;
     }
 
     const int64_t L = k.tile_elems;
     int64_t M = 0;
     if (r.mode == kModeBatched) {
-        for (int64_t i = 0; i < r.num_arrays; ++i) M += (r.arrays[i].n + L - 1) / L;
+        for (int64_t i = 0; i < r.num_arrays; ++i) M += batch_blocks(k, r.arrays[i], L);
     } else {
         M = (r.n + phase + L - 1) / L;
     }
@@ -703,9 +719,10 @@ lscan_status plan_locked(const Request& r, int dev, Workspace* ws_fixed, hipStre
             ws->desc_host[i].y = r.arrays[i].y;
             ws->desc_host[i].n = r.arrays[i].n;
             ws->desc_host[i].first_block = first;
-            first += (r.arrays[i].n + L - 1) / L;
+            ws->desc_host[i].phase = alignment_phase(k, r.arrays[i].x, r.arrays[i].y);
+            first += batch_blocks(k, r.arrays[i], L);
         }
-        ws->desc_host[r.num_arrays] = BatchArray{nullptr, nullptr, 0, first};
+        ws->desc_host[r.num_arrays] = BatchArray{nullptr, nullptr, 0, first, 0};
         e = hipMemcpyAsync(ws->desc, ws->desc_host, desc_entries * sizeof(BatchArray), hipMemcpyHostToDevice,
                            stream);
         if (e != hipSuccess) return device_error(e);

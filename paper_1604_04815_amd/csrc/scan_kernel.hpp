@@ -292,7 +292,6 @@ __global__ void __launch_bounds__(T) scan_kernel(ScanArgs a)
     constexpr int W = sizeof(VB) / 4;
     constexpr int ROW = 64 * E;                  // elements per wave-row
     constexpr int64_t L = int64_t(T) * R * E;    // elements per data block
-    constexpr int kVecBytes = int(sizeof(In)) * E;
     static_assert(T % 64 == 0 && NWAVE <= 16, "wave64 workgroups of up to 1024 threads");
 
     if (a.residency_check) {
@@ -308,14 +307,13 @@ __global__ void __launch_bounds__(T) scan_kernel(ScanArgs a)
     const int wave = threadIdx.x >> 6;
     const int64_t B = gridDim.x;
     const uint32_t tag = __hip_atomic_load(a.ctrl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1u;
-    const int64_t ph = (MODE == kModePlain) ? int64_t(a.phase) : 0;  // alignment phase (plain scans)
 
     // The block scanned in the previous iteration waits, in registers, for
     // its prefix: it is resolved (window fold) and stored one iteration
     // later, while the loads of the next block are in flight, and by then
     // the aggregates it needs were published a round earlier.
     bool have_pend = false;
-    int64_t p_i = 0, p_n = 0, p_lane0 = 0;
+    int64_t p_i = 0, p_n = 0, p_lane0 = 0, p_ph = 0;
     Out* p_y = nullptr;
     bool p_full = false;
     uint32_t p_block_head = 0;
@@ -342,6 +340,7 @@ __global__ void __launch_bounds__(T) scan_kernel(ScanArgs a)
     next_d.y = nullptr;
     next_d.n = 0;
     next_d.first_block = 0;
+    next_d.phase = 0;
     auto find_array = [&](int64_t blk) {
         const CBatchArray* arr = (const CBatchArray*)(a.arrays);
         int64_t lo = arr_lo, hi = a.num_arrays;
@@ -357,6 +356,7 @@ __global__ void __launch_bounds__(T) scan_kernel(ScanArgs a)
         next_d.y = arr[lo].y;
         next_d.n = arr[lo].n;
         next_d.first_block = arr[lo].first_block;
+        next_d.phase = arr[lo].phase;
     };
     if constexpr (MODE == kModeBatched) {
         if (int64_t(blockIdx.x) < a.num_blocks) find_array(blockIdx.x);
@@ -374,6 +374,7 @@ __global__ void __launch_bounds__(T) scan_kernel(ScanArgs a)
         const In* x = nullptr;
         Out* y = nullptr;
         int64_t n = 0, tile0 = 0, lane0 = 0;
+        int64_t ph = 0;  // alignment phase: the block grid starts ph positions before x
         bool full = false;
         uint32_t block_head = 0;
         uint32_t head[R];
@@ -383,20 +384,22 @@ __global__ void __launch_bounds__(T) scan_kernel(ScanArgs a)
         if (have_new) {
             bool vec_ok;
             if constexpr (MODE == kModeBatched) {
-                // the array of block i was looked up one step ahead (next_d)
+                // the array of block i was looked up one step ahead (next_d);
+                // the host decided its path and phase
                 const BatchArray d = next_d;
-                x = static_cast<const In*>(d.x);
-                y = static_cast<Out*>(d.y);
-                n = d.n;
+                vec_ok = d.phase >= 0;
+                ph = vec_ok ? d.phase : 0;
+                x = static_cast<const In*>(d.x) - ph;
+                y = static_cast<Out*>(d.y) - ph;
+                n = d.n + ph;
                 tile0 = (i - d.first_block) * L;
                 block_head = (tile0 == 0) ? 1u : 0u;
-                vec_ok = (reinterpret_cast<uintptr_t>(d.x) % uintptr_t(kVecBytes) == 0) &&
-                         (reinterpret_cast<uintptr_t>(d.y) % 16 == 0);
             } else {
-                // plain scans of arrays that start ph elements past a vector
-                // boundary run in virtual positions v = index + ph, so that
-                // every block but the first (whose first ph positions hold
-                // nothing) is read and written with whole vectors
+                // arrays that start ph elements past a vector boundary run in
+                // virtual positions v = index + ph, so that every block but
+                // the first (whose first ph positions hold nothing) is read
+                // and written with whole vectors (plain scans; 0 otherwise)
+                if constexpr (MODE == kModePlain) ph = a.phase;
                 x = static_cast<const In*>(a.x) - ph;
                 y = static_cast<Out*>(a.y) - ph;
                 n = a.n + ph;
@@ -609,7 +612,7 @@ __global__ void __launch_bounds__(T) scan_kernel(ScanArgs a)
                 } else {
 #pragma unroll
                     for (int k = 0; k < E; ++k)
-                        if (p + k < p_n && p + k >= ph) p_y[p + k] = out[k];
+                        if (p + k < p_n && p + k >= p_ph) p_y[p + k] = out[k];
                 }
             }
         }
@@ -619,6 +622,7 @@ __global__ void __launch_bounds__(T) scan_kernel(ScanArgs a)
         if (have_new) {
             p_i = i;
             p_n = n;
+            p_ph = ph;
             p_lane0 = lane0;
             p_y = y;
             p_full = full;

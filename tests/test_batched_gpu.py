@@ -95,3 +95,51 @@ def test_graph_batched_replays(gpu_lib):
             compare(to_host(y), h, "float32", "add", False, True, what=f"graph batched replay {rep} array {k}")
         torch.cumsum(xs[2], 0)  # unrelated eager work on the stream
     g.destroy()
+
+
+MISALIGNED = [("int32", "add", False), ("int64", "max", False), ("float32", "add", True),
+              ("bfloat16", "add", False), ("float32", "min", False)]
+
+
+@pytest.mark.parametrize("dtype,op,comp", MISALIGNED, ids=[f"{d}-{o}{'-comp' if c else ''}" for d, o, c in MISALIGNED])
+def test_batched_misaligned_arrays(gpu_lib, dtype, op, comp):
+    # arrays cut at arbitrary element offsets out of one buffer, outputs cut
+    # at the same offsets (equal phases: shifted block grids, vectors) and,
+    # for every third array, one element further on (different phases: the
+    # element path), sizes across tiles with ragged tails, empty arrays too
+    L = tile_len(gpu_lib, dtype)
+    rng = np.random.default_rng(23)
+    sizes = [1, 2, 5, L - 1, L, L + 3, 0, 2 * L + 7, 3 * L - 2, 17]
+    sizes += [int(v) for v in np.floor(np.exp(rng.uniform(0, np.log(200_000), 30)))]
+    gaps = rng.integers(1, 5, size=len(sizes))  # outputs one further on must not reach the next array
+    starts = np.cumsum(np.concatenate([[1], (np.array(sizes) + gaps)[:-1]]))
+    total = int(starts[-1] + sizes[-1] + 2)
+    host = make_input(dtype, op, total, seed=71)
+    xb = to_device(host, dtype)
+    yb = torch.empty(total + 1, dtype=gpu_lib.out_dtype(xb), device="cuda")
+    xs, ys = [], []
+    for k, (s, n) in enumerate(zip(starts, sizes)):
+        s = int(s)
+        o = s + (1 if k % 3 == 2 else 0)
+        xs.append(xb[s:s + n])
+        ys.append(yb[o:o + n])
+    log(f"[batched misaligned] {dtype} {op} comp={comp} arrays={len(xs)} L={L}")
+    for excl in (False, True):
+        yb.fill_(-7)
+        gpu_lib.batched(xs, op, exclusive=excl, compensated=comp, outs=ys)
+        gpu_lib.lscan_check(torch.cuda.current_stream().cuda_stream)
+        for k, (s, n) in enumerate(zip(starts, sizes)):
+            s = int(s)
+            compare(to_host(ys[k]), host[s:s + n], dtype, op, excl, comp,
+                    what=f"batched misaligned {dtype}/{op} array {k} n={n} at {s}")
+    if dtype == "int32":  # a captured batch of the same arrays replays the same outputs
+        want = [y.clone() for y in ys]
+        g = gpu_lib.lscan_graph_create_batched([(x.data_ptr(), y.data_ptr(), x.shape[0]) for x, y in zip(xs, ys)],
+                                               gpu_lib.I32, gpu_lib.OPS[op], gpu_lib.F_EXCLUSIVE)
+        for rep in range(3):
+            yb.fill_(-7)
+            g.launch()
+            g.check()
+            for k in range(len(ys)):
+                assert torch.equal(ys[k], want[k]), f"graph replay {rep} array {k}"
+        g.destroy()

@@ -24,7 +24,11 @@
  *
  * Pointers: x, y and offsets are DEVICE pointers owned by the caller, who
  * keeps them valid until the work completes (stream order).  x and y must be
- * aligned to their element size; 16-byte alignment selects the vector path.
+ * aligned to their element size.  Full blocks use 16-byte vectors when x
+ * sits on a vector boundary (16 bytes; 8 for bf16) and y on 16 bytes, or,
+ * for plain and batched scans, when x and y sit the same number of elements
+ * past such boundaries (the block grid is then shifted by that many
+ * elements); otherwise every element is moved on its own (slower).
  * y == x (in place) is allowed when input and output types are equal
  * (Section 4.5 of the paper: every element is read once before it is written
  * once); any other overlap is rejected.  Streams are hipStream_t passed as
@@ -163,7 +167,7 @@ lscan_status lscan_segmented(const void *x, void *y, int64_t n_total,
  * the segmented operator, restarting at the first block of every array.
  *   arrays  HOST pointer to `count` descriptors; each x / y is a DEVICE
  *           pointer with the element-alignment and in-place rules above
- *           (16-byte alignment selects the vector path per array); arrays
+ *           (the vector rule above applies per array); arrays
  *           must not overlap each other (not checked); n == 0 is allowed
  *   flags   LSCAN_F_EXCLUSIVE, LSCAN_F_COMPENSATED as above
  * The descriptor table is copied to the device before the launch; the host

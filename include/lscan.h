@@ -338,8 +338,10 @@ lscan_status lscan_radix_offsets(const void *keys, int64_t n, lscan_dtype dt,
  *   flags   0, LSCAN_F_EXCLUSIVE and/or LSCAN_F_DETERMINISTIC
  *   p       null or groups_per_cu / handoff (a tile shape: the kernel fixes
  *           it, LSCAN_ERR_UNSUPPORTED)
- * A handle built against a different version of the headers is undefined
- * behaviour; a null or malformed handle is LSCAN_ERR_INVALID_ARG.
+ * Every handle carries a tag of the kernel-argument layout of the headers it
+ * was built with: a handle built against headers of another layout is
+ * refused with LSCAN_ERR_UNSUPPORTED before any device work; a null handle,
+ * or one that lscan_custom.hpp did not make, is LSCAN_ERR_INVALID_ARG.
  */
 typedef struct lscan_custom_kernel lscan_custom_kernel;
 lscan_status lscan_scan_custom(const lscan_custom_kernel *kernel,

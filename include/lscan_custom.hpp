@@ -43,6 +43,7 @@ struct Entry {
     static lscan::KernelEntry make()
     {
         lscan::KernelEntry k;
+        k.abi = lscan::kKernelAbi;
         k.func = reinterpret_cast<const void*>(&lscan::scan_kernel<Op, T, R, lscan::kModePlain>);
         k.launch = &lscan::launch_scan<Op, lscan::kModePlain, T, R>;
         k.block_threads = T;

@@ -327,6 +327,7 @@ KernelEntry make_compact_entry()
     constexpr int TT = kShapeThreads[S];
     constexpr int R = kShapeVectors[S];
     KernelEntry k;
+    k.abi = kKernelAbi;
     k.func = reinterpret_cast<const void*>(&compact_kernel<T, TT, R>);
     k.launch = &launch_compact<T, TT, R>;
     k.block_threads = TT;

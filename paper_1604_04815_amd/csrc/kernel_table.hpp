@@ -59,7 +59,16 @@ using LaunchFn = hipError_t (*)(const ScanArgs&, int grid, hipStream_t);
 // blocks of tile_elems elements, before the scan on the same stream.
 hipError_t launch_segment_table(const ScanArgs& a, int64_t tile_elems, hipStream_t stream);
 
+// Layout tag of KernelEntry and ScanArgs: a kernel instantiated by a
+// caller's library (lscan_custom.hpp) is refused unless it was built with
+// the same layout as the runtime.  High half: a fixed mark; then the size
+// of ScanArgs; low nibble: a revision for same-size layout changes.
+constexpr uint32_t kKernelAbiMark = 0x4C530000u;
+constexpr uint32_t kKernelAbi = kKernelAbiMark | (uint32_t(sizeof(ScanArgs)) << 4) | 1u;
+static_assert(sizeof(ScanArgs) < 4096, "the size of ScanArgs fits the tag");
+
 struct KernelEntry {
+    uint32_t abi;             // kKernelAbi of the headers the kernel was built with
     const void* func;         // the __global__ function (occupancy queries)
     LaunchFn launch;
     int32_t block_threads;    // T

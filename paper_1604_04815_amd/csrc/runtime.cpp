@@ -1439,7 +1439,9 @@ lscan_status lscan_scan_custom(const lscan_custom_kernel* kernel, const void* x,
                                uint32_t flags, const lscan_params* p, void* stream)
 {
     const KernelEntry* k = reinterpret_cast<const KernelEntry*>(kernel);
-    if (!k || !k->func || !k->launch) return LSCAN_ERR_INVALID_ARG;
+    if (!k || (k->abi & 0xFFFF0000u) != kKernelAbiMark) return LSCAN_ERR_INVALID_ARG;
+    if (k->abi != kKernelAbi) return LSCAN_ERR_UNSUPPORTED;  // built against another layout of the headers
+    if (!k->func || !k->launch) return LSCAN_ERR_INVALID_ARG;
     if (k->block_threads < 64 || k->block_threads > 1024 || k->block_threads % 64 != 0 || k->vectors_per_lane < 1 ||
         k->elems_per_vec < 1 || k->in_bytes < 1 || k->out_bytes < 1 || k->slot_words < 1 ||
         k->tile_elems != int64_t(k->block_threads) * k->vectors_per_lane * k->elems_per_vec)

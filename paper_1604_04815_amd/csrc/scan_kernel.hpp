@@ -685,6 +685,7 @@ KernelEntry make_entry()
     constexpr int R = kShapeVectors[S];
     using BOp = typename ModeOps<BaseOp, MODE>::BlkOp;
     KernelEntry k;
+    k.abi = kKernelAbi;
     k.func = reinterpret_cast<const void*>(&scan_kernel<BaseOp, T, R, MODE>);
     k.launch = &launch_scan<BaseOp, MODE, T, R>;
     k.block_threads = T;

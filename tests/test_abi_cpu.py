@@ -330,6 +330,16 @@ def test_custom_scan_validation(lib):
     assert f(k, None, None, 0, 0, None, None) == binding.OK                        # nothing to do
     # the three example shapes are distinct kernels
     assert len({kernels["default"], kernels["small"], kernels["wide"]}) == 3
+    # a handle built against another layout of the headers: its layout tag
+    # (the first 32-bit word) keeps the mark but not the revision
+    copy = (ctypes.c_char * 56)()
+    ctypes.memmove(copy, k, 56)
+    tag = ctypes.c_uint32.from_buffer(copy)
+    assert tag.value >> 16 == 0x4C53
+    tag.value ^= 0x1
+    assert f(ctypes.addressof(copy), FAKE_X, FAKE_Y, 8, 0, None, None) == binding.ERR_UNSUPPORTED
+    tag.value = 0
+    assert f(ctypes.addressof(copy), FAKE_X, FAKE_Y, 8, 0, None, None) == binding.ERR_INVALID_ARG
 
 
 def test_watchdog_setter(lib):

@@ -105,3 +105,26 @@ def test_affine_full_size(gpu_lib, kernels):
     ab = maps(n, 9)
     log("[custom] affine 2^27")
     check(run(gpu_lib, kernels["default"], ab), ab, False, "2^27")
+
+
+def test_affine_misaligned(gpu_lib, kernels):
+    # maps (8 bytes each; two per 16-byte vector) starting one map past a
+    # vector boundary: with the output at the same phase the block grid is
+    # shifted and vectors are used, with the output aligned the element path
+    # runs; both bit-exact, inclusive and exclusive
+    k = kernels["default"]
+    for n in (5, 4097, 300_001):
+        ab = maps(n, 40 + n)
+        base = to_dev(np.concatenate([maps(1, 1), ab, maps(2, 2)]))   # one map before the data
+        x = base[2:2 + 2 * n]
+        for y_words, vec in ((2, 1), (4, 0)):
+            ybase = torch.zeros(2 * n + 8, dtype=torch.int32, device="cuda")
+            y = ybase[y_words:y_words + 2 * n]
+            for excl in (False, True):
+                gpu_lib.scan_custom(k, x, n, out=y, exclusive=excl)
+                gpu_lib.lscan_check(torch.cuda.current_stream().cuda_stream)
+                assert gpu_lib.lscan_last_launch().vector_path == vec, (n, y_words)
+                got = y.cpu().numpy().view(np.uint32).reshape(-1, 2)
+                check(got, ab, excl, f"misaligned n={n} y+{y_words} words excl={excl}")
+            # nothing written outside y
+            assert not torch.any(ybase[:y_words]).item() and not torch.any(ybase[y_words + 2 * n:]).item()

@@ -429,6 +429,7 @@ lscan_status ensure_segment_table(Workspace& ws, hipStream_t stream, size_t entr
     if (ws.seg_cap >= entries) return LSCAN_OK;
     if (capturing(stream)) return LSCAN_ERR_UNSUPPORTED;  // size the workspace with an eager call first
     hipError_t e;
+    const size_t old_cap = ws.seg_cap;
     if (ws.seg_first) {
         e = hipStreamSynchronize(stream);  // an earlier scan on this stream may still read it
         if (e != hipSuccess) return device_error(e);
@@ -437,7 +438,7 @@ lscan_status ensure_segment_table(Workspace& ws, hipStream_t stream, size_t entr
         ws.seg_first = nullptr;
         ws.seg_cap = 0;
     }
-    const size_t cap = std::max<size_t>(entries, std::max<size_t>(2 * ws.seg_cap, 1024));
+    const size_t cap = std::max<size_t>(entries, std::max<size_t>(2 * old_cap, 1024));
     e = hipMalloc(reinterpret_cast<void**>(&ws.seg_first), cap * sizeof(int64_t));
     if (e != hipSuccess) {
         (void)hipGetLastError();
@@ -474,9 +475,13 @@ lscan_status ensure_workspace(Workspace& ws, hipStream_t stream, size_t words, s
             (void)hipGetLastError();
             return LSCAN_ERR_NO_MEMORY;
         }
-        ws.words = alloc;
         e = hipMemsetAsync(ws.slots, 0, alloc * sizeof(uint64_t), stream);
-        if (e != hipSuccess) return device_error(e);
+        if (e != hipSuccess) {  // never keep flag words that were not cleared
+            (void)hipFree(ws.slots);
+            ws.slots = nullptr;
+            return device_error(e);
+        }
+        ws.words = alloc;
     } else if (need_reset) {
         e = hipMemsetAsync(ws.slots, 0, ws.words * sizeof(uint64_t), stream);
         if (e != hipSuccess) return device_error(e);
@@ -488,7 +493,11 @@ lscan_status ensure_workspace(Workspace& ws, hipStream_t stream, size_t words, s
             return LSCAN_ERR_NO_MEMORY;
         }
         e = hipMemsetAsync(ws.ctrl, 0, 64, stream);
-        if (e != hipSuccess) return device_error(e);
+        if (e != hipSuccess) {
+            (void)hipFree(ws.ctrl);
+            ws.ctrl = nullptr;
+            return device_error(e);
+        }
     } else if (need_reset) {
         // keep the timeout flag (word 2); restart the tag and the exit counter,
         // and forget the tag of the last launch that gave up (word 3), which
@@ -935,7 +944,10 @@ lscan_status ensure_bfs_workspace(BfsWorkspace& ws, hipStream_t stream, int64_t 
     ws.cap_grid = grid;
     ws.next_tag = 0;
     e = hipMemsetAsync(ws.mem, 0, ws.flag_bytes, stream);
-    if (e != hipSuccess) return device_error(e);
+    if (e != hipSuccess) {  // never keep flag words that were not cleared
+        free_bfs_workspace(ws);
+        return device_error(e);
+    }
     return LSCAN_OK;
 }
 

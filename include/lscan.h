@@ -406,8 +406,9 @@ lscan_status lscan_bfs_with_params(const int64_t *row_offsets,
                                    void *stream);
 
 /*
- * Graph-captured launches.  lscan_graph_create_* prepares one segmented or
- * batched launch (workspace, co-residency test, descriptor upload, all on a
+ * Graph-captured launches.  lscan_graph_create_* prepares one plain,
+ * segmented or batched launch (workspace, co-residency test, descriptor
+ * upload, all on a
  * private stream, synchronously) and captures it into a hipGraph that owns
  * its own flag workspace; lscan_graph_launch replays it on `stream`.  The
  * device pointers are fixed at creation: the caller changes the DATA in x /
@@ -418,6 +419,14 @@ lscan_status lscan_bfs_with_params(const int64_t *row_offsets,
  * replay; lscan_graph_destroy synchronizes the device and frees the graph.
  */
 typedef struct lscan_graph lscan_graph;
+/* One plain scan of n elements (Section 3): inclusive, or exclusive with
+ * LSCAN_F_EXCLUSIVE in flags; the other flags, types, operators and pointer
+ * rules are those of lscan_inclusive.  n == 0 (nothing to capture) is
+ * LSCAN_ERR_INVALID_ARG. */
+lscan_status lscan_graph_create_scan(const void *x, void *y, int64_t n,
+                                     lscan_dtype dt, lscan_op op,
+                                     uint32_t flags, const lscan_params *p,
+                                     lscan_graph **out);
 lscan_status lscan_graph_create_segmented(const void *x, void *y,
                                           int64_t n_total,
                                           const int64_t *offsets,

@@ -103,6 +103,8 @@ SIGNATURES = {
     "lscan_scan_custom": ([_vp, _vp, _vp, _i64, _u32, ctypes.POINTER(Params), _vp], _i32),
     "lscan_bfs": ([_vp, _vp, _i64, _i64, _i32, _vp, _vp, _vp, _vp], _i32),
     "lscan_bfs_with_params": ([_vp, _vp, _i64, _i64, _i32, _vp, _vp, _vp, ctypes.POINTER(Params), _vp], _i32),
+    "lscan_graph_create_scan": ([_vp, _vp, _i64, _i32, _i32, _u32, ctypes.POINTER(Params), ctypes.POINTER(_vp)],
+                                _i32),
     "lscan_graph_create_segmented": ([_vp, _vp, _i64, _vp, _i64, _i32, _i32, _u32, ctypes.POINTER(Params),
                                       ctypes.POINTER(_vp)], _i32),
     "lscan_graph_create_batched": ([ctypes.POINTER(Array), _i64, _i32, _i32, _u32, ctypes.POINTER(Params),
@@ -234,6 +236,15 @@ class Graph:
             self.destroy()
         except Exception:  # noqa: BLE001 - interpreter shutdown
             pass
+
+
+def lscan_graph_create_scan(x, y, n, dt, op, flags=0, params: Params | None = None) -> Graph:
+    """Capture one plain scan of the device pointers x -> y (n elements;
+    F_EXCLUSIVE in flags for the exclusive scan) into a graph."""
+    h = ctypes.c_void_p()
+    p = ctypes.byref(params) if params is not None else None
+    _check(load().lscan_graph_create_scan(x, y, n, dt, op, flags, p, ctypes.byref(h)), "lscan_graph_create_scan")
+    return Graph(h.value)
 
 
 def lscan_graph_create_segmented(x, y, n_total, offsets, num_segments, dt, op, flags=0,

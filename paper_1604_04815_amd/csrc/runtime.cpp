@@ -1229,6 +1229,16 @@ lscan_status lscan_batched_with_params(const lscan_array* arrays, int64_t count,
     return st != LSCAN_OK ? st : run(r, stream);
 }
 
+lscan_status lscan_graph_create_scan(const void* x, void* y, int64_t n, lscan_dtype dt, lscan_op op, uint32_t flags,
+                                     const lscan_params* p, lscan_graph** out)
+{
+    Request r;
+    const bool exclusive = (flags & LSCAN_F_EXCLUSIVE) != 0;
+    lscan_status st = make_request(kModePlain, x, y, n, nullptr, 0, nullptr, 0, dt, op, flags & ~LSCAN_F_EXCLUSIVE,
+                                   exclusive, p, &r);
+    return st != LSCAN_OK ? st : graph_create(r, out);
+}
+
 lscan_status lscan_graph_create_segmented(const void* x, void* y, int64_t n_total, const int64_t* offsets,
                                           int64_t num_segments, lscan_dtype dt, lscan_op op, uint32_t flags,
                                           const lscan_params* p, lscan_graph** out)

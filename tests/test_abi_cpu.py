@@ -181,6 +181,19 @@ def test_graph_validation(lib):
     assert st == binding.ERR_INVALID_ARG
     assert lib.lscan_graph_launch(None, None) == binding.ERR_INVALID_ARG
     assert lib.lscan_graph_destroy(None) == binding.ERR_INVALID_ARG
+    # plain scans: nothing to capture, bad flags, types, pointers
+    g = lib.lscan_graph_create_scan
+    assert g(None, None, 0, binding.I32, binding.ADD, 0, None, ctypes.byref(h)) == binding.ERR_INVALID_ARG
+    assert g(FAKE_X, FAKE_Y, 8, binding.I32, binding.ADD, 0x100, None, ctypes.byref(h)) == binding.ERR_INVALID_ARG
+    assert g(FAKE_X, FAKE_Y, 8, binding.I32, binding.ADD, binding.F_COMPENSATED, None,
+             ctypes.byref(h)) == binding.ERR_UNSUPPORTED
+    assert g(FAKE_X, FAKE_Y, 8, binding.I32, binding.ADD, binding.F_INDEX64, None,
+             ctypes.byref(h)) == binding.ERR_INVALID_ARG
+    assert g(FAKE_X, FAKE_Y, 8, 9, binding.ADD, 0, None, ctypes.byref(h)) == binding.ERR_INVALID_ARG
+    assert g(None, FAKE_Y, 8, binding.I32, binding.ADD, 0, None, ctypes.byref(h)) == binding.ERR_INVALID_ARG
+    assert g(FAKE_X + 2, FAKE_Y, 8, binding.I32, binding.ADD, 0, None, ctypes.byref(h)) == binding.ERR_INVALID_ARG
+    assert g(FAKE_X, FAKE_X + 4, 8, binding.I32, binding.ADD, 0, None, ctypes.byref(h)) == binding.ERR_INVALID_ARG
+    assert g(FAKE_X, FAKE_Y, 8, binding.I32, binding.ADD, binding.F_EXCLUSIVE, None, None) == binding.ERR_INVALID_ARG
 
 
 def test_params_kinds(lib):

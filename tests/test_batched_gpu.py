@@ -143,3 +143,38 @@ def test_batched_misaligned_arrays(gpu_lib, dtype, op, comp):
             for k in range(len(ys)):
                 assert torch.equal(ys[k], want[k]), f"graph replay {rep} array {k}"
         g.destroy()
+
+
+def test_graph_plain_replays(gpu_lib):
+    # one plain scan captured once and replayed with new data each time,
+    # eager scans on the same stream in between; int32 add inclusive, float32
+    # compensated exclusive, int32 running argmax, and an int32 scan whose x
+    # and y sit one element past a vector boundary (shifted block grid)
+    import oracle
+    n = 3 * 65_536 + 1234
+    cases = [("int32", "add", 0, 0), ("float32", "add", gpu_lib.F_EXCLUSIVE | gpu_lib.F_COMPENSATED, 0),
+             ("int32", "argmax", 0, 0), ("int32", "add", 0, 1)]
+    for dtype, op, flags, off in cases:
+        t = {"int32": torch.int32, "float32": torch.float32}[dtype]
+        xb = torch.empty(n + off, dtype=t, device="cuda")
+        xd = xb[off:]
+        yb = torch.empty(n + off, dtype=torch.int64 if op == "argmax" else t, device="cuda")
+        yd = yb[off:]
+        dt = {"int32": gpu_lib.I32, "float32": gpu_lib.F32}[dtype]
+        g = gpu_lib.lscan_graph_create_scan(xd.data_ptr(), yd.data_ptr(), n, dt, gpu_lib.OPS[op], flags)
+        assert gpu_lib.lscan_last_launch().vector_path == 1
+        excl = bool(flags & gpu_lib.F_EXCLUSIVE)
+        for rep in range(4):
+            x = make_input(dtype, "max" if op == "argmax" else op, n, seed=1300 + 11 * rep + off)
+            xd.copy_(torch.from_numpy(x))
+            g.launch()
+            g.check()
+            what = f"graph plain {dtype}/{op} flags={flags} off={off} replay {rep}"
+            if op == "argmax":
+                assert np.array_equal(to_host(yd), oracle.argscan(x, dtype, "argmax", excl)), what
+            else:
+                compare(to_host(yd), x, dtype, op, excl, bool(flags & gpu_lib.F_COMPENSATED), what=what)
+            z = gpu_lib.inclusive(xd, "max")  # eager work between replays, on the same stream
+            torch.cuda.synchronize()
+            compare(to_host(z), x, dtype, "max", False, what=f"eager between replays {rep}")
+        g.destroy()

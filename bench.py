@@ -502,10 +502,28 @@ def bench_latency(binding, workloads, steps):
         fn()
         torch.cuda.synchronize()
         host.append((time.perf_counter() - t0) * 1e3)
+    # the same scan captured once into a graph and replayed
+    g = binding.lscan_graph_create_scan(xd.data_ptr(), y.data_ptr(), 1 << 20, binding.I32, binding.ADD)
+    want = y.clone()
+    g.launch()
+    g.check()
+    if not torch.equal(y, want):
+        raise RuntimeError("graph replay differs from the eager scan")
+    gms, gper = time_steps(g.launch, max(steps, 50), 5)
+    ghost = []
+    for _ in range(max(steps, 50)):
+        t0 = time.perf_counter()
+        g.launch()
+        torch.cuda.synchronize()
+        ghost.append((time.perf_counter() - t0) * 1e3)
+    g.destroy()
     e = rate_entry(8 * (1 << 20), 1 << 20, ms, per)
     e.update({"device_ms_p50": round(pct(dev, 50), 5), "device_ms_min": round(min(dev), 5),
               "device_ms_p99": round(pct(dev, 99), 5),
-              "host_call_sync_ms_p50": round(pct(host, 50), 4), "host_call_sync_ms_p99": round(pct(host, 99), 4)})
+              "host_call_sync_ms_p50": round(pct(host, 50), 4), "host_call_sync_ms_p99": round(pct(host, 99), 4),
+              "graph_replay_ms_per_step": round(gms, 5),
+              "graph_host_launch_sync_ms_p50": round(pct(ghost, 50), 4),
+              "graph_host_launch_sync_ms_p99": round(pct(ghost, 99), 4)})
     return e
 
 

@@ -688,6 +688,77 @@ def cpu_baseline(x_host, budget_s: float):
             "gelem_s": round(n / t / 1e9, 3)}
 
 
+def cpu_oracle_rows(workloads, configs):
+    """The oracle (one core) timed on a bounded sample of each workload line
+    present in configs; attaches {"gelem_s", "sample", "cores"} as
+    "oracle_cpu" to that line (rates in the line's own element unit)."""
+    import numpy as np
+
+    import oracle
+
+    oracle.build(force=False)
+    n = 1 << 22
+
+    def timed(fn, elems, sample):
+        times = []
+        for _ in range(3):
+            t0 = time.perf_counter_ns()
+            fn()
+            times.append((time.perf_counter_ns() - t0) * 1e-9)
+        t = statistics.median(times)
+        return {"gelem_s": round(elems / t / 1e9, 4), "sample": sample, "cores": 1}
+
+    s = workloads.seed_for(9)
+    rows = {}
+    if "int64_add_2p27" in configs:
+        x = workloads.int64_half_open(n, -(2 ** 31), 2 ** 31, s)
+        rows["int64_add_2p27"] = timed(lambda: oracle.scan(x, "int64", "add"), n, "2^22 int64 of the same recipe")
+    if "int32_max_2p28" in configs:
+        x = workloads.full_range_int32(n, s)
+        rows["int32_max_2p28"] = timed(lambda: oracle.scan(x, "int32", "max"), n, "2^22 int32 of the same recipe")
+    if "float32_add_2p27" in configs:
+        x = workloads.signed_lognormal_f32(n, s)
+        r = timed(lambda: oracle.scan(x, "float32", "add"), n, "2^22 float32 of the same recipe (fp64 fold)")
+        rows["float32_add_2p27"] = rows["float32_add_2p27_compensated"] = r
+    if "bf16_add_2p27" in configs:
+        x = workloads.bf16_unit(n, s)
+        r = timed(lambda: oracle.scan(x, "bfloat16", "add"), n, "2^22 bf16 of the same recipe (fp64 fold)")
+        rows["bf16_add_2p27"] = rows["bf16_add_2p27_compensated"] = r
+    if "segmented_4096_int32_add" in configs:
+        off = workloads.segment_offsets(64, 1 << 16, s)
+        x = workloads.uniform_int(int(off[-1]), -1000, 1000, s)
+        rows["segmented_4096_int32_add"] = timed(lambda: oracle.segscan(x, off, "int32", "add"), x.shape[0],
+                                                 f"64 log-uniform segments, {x.shape[0]} int32")
+    if "compact_int32_2p28_half" in configs:
+        x = workloads.uniform_int(n, -1024, 1024, s)
+        keep = (np.random.default_rng(s).random(n) < 0.5).astype(np.uint8)
+        rows["compact_int32_2p28_half"] = timed(lambda: oracle.compact(x, keep), n, "2^22 int32, half kept")
+    if "argmax_int32_2p28" in configs:
+        x = workloads.uniform_int(n, -1024, 1024, s)
+        rows["argmax_int32_2p28"] = timed(lambda: oracle.argscan(x, "int32", "argmax"), n, "2^22 int32")
+    if "radix_offsets_int32_2p28_8bit" in configs:
+        x = workloads.full_range_int32(n, s)
+        rows["radix_offsets_int32_2p28_8bit"] = timed(lambda: oracle.radix_offsets(x, 0, 8, 1 << 14), n,
+                                                      "2^22 int32 keys, 8 bits, 16K-key blocks")
+    if "custom_affine_2p27" in configs:
+        g = np.random.default_rng(s)
+        ab = g.integers(0, 1 << 32, (n, 2), dtype=np.uint64).astype(np.uint32)
+        rows["custom_affine_2p27"] = timed(lambda: oracle.affine_scan(ab), n, "2^22 affine maps")
+    if "bfs_rmat22" in configs:
+        src, dst = workloads.rmat_edges(16, 16, s)
+        row, col = workloads.csr_from_edges(src, dst, 1 << 16)
+        deg = np.diff(row)
+        root = int(np.flatnonzero(deg > 0)[0])
+        lev = oracle.bfs_levels(row, col, root)
+        scanned = int(deg[lev >= 0].sum())
+        r = timed(lambda: oracle.bfs_levels(row, col, root), scanned,
+                  "R-MAT 2^16 vertices, edge factor 16, symmetric, one source")
+        r["unit"] = "G edges scanned/s"
+        rows["bfs_rmat22"] = r
+    for k, v in rows.items():
+        configs[k]["oracle_cpu"] = v
+
+
 def main(argv=None) -> int:
     global SETTLE_S
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
@@ -840,6 +911,8 @@ def main(argv=None) -> int:
         log(f"CPU oracle baseline (~{args.cpu_seconds:.0f} s)")
         cpu = cpu_baseline(x, args.cpu_seconds)
         cpu["cores_available"] = len(os.sched_getaffinity(0))
+        log("CPU oracle on a sample of every other line")
+        cpu_oracle_rows(workloads, configs)
 
     achieved = head["bytes"] / (head["ms"] * 1e-3) / 1e9
     # the kernel alone: algorithmic bytes over the mean of the per-launch

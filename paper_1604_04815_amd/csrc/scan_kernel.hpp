@@ -293,6 +293,7 @@ __global__ void __launch_bounds__(T) scan_kernel(ScanArgs a)
     constexpr int ROW = 64 * E;                  // elements per wave-row
     constexpr int64_t L = int64_t(T) * R * E;    // elements per data block
     static_assert(T % 64 == 0 && NWAVE <= 16, "wave64 workgroups of up to 1024 threads");
+    static_assert(R <= 32, "one bit per row");
 
     if (a.residency_check) {
         check_residency(a.ctrl, a.spin_limit);
@@ -314,6 +315,7 @@ __global__ void __launch_bounds__(T) scan_kernel(ScanArgs a)
     // the aggregates it needs were published a round earlier.
     bool have_pend = false;
     int64_t p_i = 0, p_n = 0, p_lane0 = 0, p_ph = 0;
+    uint32_t p_vrow = 0;
     Out* p_y = nullptr;
     bool p_full = false;
     uint32_t p_block_head = 0;
@@ -376,6 +378,7 @@ __global__ void __launch_bounds__(T) scan_kernel(ScanArgs a)
         int64_t n = 0, tile0 = 0, lane0 = 0;
         int64_t ph = 0;  // alignment phase: the block grid starts ph positions before x
         bool full = false;
+        uint32_t vrow = 0;  // batched partial blocks: the wave's rows that lie wholly inside the array
         uint32_t block_head = 0;
         uint32_t head[R];
 #pragma unroll
@@ -411,6 +414,18 @@ __global__ void __launch_bounds__(T) scan_kernel(ScanArgs a)
             if (full) {
 #pragma unroll
                 for (int r = 0; r < R; ++r) load_vector<In, E>(x + lane0 + int64_t(r) * ROW, raw[r]);
+            } else if (MODE == kModeBatched && vec_ok) {
+                // an array's first or last block: whole rows of the wave (a
+                // wave-uniform choice) still move as vectors
+                const int64_t row0 = tile0 + int64_t(wave) * (R * ROW);
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const int64_t rs = row0 + int64_t(r) * ROW;
+                    if (rs >= ph && rs + ROW <= n) {
+                        load_vector<In, E>(x + lane0 + int64_t(r) * ROW, raw[r]);
+                        vrow |= 1u << r;
+                    }
+                }
             }
             if constexpr (MODE == kModeBatched) {  // while the loads are in flight: the next block's array
                 if (i + B < a.num_blocks) find_array(i + B);
@@ -519,7 +534,15 @@ __global__ void __launch_bounds__(T) scan_kernel(ScanArgs a)
                     }
             } else {
 #pragma unroll
-                for (int r = 0; r < R; ++r)
+                for (int r = 0; r < R; ++r) {
+                    if constexpr (MODE == kModeBatched) {
+                        if ((vrow >> r) & 1u) {  // a whole row, read as vectors in stage 1
+#pragma unroll
+                            for (int k = 0; k < E; ++k)
+                                e[r][k] = lift_elem<BaseOp>(raw[r][k], lane0 + int64_t(r) * ROW + k - ph);
+                            continue;
+                        }
+                    }
 #pragma unroll
                     for (int k = 0; k < E; ++k) {
                         const int64_t p = lane0 + int64_t(r) * ROW + k;
@@ -532,6 +555,7 @@ __global__ void __launch_bounds__(T) scan_kernel(ScanArgs a)
                             e[r][k] = EOp::identity();
                         }
                     }
+                }
             }
 #pragma unroll
             for (int r = 0; r < R; ++r)
@@ -607,7 +631,7 @@ __global__ void __launch_bounds__(T) scan_kernel(ScanArgs a)
                         out[k] = BaseOp::lower(v);
                 }
                 const int64_t p = p_lane0 + int64_t(r) * ROW;
-                if (p_full) {
+                if (p_full || ((p_vrow >> r) & 1u)) {
                     store_vector<Out, E>(p_y + p, out);
                 } else {
 #pragma unroll
@@ -623,6 +647,7 @@ __global__ void __launch_bounds__(T) scan_kernel(ScanArgs a)
             p_i = i;
             p_n = n;
             p_ph = ph;
+            p_vrow = vrow;
             p_lane0 = lane0;
             p_y = y;
             p_full = full;

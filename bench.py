@@ -256,6 +256,32 @@ def bench_segmented(binding, workloads, steps, warmup):
                   "graph_bit_equal_to_eager": graph_same})
         if same is not None:
             e["bit_equal_to_plain_launches"] = same
+        if dtype == "int32":
+            # the same 4096 arrays as separate arrays of one batched launch
+            # (cut at arbitrary element offsets: each array's own alignment
+            # phase), eager and as a graph
+            table = [(xs.data_ptr(), ys.data_ptr(), xs.shape[0]) for xs, ys in views]
+            tab = binding._array_table(table)
+            lib = binding.load()
+            stream = torch.cuda.current_stream().cuda_stream
+
+            def batched():
+                binding._check(lib.lscan_batched(tab, len(table), binding.I32, binding.ADD, 0, stream),
+                               "lscan_batched")
+
+            y.zero_()
+            ms_b, per_b = time_steps(batched, steps, warmup)
+            binding.lscan_check(stream)
+            b_same = bool(torch.equal(seg_y, y))
+            gb = binding.lscan_graph_create_batched(table, binding.I32, binding.ADD)
+            y.zero_()
+            ms_bg, per_bg = time_steps(gb.launch, steps, warmup)
+            gb.check()
+            gb.destroy()
+            e.update({"batched": rate_entry(nbytes, n, ms_b, per_b),
+                      "batched_graph": rate_entry(nbytes, n, ms_bg, per_bg),
+                      "batched_speedup_vs_plain_launches": round(ms_plain / ms_bg, 2),
+                      "batched_bit_equal_to_segmented": b_same and bool(torch.equal(seg_y, y))})
         out[f"segmented_4096_{dtype}_add"] = e
         del xd, y, seg_y, views, od
         torch.cuda.empty_cache()

@@ -42,7 +42,7 @@ struct ScanArgs {
     uint64_t spin_limit;      // wall-clock ticks one wait may last
     int32_t exclusive;        // 1: exclusive scan
     int32_t vec_ok;           // 1: x and y allow full-width vector access
-    int32_t phase;            // plain scans: x and y sit this many elements past a vector
+    int32_t phase;            // plain and segmented scans: x and y sit this many elements past a vector
                               // boundary (the block grid is shifted by it; 0 when aligned)
     int32_t residency_check;  // 1: only test that all workgroups are resident at once, then exit
     int32_t chain;            // 1: the paper's prefix chain (block i waits for P(i - 1))

@@ -669,19 +669,17 @@ lscan_status plan_locked(const Request& r, int dev, Workspace* ws_fixed, hipStre
     }
     if (occ <= 0) return LSCAN_ERR_UNSUPPORTED;
 
-    // Plain and batched scans whose x sits `phase` elements past a vector
+    // Plain, segmented and batched scans whose x sits `phase` elements past a vector
     // boundary, with y at the same element phase, shift the block grid back
     // by `phase`: the vector accesses of every full tile are then aligned
     // again, and the blocks cover n + phase positions, the first `phase` of
     // them empty.
     int32_t phase = 0;
     bool vec_ok = false;
-    if (r.mode == kModePlain) {
+    if (r.mode == kModePlain || r.mode == kModeSegmented) {
         phase = int32_t(alignment_phase(k, r.x, r.y));
         vec_ok = phase >= 0;
         if (phase < 0) phase = 0;
-    } else if (r.mode == kModeSegmented) {
-        vec_ok = alignment_phase(k, r.x, r.y) == 0;
     }
 
     const int64_t L = k.tile_elems;

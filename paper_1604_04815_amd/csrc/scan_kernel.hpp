@@ -401,8 +401,9 @@ __global__ void __launch_bounds__(T) scan_kernel(ScanArgs a)
                 // arrays that start ph elements past a vector boundary run in
                 // virtual positions v = index + ph, so that every block but
                 // the first (whose first ph positions hold nothing) is read
-                // and written with whole vectors (plain scans; 0 otherwise)
-                if constexpr (MODE == kModePlain) ph = a.phase;
+                // and written with whole vectors (plain and segmented scans;
+                // segment offsets move with the grid)
+                ph = a.phase;
                 x = static_cast<const In*>(a.x) - ph;
                 y = static_cast<Out*>(a.y) - ph;
                 n = a.n + ph;
@@ -440,6 +441,7 @@ __global__ void __launch_bounds__(T) scan_kernel(ScanArgs a)
                 const CInt64* off = (const CInt64*)(a.offsets);
                 const int64_t S = a.num_segments;
                 int64_t s_lo, s_hi;
+                // offsets count from x, block positions from ph before it
                 if (a.seg_first) {  // the table written just before this launch: two scalar loads
                     const CInt64* first = (const CInt64*)(a.seg_first);
                     s_lo = first[i];
@@ -452,10 +454,10 @@ __global__ void __launch_bounds__(T) scan_kernel(ScanArgs a)
                         const int64_t m2 = a2 ? lo2 + ((hi2 - lo2) >> 1) : 0;
                         const int64_t v1 = off[m1], v2 = off[m2];
                         if (a1) {
-                            if (v1 < tile0) lo1 = m1 + 1; else hi1 = m1;
+                            if (v1 + ph < tile0) lo1 = m1 + 1; else hi1 = m1;
                         }
                         if (a2) {
-                            if (v2 < tile0 + L) lo2 = m2 + 1; else hi2 = m2;
+                            if (v2 + ph < tile0 + L) lo2 = m2 + 1; else hi2 = m2;
                         }
                     }
                     s_lo = lo1;
@@ -463,7 +465,7 @@ __global__ void __launch_bounds__(T) scan_kernel(ScanArgs a)
                 }
                 if (s_hi - s_lo <= kFewHeads) {
                     for (int64_t k = s_lo; k < s_hi; ++k) {
-                        const int64_t rel = off[k] - lane0;
+                        const int64_t rel = off[k] + ph - lane0;
 #pragma unroll
                         for (int r = 0; r < R; ++r) {
                             const int64_t d = rel - int64_t(r) * ROW;
@@ -474,10 +476,10 @@ __global__ void __launch_bounds__(T) scan_kernel(ScanArgs a)
 #pragma unroll
                     for (int r = 0; r < R; ++r) {
                         const int64_t p = lane0 + int64_t(r) * ROW;
-                        int64_t k = lower_bound_i64(a.offsets, s_lo, s_hi, p);
+                        int64_t k = lower_bound_i64(a.offsets, s_lo, s_hi, p - ph);
                         uint32_t h = 0;
                         for (; k < s_hi; ++k) {
-                            const int64_t o = a.offsets[k];
+                            const int64_t o = a.offsets[k] + ph;
                             if (o >= p + E) break;
                             h |= 1u << uint32_t(o - p);
                         }
@@ -527,7 +529,7 @@ __global__ void __launch_bounds__(T) scan_kernel(ScanArgs a)
 #pragma unroll
                     for (int k = 0; k < E; ++k) {
                         if constexpr (MODE == kModeSegmented)
-                            e[r][k] = EOp::make(lift_elem<BaseOp>(raw[r][k], lane0 + int64_t(r) * ROW + k),
+                            e[r][k] = EOp::make(lift_elem<BaseOp>(raw[r][k], lane0 + int64_t(r) * ROW + k - ph),
                                                 (head[r] >> k) & 1u);
                         else
                             e[r][k] = lift_elem<BaseOp>(raw[r][k], lane0 + int64_t(r) * ROW + k - ph);
@@ -548,7 +550,7 @@ __global__ void __launch_bounds__(T) scan_kernel(ScanArgs a)
                         const int64_t p = lane0 + int64_t(r) * ROW + k;
                         if (p < n && p >= ph) {
                             if constexpr (MODE == kModeSegmented)
-                                e[r][k] = EOp::make(lift_elem<BaseOp>(x[p], p), (head[r] >> k) & 1u);
+                                e[r][k] = EOp::make(lift_elem<BaseOp>(x[p], p - ph), (head[r] >> k) & 1u);
                             else
                                 e[r][k] = lift_elem<BaseOp>(x[p], p - ph);
                         } else {

@@ -99,3 +99,41 @@ def test_heads_per_block_around_matching_limit(gpu_lib, max_len):
         for excl in (False, True):
             got = run(gpu_lib, x, off, dtype, op, excl, comp)
             compare(got, x, dtype, op, excl, comp, offsets=off, what=f"heads {max_len} {dtype}/{op}/excl={excl}")
+
+
+SEG_UNALIGNED = [("int32", "add", False), ("int64", "max", False), ("float32", "add", True),
+                 ("bfloat16", "add", False), ("float32", "min", False)]
+
+
+@pytest.mark.parametrize("dtype,op,comp", SEG_UNALIGNED,
+                         ids=[f"{d}-{o}{'-comp' if c else ''}" for d, o, c in SEG_UNALIGNED])
+def test_segmented_unaligned(gpu_lib, dtype, op, comp):
+    # x and y a few elements past a vector boundary: with equal phases the
+    # block grid and the segment heads shift together and vectors are used,
+    # with different phases the element path runs; log-uniform segments with
+    # empty ones at the start, inside and at the end; inclusive and exclusive
+    from paper_1604_04815_amd import workloads as w
+    off = w.segment_offsets(700, 1 << 12, seed=w.seed_for(3, 7))
+    off = np.concatenate([[0, 0], off, [off[-1]]]).astype(np.int64)   # empty first and last segments
+    off[300] = off[299]                                                # and one inside
+    n = int(off[-1])
+    x = make_input(dtype, op, n + 4, seed=77)
+    od = torch.from_numpy(off).to("cuda")
+    t = {"int32": torch.int32, "int64": torch.int64, "float32": torch.float32, "bfloat16": torch.float32}[dtype]
+    in_el = {"int32": 4, "int64": 8, "float32": 4, "bfloat16": 2}[dtype]
+    out_el = 8 if dtype == "int64" else 4
+    vec_in = 8 if dtype == "bfloat16" else 16
+    for xo, yo in ((1, 1), (3, 3), (1, 2)):
+        base = to_device(x, dtype)
+        xd = base[xo:xo + n]
+        yb = torch.full((n + 4,), 7, dtype=t, device="cuda")
+        yd = yb[yo:yo + n]
+        same = ((xo * in_el) % vec_in) // in_el * out_el % 16 == (yo * out_el) % 16
+        for excl in (False, True):
+            gpu_lib.segmented(xd, od, op, exclusive=excl, compensated=comp, out=yd)
+            gpu_lib.lscan_check(torch.cuda.current_stream().cuda_stream)
+            assert gpu_lib.lscan_last_launch().vector_path == (1 if same else 0), (xo, yo)
+            compare(to_host(yd), x[xo:xo + n], dtype, op, excl, comp, offsets=off,
+                    what=f"seg unaligned {dtype}/{op} x+{xo} y+{yo} excl={excl}")
+        # nothing written outside y
+        assert torch.all(yb[:yo] == 7).item() and torch.all(yb[yo + n:] == 7).item()

@@ -25,10 +25,12 @@
  * Pointers: x, y and offsets are DEVICE pointers owned by the caller, who
  * keeps them valid until the work completes (stream order).  x and y must be
  * aligned to their element size.  Full blocks use 16-byte vectors when x
- * sits on a vector boundary (16 bytes; 8 for bf16) and y on 16 bytes, or,
- * for plain and batched scans, when x and y sit the same number of elements
- * past such boundaries (the block grid is then shifted by that many
- * elements); otherwise every element is moved on its own (slower).
+ * sits on a vector boundary (16 bytes; 8 for bf16) and y on 16 bytes, or
+ * when x and y sit the same number of elements past such boundaries (the
+ * block grid is then shifted by that many elements).  Plain and segmented
+ * scans whose y sits at another phase than x still read vectors and write
+ * element by element; batched arrays in that case move every element on
+ * its own (slower).
  * y == x (in place) is allowed when input and output types are equal
  * (Section 4.5 of the paper: every element is read once before it is written
  * once); any other overlap is rejected.  Streams are hipStream_t passed as
@@ -547,7 +549,9 @@ typedef struct {
     int32_t grid;          /* B */
     int32_t block_threads; /* T */
     int32_t slot_words;    /* 64-bit flag words per data block */
-    int32_t vector_path;   /* 1 if the 16-byte path was used */
+    int32_t vector_path;   /* 1: full blocks read and write vectors; 2: they
+                              read vectors and write element by element (y at
+                              another alignment phase than x); 0: elements */
     int32_t groups_per_cu; /* workgroups per CU of the launch */
     int32_t occupancy;     /* workgroups per CU the occupancy query allows */
 } lscan_launch_info;

@@ -41,9 +41,11 @@ struct ScanArgs {
                               // [4] residency arrivals, [5] residency failure, [6] residency exits
     uint64_t spin_limit;      // wall-clock ticks one wait may last
     int32_t exclusive;        // 1: exclusive scan
-    int32_t vec_ok;           // 1: x and y allow full-width vector access
-    int32_t phase;            // plain and segmented scans: x and y sit this many elements past a vector
+    int32_t vec_ok;           // 1: full blocks read x with full-width vectors
+    int32_t phase;            // plain and segmented scans: x sits this many elements past a vector
                               // boundary (the block grid is shifted by it; 0 when aligned)
+    int32_t store_vec;        // plain and segmented scans: 1 when y sits at the same phase, so full
+                              // blocks also write vectors (else they write element by element)
     int32_t residency_check;  // 1: only test that all workgroups are resident at once, then exit
     int32_t chain;            // 1: the paper's prefix chain (block i waits for P(i - 1))
     uint32_t* status_host;    // optional host-visible word that also receives the timeout flag
@@ -64,7 +66,7 @@ hipError_t launch_segment_table(const ScanArgs& a, int64_t tile_elems, hipStream
 // the same layout as the runtime.  High half: a fixed mark; then the size
 // of ScanArgs; low nibble: a revision for same-size layout changes.
 constexpr uint32_t kKernelAbiMark = 0x4C530000u;
-constexpr uint32_t kKernelAbi = kKernelAbiMark | (uint32_t(sizeof(ScanArgs)) << 4) | 1u;
+constexpr uint32_t kKernelAbi = kKernelAbiMark | (uint32_t(sizeof(ScanArgs)) << 4) | 2u;
 static_assert(sizeof(ScanArgs) < 4096, "the size of ScanArgs fits the tag");
 
 struct KernelEntry {

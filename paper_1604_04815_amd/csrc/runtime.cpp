@@ -674,12 +674,18 @@ lscan_status plan_locked(const Request& r, int dev, Workspace* ws_fixed, hipStre
     // by `phase`: the vector accesses of every full tile are then aligned
     // again, and the blocks cover n + phase positions, the first `phase` of
     // them empty.
+    // When y sits at another phase than x, the grid follows x: full blocks
+    // still read vectors and write element by element.
     int32_t phase = 0;
-    bool vec_ok = false;
+    bool vec_ok = false, store_vec = false;
     if (r.mode == kModePlain || r.mode == kModeSegmented) {
-        phase = int32_t(alignment_phase(k, r.x, r.y));
-        vec_ok = phase >= 0;
-        if (phase < 0) phase = 0;
+        const uintptr_t xa = reinterpret_cast<uintptr_t>(r.x);
+        const uintptr_t vec_bytes = uintptr_t(k.in_bytes) * uintptr_t(k.elems_per_vec);
+        if (xa % uintptr_t(k.in_bytes) == 0) {
+            phase = int32_t((xa % vec_bytes) / uintptr_t(k.in_bytes));
+            vec_ok = true;
+            store_vec = alignment_phase(k, r.x, r.y) >= 0;
+        }
     }
 
     const int64_t L = k.tile_elems;
@@ -759,6 +765,7 @@ lscan_status plan_locked(const Request& r, int dev, Workspace* ws_fixed, hipStre
         a.num_segments = r.num_segments;
         a.vec_ok = vec_ok ? 1 : 0;
         a.phase = phase;
+        a.store_vec = store_vec ? 1 : 0;
         if (r.mode == kModeSegmented) {  // the first segment of every block, written before the scan
             st = ensure_segment_table(*ws, stream, size_t(M) + 1);
             if (st != LSCAN_OK) return st;
@@ -791,7 +798,9 @@ lscan_status plan_locked(const Request& r, int dev, Workspace* ws_fixed, hipStre
     t_last_launch.grid = int32_t(B);
     t_last_launch.block_threads = k.block_threads;
     t_last_launch.slot_words = k.slot_words;
-    t_last_launch.vector_path = a.vec_ok;
+    // 1: vectors both ways; 2: vector reads, element writes; 0: elements
+    const bool split = (r.mode == kModePlain || r.mode == kModeSegmented) && !a.store_vec;
+    t_last_launch.vector_path = a.vec_ok ? (split ? 2 : 1) : 0;
     t_last_launch.groups_per_cu = groups;
     t_last_launch.occupancy = occ;
     return LSCAN_OK;

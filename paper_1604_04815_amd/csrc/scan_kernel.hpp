@@ -316,6 +316,7 @@ __global__ void __launch_bounds__(T) scan_kernel(ScanArgs a)
     bool have_pend = false;
     int64_t p_i = 0, p_n = 0, p_lane0 = 0, p_ph = 0;
     uint32_t p_vrow = 0;
+    bool p_svec = true;
     Out* p_y = nullptr;
     bool p_full = false;
     uint32_t p_block_head = 0;
@@ -378,6 +379,7 @@ __global__ void __launch_bounds__(T) scan_kernel(ScanArgs a)
         int64_t n = 0, tile0 = 0, lane0 = 0;
         int64_t ph = 0;  // alignment phase: the block grid starts ph positions before x
         bool full = false;
+        bool svec = true;  // full blocks store vectors (y at the grid's phase)
         uint32_t vrow = 0;  // batched partial blocks: the wave's rows that lie wholly inside the array
         uint32_t block_head = 0;
         uint32_t head[R];
@@ -409,6 +411,7 @@ __global__ void __launch_bounds__(T) scan_kernel(ScanArgs a)
                 n = a.n + ph;
                 tile0 = i * L;
                 vec_ok = a.vec_ok != 0;
+                svec = a.store_vec != 0;
             }
             lane0 = tile0 + int64_t(wave) * (R * ROW) + int64_t(lane) * E;
             full = vec_ok && (tile0 + L <= n) && (tile0 >= ph);
@@ -633,7 +636,7 @@ __global__ void __launch_bounds__(T) scan_kernel(ScanArgs a)
                         out[k] = BaseOp::lower(v);
                 }
                 const int64_t p = p_lane0 + int64_t(r) * ROW;
-                if (p_full || ((p_vrow >> r) & 1u)) {
+                if ((p_full && p_svec) || ((p_vrow >> r) & 1u)) {
                     store_vector<Out, E>(p_y + p, out);
                 } else {
 #pragma unroll
@@ -650,6 +653,7 @@ __global__ void __launch_bounds__(T) scan_kernel(ScanArgs a)
             p_n = n;
             p_ph = ph;
             p_vrow = vrow;
+            p_svec = svec;
             p_lane0 = lane0;
             p_y = y;
             p_full = full;

@@ -110,14 +110,14 @@ def test_affine_full_size(gpu_lib, kernels):
 def test_affine_misaligned(gpu_lib, kernels):
     # maps (8 bytes each; two per 16-byte vector) starting one map past a
     # vector boundary: with the output at the same phase the block grid is
-    # shifted and vectors are used, with the output aligned the element path
-    # runs; both bit-exact, inclusive and exclusive
+    # shifted and vectors are used, with the output aligned the maps are read
+    # as vectors and written one by one; both bit-exact, inclusive and exclusive
     k = kernels["default"]
     for n in (5, 4097, 300_001):
         ab = maps(n, 40 + n)
         base = to_dev(np.concatenate([maps(1, 1), ab, maps(2, 2)]))   # one map before the data
         x = base[2:2 + 2 * n]
-        for y_words, vec in ((2, 1), (4, 0)):
+        for y_words, vec in ((2, 1), (4, 2)):
             ybase = torch.zeros(2 * n + 8, dtype=torch.int32, device="cuda")
             y = ybase[y_words:y_words + 2 * n]
             for excl in (False, True):

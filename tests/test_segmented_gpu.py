@@ -110,7 +110,7 @@ SEG_UNALIGNED = [("int32", "add", False), ("int64", "max", False), ("float32", "
 def test_segmented_unaligned(gpu_lib, dtype, op, comp):
     # x and y a few elements past a vector boundary: with equal phases the
     # block grid and the segment heads shift together and vectors are used,
-    # with different phases the element path runs; log-uniform segments with
+    # with different phases vector reads and element writes; log-uniform segments with
     # empty ones at the start, inside and at the end; inclusive and exclusive
     from paper_1604_04815_amd import workloads as w
     off = w.segment_offsets(700, 1 << 12, seed=w.seed_for(3, 7))
@@ -132,7 +132,7 @@ def test_segmented_unaligned(gpu_lib, dtype, op, comp):
         for excl in (False, True):
             gpu_lib.segmented(xd, od, op, exclusive=excl, compensated=comp, out=yd)
             gpu_lib.lscan_check(torch.cuda.current_stream().cuda_stream)
-            assert gpu_lib.lscan_last_launch().vector_path == (1 if same else 0), (xo, yo)
+            assert gpu_lib.lscan_last_launch().vector_path == (1 if same else 2), (xo, yo)
             compare(to_host(yd), x[xo:xo + n], dtype, op, excl, comp, offsets=off,
                     what=f"seg unaligned {dtype}/{op} x+{xo} y+{yo} excl={excl}")
         # nothing written outside y

@@ -29,8 +29,8 @@
  * when x and y sit the same number of elements past such boundaries (the
  * block grid is then shifted by that many elements).  Plain and segmented
  * scans whose y sits at another phase than x still read vectors and write
- * element by element; batched arrays in that case move every element on
- * its own (slower).
+ * aligned vectors staged through LDS; batched arrays in that case move
+ * every element on its own (slower).
  * y == x (in place) is allowed when input and output types are equal
  * (Section 4.5 of the paper: every element is read once before it is written
  * once); any other overlap is rejected.  Streams are hipStream_t passed as
@@ -550,8 +550,9 @@ typedef struct {
     int32_t block_threads; /* T */
     int32_t slot_words;    /* 64-bit flag words per data block */
     int32_t vector_path;   /* 1: full blocks read and write vectors; 2: they
-                              read vectors and write element by element (y at
-                              another alignment phase than x); 0: elements */
+                              read vectors and write y, which sits at another
+                              alignment phase than x, through an LDS stage;
+                              0: elements */
     int32_t groups_per_cu; /* workgroups per CU of the launch */
     int32_t occupancy;     /* workgroups per CU the occupancy query allows */
 } lscan_launch_info;

@@ -45,7 +45,8 @@ struct ScanArgs {
     int32_t phase;            // plain and segmented scans: x sits this many elements past a vector
                               // boundary (the block grid is shifted by it; 0 when aligned)
     int32_t store_vec;        // plain and segmented scans: 1 when y sits at the same phase, so full
-                              // blocks also write vectors (else they write element by element)
+                              // blocks also write vectors directly (else through an LDS stage, or
+                              // element by element for 32-byte output vectors)
     int32_t residency_check;  // 1: only test that all workgroups are resident at once, then exit
     int32_t chain;            // 1: the paper's prefix chain (block i waits for P(i - 1))
     uint32_t* status_host;    // optional host-visible word that also receives the timeout flag

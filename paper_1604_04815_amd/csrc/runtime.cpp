@@ -675,7 +675,7 @@ lscan_status plan_locked(const Request& r, int dev, Workspace* ws_fixed, hipStre
     // again, and the blocks cover n + phase positions, the first `phase` of
     // them empty.
     // When y sits at another phase than x, the grid follows x: full blocks
-    // still read vectors and write element by element.
+    // still read vectors and write y through an LDS stage.
     int32_t phase = 0;
     bool vec_ok = false, store_vec = false;
     if (r.mode == kModePlain || r.mode == kModeSegmented) {

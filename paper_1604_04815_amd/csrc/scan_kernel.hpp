@@ -300,6 +300,10 @@ __global__ void __launch_bounds__(T) scan_kernel(ScanArgs a)
         return;
     }
 
+    // plain and segmented scans whose y sits at another alignment phase than
+    // x: each wave stages one output row here to write it as aligned vectors
+    constexpr bool kStageY = (MODE == kModePlain || MODE == kModeSegmented) && E * sizeof(Out) == 16;
+    __shared__ __attribute__((aligned(16))) Out s_ystage[kStageY ? NWAVE : 1][kStageY ? ROW + E : 1];
     __shared__ V s_wave_total[2][NWAVE];
     __shared__ VB s_block_prefix[2];
     __shared__ int s_abort[2];
@@ -638,6 +642,32 @@ __global__ void __launch_bounds__(T) scan_kernel(ScanArgs a)
                 const int64_t p = p_lane0 + int64_t(r) * ROW;
                 if ((p_full && p_svec) || ((p_vrow >> r) & 1u)) {
                     store_vector<Out, E>(p_y + p, out);
+                } else if (kStageY && p_full) {
+                    // y at another phase than the grid: stage the wave's row
+                    // at its offset from the aligned vector below it, then
+                    // write whole aligned vectors (and the partial vectors at
+                    // both ends element by element)
+                    Out* stage = s_ystage[kStageY ? wave : 0];
+                    Out* row_y = p_y + (p - int64_t(lane) * E);  // the wave-row's first output
+                    const int32_t shift = int32_t((reinterpret_cast<uintptr_t>(row_y) % 16) / sizeof(Out));
+#pragma unroll
+                    for (int k = 0; k < E; ++k) stage[shift + lane * E + k] = out[k];
+                    __builtin_amdgcn_wave_barrier();
+                    Out* dst = row_y - shift;
+                    const int32_t span = shift + ROW;  // staged outputs occupy [shift, span)
+                    for (int32_t c = lane * E; c < span; c += 64 * E) {
+                        if (c >= shift && c + E <= span) {
+                            Out v[E];
+#pragma unroll
+                            for (int k = 0; k < E; ++k) v[k] = stage[c + k];
+                            store_vector<Out, E>(dst + c, v);
+                        } else {
+#pragma unroll
+                            for (int k = 0; k < E; ++k)
+                                if (c + k >= shift && c + k < span) dst[c + k] = stage[c + k];
+                        }
+                    }
+                    __builtin_amdgcn_wave_barrier();
                 } else {
 #pragma unroll
                     for (int k = 0; k < E; ++k)

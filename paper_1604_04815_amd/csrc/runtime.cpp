@@ -198,9 +198,11 @@ void init_params_locked()
         g_params[kModeBatched][o] = g_params[kModePlain][o];
         g_params[kModeCompact][o] = t1024x4;
     }
-    // batches of many arrays: smaller blocks than the single-array 256 x 16
-    // (4096 arrays, int32 add: 4.93 -> 5.10 TB/s as a graph; 64 arrays: same)
-    for (int o : {kI32Add, kF32Add, kBF16Add, kBF16Max, kBF16Min}) g_params[kModeBatched][o] = t512x8g2;
+    // batches of many int32 arrays: smaller blocks than the single-array
+    // 256 x 16 (4096 arrays: 4.93 -> 5.10 TB/s as a graph; 64 arrays: same).
+    // The float32 and bf16 batched kernels at 512 x 8 need 129 VGPRs, so
+    // only one such group fits per CU: they keep 256 x 16.
+    g_params[kModeBatched][kI32Add] = t512x8g2;
     for (int m = 0; m < kNumModes; ++m)
         for (int o = 0; o < kNumOpCodes; ++o) g_default_params[m][o] = g_params[m][o];
     g_params_init = true;

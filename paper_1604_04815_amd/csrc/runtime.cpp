@@ -200,9 +200,10 @@ void init_params_locked()
     }
     // batches of many int32 arrays: smaller blocks than the single-array
     // 256 x 16 (4096 arrays: 4.93 -> 5.10 TB/s as a graph; 64 arrays: same).
-    // The float32 and bf16 batched kernels at 512 x 8 need 129 VGPRs, so
-    // only one such group fits per CU: they keep 256 x 16.
+    // The float32 batched kernel at 512 x 8 needs 129 VGPRs (one group per
+    // CU); 1024 x 4 measures best for it (4096 arrays: 4.72 -> 4.84 TB/s).
     g_params[kModeBatched][kI32Add] = t512x8g2;
+    g_params[kModeBatched][kF32Add] = t1024x4;
     for (int m = 0; m < kNumModes; ++m)
         for (int o = 0; o < kNumOpCodes; ++o) g_default_params[m][o] = g_params[m][o];
     g_params_init = true;

@@ -49,3 +49,22 @@ def test_bench_refuses_several_gpus():
     r = subprocess.run([sys.executable, BENCH, "--gpus", "2"], capture_output=True, text=True, timeout=120, cwd=ROOT)
     assert r.returncode != 0
     assert "one GPU" in (r.stdout + r.stderr)
+
+
+def test_oracle_rows_on_samples():
+    # the per-line oracle timing of the bench runs on the host alone: every
+    # line it knows gets a positive rate and a stated sample
+    sys.path.insert(0, ROOT)
+    import bench
+    from paper_1604_04815_amd import workloads
+
+    keys = ["int64_add_2p27", "int32_max_2p28", "float32_add_2p27", "float32_add_2p27_compensated",
+            "bf16_add_2p27", "bf16_add_2p27_compensated", "segmented_4096_int32_add", "compact_int32_2p28_half",
+            "argmax_int32_2p28", "radix_offsets_int32_2p28_8bit", "custom_affine_2p27", "bfs_rmat22"]
+    configs = {k: {} for k in keys}
+    configs["serving"] = {}
+    bench.cpu_oracle_rows(workloads, configs)
+    for k in keys:
+        row = configs[k]["oracle_cpu"]
+        assert row["gelem_s"] > 0 and row["cores"] == 1 and row["sample"], k
+    assert "oracle_cpu" not in configs["serving"]

@@ -205,6 +205,9 @@ void init_params_locked()
     g_params[kModeBatched][kI32Add] = t512x8g2;
     g_params[kModeBatched][kF32Add] = t1024x4;
     g_params[kModeBatched][kI64Add] = t1024x4;  // 4096 arrays: 4.38 -> 4.60 TB/s
+    // max / min batches: 512 x 8 fits one group per CU there too (int32 max
+    // 4.75 -> 4.83 TB/s, int64 max 3.95 -> 4.37 at 1024 x 4)
+    for (int o : {kI32Max, kI32Min, kI64Max, kI64Min}) g_params[kModeBatched][o] = t1024x4;
     for (int m = 0; m < kNumModes; ++m)
         for (int o = 0; o < kNumOpCodes; ++o) g_default_params[m][o] = g_params[m][o];
     g_params_init = true;

@@ -207,7 +207,10 @@ void init_params_locked()
     g_params[kModeBatched][kI64Add] = t1024x4;  // 4096 arrays: 4.38 -> 4.60 TB/s
     // max / min batches: 512 x 8 fits one group per CU there too (int32 max
     // 4.75 -> 4.83 TB/s, int64 max 3.95 -> 4.37 at 1024 x 4)
-    for (int o : {kI32Max, kI32Min, kI64Max, kI64Min}) g_params[kModeBatched][o] = t1024x4;
+    for (int o : {kI32Max, kI32Min, kI64Max, kI64Min, kF32Max, kF32Min}) g_params[kModeBatched][o] = t1024x4;
+    // (float32 max 4.39 -> 4.75); bf16 max / min fit two 512 x 8 groups: 3.45 -> 3.87
+    g_params[kModeBatched][kBF16Max] = t512x8g2;
+    g_params[kModeBatched][kBF16Min] = t512x8g2;
     for (int m = 0; m < kNumModes; ++m)
         for (int o = 0; o < kNumOpCodes; ++o) g_default_params[m][o] = g_params[m][o];
     g_params_init = true;

@@ -56,6 +56,15 @@
  * Graph replays and the request server's launches are not part of this
  * order: do not run them on a device at the same time as other scans.
  *
+ * Graph capture: every call that enqueues device work, except
+ * lscan_graph_launch, refuses a stream that
+ * is being captured into a HIP graph (LSCAN_ERR_UNSUPPORTED, nothing
+ * enqueued).  A kernel captured from such a call would keep pointers into
+ * the stream's flag workspace, which a later call may free or regrow, and
+ * its replays would escape the host's count of flag epochs.  To replay
+ * scans, capture them with lscan_graph_create_*: those graphs own their
+ * workspace.
+ *
  * Besides the scans (plain, exclusive, segmented, batched, graph-captured,
  * served), the same persistent machinery gives: stream compaction
  * (lscan_compact), radix-sort digit offsets (lscan_radix_offsets),
@@ -421,7 +430,7 @@ lscan_status lscan_bfs_with_params(const int64_t *row_offsets,
  * replay; lscan_graph_destroy synchronizes the device and frees the graph.
  */
 typedef struct lscan_graph lscan_graph;
-/* One plain scan of n elements (Section 3): inclusive, or exclusive with
+/* One plain scan of n elements (Section 1): inclusive, or exclusive with
  * LSCAN_F_EXCLUSIVE in flags; the other flags, types, operators and pointer
  * rules are those of lscan_inclusive.  n == 0 (nothing to capture) is
  * LSCAN_ERR_INVALID_ARG. */

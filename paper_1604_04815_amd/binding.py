@@ -126,6 +126,12 @@ SIGNATURES = {
     "lscan_release_workspaces": ([], _i32),
     "lscan_status_string": ([_i32], ctypes.c_char_p),
     "lscan_last_device_error": ([], _i32),
+    # include/lscan_testing.h
+    "lscan_test_epoch_limit": ([], ctypes.c_uint64),
+    "lscan_test_seed_epoch": ([_vp, ctypes.c_uint64, _u32, _u32], _i32),
+    "lscan_test_graph_seed_epoch": ([_vp, ctypes.c_uint64, _u32, _u32], _i32),
+    "lscan_test_epoch_state": ([_vp, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(_u32)], _i32),
+    "lscan_test_graph_epoch_state": ([_vp, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(_u32)], _i32),
 }
 
 
@@ -301,6 +307,34 @@ def lscan_check(stream: int = 0) -> None:
 
 def lscan_release_workspaces() -> None:
     _check(load().lscan_release_workspaces(), "lscan_release_workspaces")
+
+
+def lscan_test_epoch_limit() -> int:
+    return int(load().lscan_test_epoch_limit())
+
+
+def lscan_test_seed_epoch(launches: int, tag: int, abort_tag: int = 0, stream=None,
+                          graph: Graph | None = None) -> None:
+    """Seed the flag workspace of a stream (or of a graph) near the epoch
+    reset (include/lscan_testing.h)."""
+    if graph is not None:
+        _check(load().lscan_test_graph_seed_epoch(graph.handle, launches, tag, abort_tag),
+               "lscan_test_graph_seed_epoch")
+    else:
+        _check(load().lscan_test_seed_epoch(_stream(stream), launches, tag, abort_tag), "lscan_test_seed_epoch")
+
+
+def lscan_test_epoch_state(stream=None, graph: Graph | None = None):
+    """(launch count, [ctrl0, ctrl1, ctrl2, ctrl3]) of a stream's or a
+    graph's flag workspace."""
+    n = ctypes.c_uint64()
+    ctrl = (ctypes.c_uint32 * 4)()
+    if graph is not None:
+        _check(load().lscan_test_graph_epoch_state(graph.handle, ctypes.byref(n), ctrl),
+               "lscan_test_graph_epoch_state")
+    else:
+        _check(load().lscan_test_epoch_state(_stream(stream), ctypes.byref(n), ctrl), "lscan_test_epoch_state")
+    return int(n.value), [int(c) for c in ctrl]
 
 
 # ---------------------------------------------------------------------------

@@ -198,10 +198,10 @@ __global__ void __launch_bounds__(TT) compact_kernel(ScanArgs a)
 #pragma unroll
                 for (int q = 0; q < FC::N; ++q)
                     *reinterpret_cast<typename FC::Word*>(sf + q * 64 * FC::C + lane * FC::C) = fw[q];
-                __builtin_amdgcn_wave_barrier();
+                wave_lds_sync();
 #pragma unroll
                 for (int r = 0; r < R; ++r) bits[r] = keep_bits<E>(sf + r * ROW + lane * E);
-                __builtin_amdgcn_wave_barrier();
+                wave_lds_sync();
             }
 #pragma unroll
             for (int r = 0; r < R; ++r) {
@@ -259,7 +259,7 @@ __global__ void __launch_bounds__(TT) compact_kernel(ScanArgs a)
                     if ((m >> k) & 1u) stage[at] = p_x[r][k];
                     at += int32_t((m >> k) & 1u);
                 }
-                __builtin_amdgcn_wave_barrier();
+                wave_lds_sync();
                 const int32_t span = shift + p_rowcnt[r];  // staged items occupy [shift, span)
                 T* dst = out + (g0 - shift);
                 for (int32_t c = lane * E; c < span; c += 64 * E) {
@@ -275,7 +275,7 @@ __global__ void __launch_bounds__(TT) compact_kernel(ScanArgs a)
                             if (c + k >= shift && c + k < span) dst[c + k] = stage[c + k];
                     }
                 }
-                __builtin_amdgcn_wave_barrier();
+                wave_lds_sync();
             }
         }
 

@@ -16,6 +16,7 @@
 #include "kernel_table.hpp"
 #include "radix_kernel.hpp"
 #include "lscan.h"
+#include "lscan_testing.h"
 #include "runtime_internal.hpp"
 
 namespace lscan {
@@ -108,6 +109,7 @@ struct Workspace {
     bool desc_pending = false;
     int64_t* seg_first = nullptr;      // segmented scans: first segment of every block
     size_t seg_cap = 0;
+    bool fixed = false;                // slots and ctrl live in memory the library never frees or grows
 };
 
 struct Params {
@@ -427,8 +429,8 @@ lscan_status device_info_locked(int dev, DeviceInfo** out)
 
 void free_workspace(Workspace& ws)
 {
-    if (ws.slots) (void)hipFree(ws.slots);
-    if (ws.ctrl) (void)hipFree(ws.ctrl);
+    if (ws.slots && !ws.fixed) (void)hipFree(ws.slots);
+    if (ws.ctrl && !ws.fixed) (void)hipFree(ws.ctrl);
     if (ws.desc) (void)hipFree(ws.desc);
     if (ws.desc_host) (void)hipHostFree(ws.desc_host);
     if (ws.desc_copied) (void)hipEventDestroy(ws.desc_copied);
@@ -462,6 +464,25 @@ lscan_status ensure_segment_table(Workspace& ws, hipStream_t stream, size_t entr
     return LSCAN_OK;
 }
 
+// Start a new epoch run on ws before its 32-bit tag could wrap: clear every
+// flag word, restart the tag (word 0) and the exit counter (word 1), and
+// forget the tag of the last launch that gave up (word 3), which a restarted
+// tag could otherwise meet again and read as its own abort.  The timeout
+// flag (word 2) is kept for the next check.  Stream-ordered after the
+// launches that used the old tags.  The eager path, graph replays and the
+// test hooks all reset through here.
+lscan_status reset_epoch(Workspace& ws, hipStream_t stream)
+{
+    if (capturing(stream)) return LSCAN_ERR_UNSUPPORTED;  // never a memset node in a caller's graph
+    hipError_t e = hipSuccess;
+    if (ws.slots && ws.words) e = hipMemsetAsync(ws.slots, 0, ws.words * sizeof(uint64_t), stream);
+    if (e == hipSuccess && ws.ctrl) e = hipMemsetAsync(ws.ctrl, 0, 2 * sizeof(uint32_t), stream);
+    if (e == hipSuccess && ws.ctrl) e = hipMemsetAsync(ws.ctrl + 3, 0, sizeof(uint32_t), stream);
+    if (e != hipSuccess) return device_error(e);
+    ws.launches = 0;
+    return LSCAN_OK;
+}
+
 // Make ws hold at least `words` flag words and `desc_entries` descriptors.
 lscan_status ensure_workspace(Workspace& ws, hipStream_t stream, size_t words, size_t desc_entries)
 {
@@ -471,6 +492,10 @@ lscan_status ensure_workspace(Workspace& ws, hipStream_t stream, size_t words, s
     const bool grow_desc = ws.desc_cap < desc_entries;
     if (!grow_slots && !grow_desc && !need_reset) return LSCAN_OK;
     if (capturing(stream)) return LSCAN_ERR_UNSUPPORTED;  // size the workspace with an eager call first
+    if (ws.fixed) {  // memory the library does not own: never grown or freed
+        if (grow_slots || grow_desc) return LSCAN_ERR_NO_MEMORY;
+        return reset_epoch(ws, stream);
+    }
     if (ws.slots || ws.ctrl || ws.desc) {
         e = hipStreamSynchronize(stream);
         if (e != hipSuccess) return device_error(e);
@@ -495,9 +520,6 @@ lscan_status ensure_workspace(Workspace& ws, hipStream_t stream, size_t words, s
             return device_error(e);
         }
         ws.words = alloc;
-    } else if (need_reset) {
-        e = hipMemsetAsync(ws.slots, 0, ws.words * sizeof(uint64_t), stream);
-        if (e != hipSuccess) return device_error(e);
     }
     if (!ws.ctrl) {
         e = hipMalloc(reinterpret_cast<void**>(&ws.ctrl), 64);
@@ -511,15 +533,11 @@ lscan_status ensure_workspace(Workspace& ws, hipStream_t stream, size_t words, s
             ws.ctrl = nullptr;
             return device_error(e);
         }
-    } else if (need_reset) {
-        // keep the timeout flag (word 2); restart the tag and the exit counter,
-        // and forget the tag of the last launch that gave up (word 3), which
-        // a restarted tag could otherwise meet again
-        e = hipMemsetAsync(ws.ctrl, 0, 2 * sizeof(uint32_t), stream);
-        if (e == hipSuccess) e = hipMemsetAsync(ws.ctrl + 3, 0, sizeof(uint32_t), stream);
-        if (e != hipSuccess) return device_error(e);
     }
-    if (need_reset) ws.launches = 0;
+    if (need_reset) {
+        const lscan_status st = reset_epoch(ws, stream);
+        if (st != LSCAN_OK) return st;
+    }
     if (grow_desc) {
         const size_t cap = std::max<size_t>(desc_entries, std::max<size_t>(ws.desc_cap * 2, 256));
         if (ws.desc) (void)hipFree(ws.desc);
@@ -818,13 +836,13 @@ lscan_status plan_locked(const Request& r, int dev, Workspace* ws_fixed, hipStre
 
 // Cross-stream ordering of one persistent launch on `stream` (see
 // DeviceOrder); *out receives the device's record, to be passed to
-// order_after_locked once the launch is enqueued.  Called with g_mu held.
+// order_after_locked once the launch is enqueued.  Called with g_mu held,
+// never on a capturing stream (both callers refuse capture first).
 lscan_status order_before_locked(int dev, hipStream_t stream, DeviceOrder** out)
 {
     DeviceOrder* order = &g_order[dev];
     hipError_t e = hipSuccess;
-    // (the capture query is made only on a stream switch: it is not free)
-    if (order->any && order->last != stream && !capturing(stream)) {  // before the co-residency test, too
+    if (order->any && order->last != stream) {  // before the co-residency test, too
         if (!order->multi) {
             if (!order->done) {
                 e = hipEventCreateWithFlags(&order->done, hipEventDisableTiming);
@@ -848,7 +866,7 @@ lscan_status order_before_locked(int dev, hipStream_t stream, DeviceOrder** out)
 
 lscan_status order_after_locked(DeviceOrder* order, hipStream_t stream)
 {
-    if (order && order->multi && !capturing(stream)) {
+    if (order && order->multi) {
         const hipError_t e = hipEventRecord(order->done, stream);
         if (e != hipSuccess) return device_error(e);
     }
@@ -859,6 +877,12 @@ lscan_status run(const Request& r, void* stream_ptr)
 {
     if (r.empty) return LSCAN_OK;
     hipStream_t stream = static_cast<hipStream_t>(stream_ptr);
+    // A captured kernel node would hold the per-stream workspace's raw
+    // pointers, which a later call may free (a larger workspace, or
+    // lscan_release_workspaces), and its replays would bypass the host's
+    // epoch count.  Captured scans go through lscan_graph_create_*, whose
+    // graphs own their workspace.
+    if (capturing(stream)) return LSCAN_ERR_UNSUPPORTED;
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return device_error(e);
@@ -1282,16 +1306,11 @@ lscan_status lscan_graph_launch(lscan_graph* g, void* stream_ptr)
 {
     if (!g || !g->exec) return LSCAN_ERR_INVALID_ARG;
     hipStream_t stream = static_cast<hipStream_t>(stream_ptr);
-    hipError_t e;
     if (g->ws.launches >= kMaxLaunchesPerEpochRun) {
-        if (capturing(stream)) return LSCAN_ERR_UNSUPPORTED;
-        e = hipMemsetAsync(g->ws.slots, 0, g->ws.words * sizeof(uint64_t), stream);
-        if (e != hipSuccess) return device_error(e);
-        e = hipMemsetAsync(g->ws.ctrl, 0, 2 * sizeof(uint32_t), stream);
-        if (e != hipSuccess) return device_error(e);
-        g->ws.launches = 0;
+        const lscan_status st = reset_epoch(g->ws, stream);
+        if (st != LSCAN_OK) return st;
     }
-    e = hipGraphLaunch(g->exec, stream);
+    const hipError_t e = hipGraphLaunch(g->exec, stream);
     if (e != hipSuccess) return device_error(e);
     g->ws.launches++;
     return LSCAN_OK;
@@ -1324,6 +1343,95 @@ lscan_status lscan_graph_destroy(lscan_graph* g)
     if (g->prep) (void)hipStreamDestroy(g->prep);
     delete g;
     return e == hipSuccess ? LSCAN_OK : device_error(e);
+}
+
+// ---------------------------------------------------------------------------
+// Test hooks (include/lscan_testing.h)
+// ---------------------------------------------------------------------------
+
+}  // extern "C"
+
+namespace {
+
+// Seed ws after the work that used it has finished: all flag words cleared,
+// the tag and launch count set, the exit counter zeroed.
+lscan_status seed_epoch(Workspace& ws, uint64_t launches, uint32_t tag, uint32_t abort_tag)
+{
+    if (!ws.ctrl || !ws.slots) return LSCAN_ERR_NOT_FOUND;
+    if (launches > kMaxLaunchesPerEpochRun) return LSCAN_ERR_INVALID_ARG;
+    if (uint64_t(tag) + (kMaxLaunchesPerEpochRun - launches) + 1 >= uint64_t(UINT32_MAX)) return LSCAN_ERR_INVALID_ARG;
+    hipError_t e = hipMemset(ws.slots, 0, ws.words * sizeof(uint64_t));
+    const uint32_t words[2] = {tag, 0u};
+    if (e == hipSuccess) e = hipMemcpy(ws.ctrl, words, sizeof(words), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(ws.ctrl + 3, &abort_tag, sizeof(abort_tag), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) return device_error(e);
+    ws.launches = launches;
+    return LSCAN_OK;
+}
+
+lscan_status epoch_state(const Workspace& ws, uint64_t* launches, uint32_t* ctrl)
+{
+    if (!launches || !ctrl) return LSCAN_ERR_INVALID_ARG;
+    if (!ws.ctrl) return LSCAN_ERR_NOT_FOUND;
+    const hipError_t e = hipMemcpy(ctrl, ws.ctrl, 4 * sizeof(uint32_t), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return device_error(e);
+    *launches = ws.launches;
+    return LSCAN_OK;
+}
+
+// The per-stream workspace of (current device, stream), after the stream
+// has drained; null if there is none.
+lscan_status stream_workspace_synced(void* stream_ptr, Workspace** out)
+{
+    hipStream_t stream = static_cast<hipStream_t>(stream_ptr);
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return device_error(e);
+    auto it = g_ws.find(std::make_pair(dev, stream));
+    *out = (it == g_ws.end()) ? nullptr : &it->second;
+    return LSCAN_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+uint64_t lscan_test_epoch_limit(void) { return kMaxLaunchesPerEpochRun; }
+
+lscan_status lscan_test_seed_epoch(void* stream, uint64_t launches, uint32_t tag, uint32_t abort_tag)
+{
+    std::lock_guard<std::mutex> lock(g_mu);
+    Workspace* ws = nullptr;
+    lscan_status st = stream_workspace_synced(stream, &ws);
+    if (st != LSCAN_OK) return st;
+    return ws ? seed_epoch(*ws, launches, tag, abort_tag) : LSCAN_ERR_NOT_FOUND;
+}
+
+lscan_status lscan_test_graph_seed_epoch(lscan_graph* g, uint64_t launches, uint32_t tag, uint32_t abort_tag)
+{
+    if (!g) return LSCAN_ERR_INVALID_ARG;
+    const hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return device_error(e);
+    return seed_epoch(g->ws, launches, tag, abort_tag);
+}
+
+lscan_status lscan_test_epoch_state(void* stream, uint64_t* launches, uint32_t ctrl[4])
+{
+    std::lock_guard<std::mutex> lock(g_mu);
+    Workspace* ws = nullptr;
+    lscan_status st = stream_workspace_synced(stream, &ws);
+    if (st != LSCAN_OK) return st;
+    return ws ? epoch_state(*ws, launches, ctrl) : LSCAN_ERR_NOT_FOUND;
+}
+
+lscan_status lscan_test_graph_epoch_state(lscan_graph* g, uint64_t* launches, uint32_t ctrl[4])
+{
+    if (!g) return LSCAN_ERR_INVALID_ARG;
+    const hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return device_error(e);
+    return epoch_state(g->ws, launches, ctrl);
 }
 
 int32_t lscan_num_tile_shapes(void) { return kNumShapes; }
@@ -1380,7 +1488,9 @@ lscan_status lscan_compact_with_params(const void* x, const uint8_t* keep, void*
     lscan_status st = make_compact_request(x, keep, out, count, n, dt, p, &r);
     if (st != LSCAN_OK) return st;
     if (r.empty) {  // nothing is launched: the count is zero
-        hipError_t e = hipMemsetAsync(count, 0, sizeof(int64_t), static_cast<hipStream_t>(stream));
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        if (capturing(s)) return LSCAN_ERR_UNSUPPORTED;  // no memset node in a caller's graph
+        hipError_t e = hipMemsetAsync(count, 0, sizeof(int64_t), s);
         return e == hipSuccess ? LSCAN_OK : device_error(e);
     }
     return run(r, stream);
@@ -1409,6 +1519,7 @@ lscan_status lscan_radix_offsets(const void* keys, int64_t n, lscan_dtype dt, in
     if (m > (INT64_MAX / 16) / digits) return LSCAN_ERR_INVALID_ARG;
     const int64_t total = digits * m;
     if (ranges_overlap(keys, n * kb, offsets, total * 8)) return LSCAN_ERR_INVALID_ARG;
+    if (capturing(static_cast<hipStream_t>(stream))) return LSCAN_ERR_UNSUPPORTED;  // as every eager scan
     RadixArgs a;
     a.keys = keys;
     a.n = n;
@@ -1449,6 +1560,7 @@ lscan_status lscan_bfs_with_params(const int64_t* row_offsets, const int32_t* co
     if (stats && mis(stats, 8)) return LSCAN_ERR_INVALID_ARG;
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (num_vertices == 0) {
+        if (capturing(s)) return LSCAN_ERR_UNSUPPORTED;  // no memset node in a caller's graph
         if (stats) {
             const hipError_t e = hipMemsetAsync(stats, 0, 4 * sizeof(int64_t), s);
             if (e != hipSuccess) return device_error(e);

@@ -86,6 +86,17 @@ __device__ __forceinline__ void store_vector(T* p, const T (&v)[E])
     for (int h = 0; h < kBytes / 16; ++h) __builtin_nontemporal_store(w[h], reinterpret_cast<u32x4*>(p) + h);
 }
 
+// Lanes of one wave exchange values through LDS: every lane's LDS writes
+// before this point are visible to every lane's reads after it.  The wave
+// barrier alone orders only the instructions; the wavefront-scope fences
+// order the memory accesses themselves.
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // ---------------------------------------------------------------------------
 // Flag slots: one 64-bit word per 32 bits of payload, (tag << 32) | data.
 // ---------------------------------------------------------------------------
@@ -652,7 +663,7 @@ __global__ void __launch_bounds__(T) scan_kernel(ScanArgs a)
                     const int32_t shift = int32_t((reinterpret_cast<uintptr_t>(row_y) % 16) / sizeof(Out));
 #pragma unroll
                     for (int k = 0; k < E; ++k) stage[shift + lane * E + k] = out[k];
-                    __builtin_amdgcn_wave_barrier();
+                    wave_lds_sync();  // lanes read what other lanes wrote
                     Out* dst = row_y - shift;
                     const int32_t span = shift + ROW;  // staged outputs occupy [shift, span)
                     for (int32_t c = lane * E; c < span; c += 64 * E) {
@@ -667,7 +678,7 @@ __global__ void __launch_bounds__(T) scan_kernel(ScanArgs a)
                                 if (c + k >= shift && c + k < span) dst[c + k] = stage[c + k];
                         }
                     }
-                    __builtin_amdgcn_wave_barrier();
+                    wave_lds_sync();  // the next row's stage writes come after every lane's reads
                 } else {
 #pragma unroll
                     for (int k = 0; k < E; ++k)

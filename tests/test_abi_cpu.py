@@ -2,6 +2,7 @@
 include/lscan.h declares, and rejects bad arguments before any device work
 (no GPU call is made by these tests)."""
 import ctypes
+import glob
 import os
 import re
 
@@ -11,12 +12,16 @@ from paper_1604_04815_amd import binding
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "lscan.h")
+HEADERS = sorted(glob.glob(os.path.join(ROOT, "include", "*.h")))
 
 
-def declared_symbols():
-    text = open(HEADER).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(lscan_[a-z_0-9]+)\s*\(", text)))
+def declared_symbols(headers=None):
+    syms = set()
+    for h in headers or HEADERS:
+        text = open(h).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        syms.update(re.findall(r"\b(lscan_[a-z_0-9]+)\s*\(", text))
+    return sorted(syms)
 
 
 @pytest.fixture(scope="module")
@@ -27,10 +32,12 @@ def lib():
 
 
 def test_header_declares_the_abi():
-    syms = declared_symbols()
+    syms = declared_symbols([HEADER])
     for name in ("lscan_inclusive", "lscan_exclusive", "lscan_segmented", "lscan_check",
                  "lscan_status_string"):
         assert name in syms
+    assert os.path.join(ROOT, "include", "lscan_testing.h") in HEADERS
+    assert "lscan_test_seed_epoch" in declared_symbols()
 
 
 def test_every_declared_symbol_is_exported(lib):
@@ -376,3 +383,13 @@ def test_index64_flag_validation(lib):
                                None) == binding.ERR_INVALID_ARG
     # an argmax with the flag and nothing to do is accepted
     assert f(None, None, 0, binding.I32, binding.ARGMAX, binding.F_INDEX64, None) == binding.OK
+
+
+def test_epoch_test_hooks_validation(lib):
+    # include/lscan_testing.h: the limit, and the null-graph checks made
+    # before any device call
+    assert lib.lscan_test_epoch_limit() == 0xFFFFFFF0
+    assert lib.lscan_test_graph_seed_epoch(None, 0, 0, 0) == binding.ERR_INVALID_ARG
+    n = ctypes.c_uint64()
+    ctrl = (ctypes.c_uint32 * 4)()
+    assert lib.lscan_test_graph_epoch_state(None, ctypes.byref(n), ctrl) == binding.ERR_INVALID_ARG

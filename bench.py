@@ -164,6 +164,38 @@ def rate_entry(nbytes: float, n: int, ms: float, per=None):
     return d
 
 
+def float_error(xd, y, offsets=None):
+    """max_j |y_j - y64_j| / A_j over the whole array, with y64 the exact
+    prefix sums in float64 and A_j = sum_{i<=j} |x_i| (the bound the float
+    tolerances are stated in), and the j where it is largest.  The float64
+    reference runs on the device (torch.cumsum in float64: its own error,
+    about log2(N) * 2^-53 * A_j, is far below the float32 tolerances).
+    Segmented scans restart the sums at every segment."""
+    import torch
+
+    xf = xd.float().double() if xd.dtype == torch.bfloat16 else xd.double()
+    if offsets is None:
+        ref = torch.cumsum(xf, 0)
+        a = torch.cumsum(xf.abs(), 0)
+    else:
+        ref = torch.empty_like(xf)
+        a = torch.empty_like(xf)
+        off = offsets.tolist()
+        for s in range(len(off) - 1):
+            lo, hi = off[s], off[s + 1]
+            if hi > lo:
+                torch.cumsum(xf[lo:hi], 0, out=ref[lo:hi])
+                torch.cumsum(xf[lo:hi].abs(), 0, out=a[lo:hi])
+    err = (y.double() - ref).abs()
+    ratio = torch.where(a > 0, err / a.clamp_min(1e-300), torch.where(err > 0, float("inf"), 0.0))
+    j = int(torch.argmax(ratio).item())
+    out = {"max_error_ratio": float(ratio[j].item()), "argmax": j,
+           "reference": "float64 prefix sums on the device", "bound": "|y_j - y64_j| / sum_{i<=j} |x_i|"}
+    del xf, ref, a, err, ratio
+    torch.cuda.empty_cache()
+    return out
+
+
 # ---------------------------------------------------------------------------
 # workloads
 # ---------------------------------------------------------------------------
@@ -193,21 +225,57 @@ def bench_plain(binding, x_host, dtype, op, comp, steps, warmup):
     entry.update({"n": n, "dtype": dtype, "op": op, "compensated": comp, "bytes": nbytes,
                   "grid": info.grid, "block_threads": info.block_threads, "tile_elems": info.tile_elems,
                   "num_blocks": info.num_blocks})
+    if op == "add" and dtype in ("float32", "bfloat16"):
+        entry["error"] = float_error(xd, y)
+        entry["error"]["tolerance"] = 2e-7 if comp else 1e-6
     del xd, y
     torch.cuda.empty_cache()
     return entry
 
 
-def bench_copy(n, steps, warmup):
+CEILING_LIB = os.path.join(ROOT, "paper_1604_04815_amd", "ceiling", "libcopy_ceiling.so")
+
+
+def bench_copy(n, steps, warmup, scan_shape=(256, 16, 2)):
+    """Copies of the headline's bytes (N int32 read, N written): the
+    practical ceiling of a kernel that touches every byte once.
+      persistent  the scan's structure without the hand-off: the scan's grid
+                  (groups per CU), tile (threads x vectors) and one-round
+                  load/store pipeline, the same 16-byte non-temporal vectors
+      flat        one 4 KiB tile per workgroup, hardware-dispatched grid
+      torch       torch's copy_ (the runtime's copy kernel)"""
+    import ctypes
+
     import torch
 
     a = torch.empty(n, dtype=torch.int32, device="cuda").fill_(1)
     b = torch.empty_like(a)
+    out = {}
+    lib = ctypes.CDLL(CEILING_LIB)
+    lib.ceiling_copy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_int,
+                                 ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.POINTER(ctypes.c_int)]
+    lib.ceiling_copy.restype = ctypes.c_int
+    grid = ctypes.c_int()
+    stream = torch.cuda.current_stream().cuda_stream
+    t, r, g = scan_shape
+    for name, structure, shape in (("persistent", 1, (t, r, g)), ("flat", 0, (256, 1, 0))):
+        def fn(structure=structure, shape=shape):
+            st = lib.ceiling_copy(a.data_ptr(), b.data_ptr(), 4 * n, structure, shape[0], shape[1], shape[2],
+                                  stream, ctypes.byref(grid))
+            if st != 0:
+                raise RuntimeError(f"ceiling_copy failed: {st}")
+        ms, per = time_steps(fn, steps, warmup)
+        e = rate_entry(2 * 4 * n, n, ms, per)
+        e.update({"structure": name, "block_threads": shape[0], "vectors_per_lane": shape[1], "grid": grid.value})
+        if structure == 1:
+            e["groups_per_cu"] = shape[2]
+        out[name] = e
+    assert torch.equal(a, b)
     ms, per = time_steps(lambda: b.copy_(a), steps, warmup)
-    e = rate_entry(2 * 4 * n, n, ms, per)
+    out["torch"] = rate_entry(2 * 4 * n, n, ms, per)
     del a, b
     torch.cuda.empty_cache()
-    return e
+    return out
 
 
 def bench_segmented(binding, workloads, steps, warmup):
@@ -247,6 +315,7 @@ def bench_segmented(binding, workloads, steps, warmup):
         g.check()
         g.destroy()
         graph_same = bool(torch.equal(seg_y, y))
+        err = float_error(xd, seg_y, od) if dtype == "float32" else None
         nbytes = n * 8
         e = rate_entry(nbytes, n, ms_seg, per)
         e.update({"n": n, "segments": 4096, "plain_4096_launches_ms": round(ms_plain, 4),
@@ -256,6 +325,9 @@ def bench_segmented(binding, workloads, steps, warmup):
                   "graph_bit_equal_to_eager": graph_same})
         if same is not None:
             e["bit_equal_to_plain_launches"] = same
+        if err is not None:
+            err["tolerance"] = 1e-6
+            e["error"] = err
         if dtype == "int32":
             # the same 4096 arrays as separate arrays of one batched launch
             # (cut at arbitrary element offsets: each array's own alignment
@@ -599,8 +671,14 @@ def bench_chain(binding, x_host, steps):
 
 
 def bench_serving(binding, workloads, seconds: float, rate: float):
-    """Poisson trace through the request server, and the same trace as
-    serial plain launches (one launch + synchronize per request, FIFO)."""
+    """Poisson trace through the request server (two streams, continuous
+    batching), and the same trace served one request at a time: a server
+    with one stream in which every request runs alone as a plain
+    full-device scan, launched when the previous one has completed (FIFO,
+    no overlap).  Both arms take their timestamps the same way: latency is
+    the server's completion time (its completion thread, after the batch's
+    event) minus the request's arrival time, both from the host's monotonic
+    clock."""
     import numpy as np
     import torch
 
@@ -612,6 +690,42 @@ def bench_serving(binding, workloads, seconds: float, rate: float):
     rng = np.random.default_rng(workloads.seed_for(4, 9))
     xs = [_pool_slice(pools, r, rng) for r in trace]
     out = {"requests": len(trace), "seconds": seconds, "rate_hz": rate, "bytes": total_bytes}
+    ops = {"add": binding.ADD, "max": binding.MAX}
+
+    def run_trace(srv, keep_for_check):
+        """Submit every request at its arrival time; returns per-request
+        latencies (ns), batch sizes, the last completion time, the first
+        arrival and the outputs kept for spot checks."""
+        torch.cuda.synchronize()
+        t0 = time.monotonic_ns() + 20_000_000
+        arrivals = [t0 + int(r["t"] * 1e9) for r in trace]
+        live = {}
+        lat, sizes, t_done_last = [], [], t0
+        kept = []
+        k = 0
+        while k < len(trace) or live:
+            now = time.monotonic_ns()
+            while k < len(trace) and arrivals[k] <= now:
+                r, x = trace[k], xs[k]
+                y = torch.empty(r["n"], dtype=x.dtype, device="cuda")
+                tk = srv.submit_raw(x.data_ptr(), y.data_ptr(), r["n"], binding.dtype_code(x), ops[r["op"]])
+                if tk < 0:
+                    raise RuntimeError(f"submit refused: {tk}")
+                live[tk] = (k, y)
+                k += 1
+            for tk in list(live):
+                st, res = srv.poll(tk)
+                if st == binding.PENDING:
+                    continue
+                if st != binding.OK:
+                    raise RuntimeError(f"request failed: {st}")
+                idx, y = live.pop(tk)
+                lat.append(res.t_done_ns - arrivals[idx])
+                sizes.append(res.batch_size)
+                t_done_last = max(t_done_last, res.t_done_ns)
+                if keep_for_check(idx):
+                    kept.append((idx, y))
+        return lat, sizes, t_done_last, arrivals[0], kept
 
     def summarize(lat_ns, t_first, t_last):
         lat = np.array(lat_ns, dtype=np.float64) / 1e3
@@ -620,40 +734,25 @@ def bench_serving(binding, workloads, seconds: float, rate: float):
                 "mean_us": round(float(lat.mean()), 1), "gbs": round(total_bytes / span / 1e9, 1),
                 "makespan_s": round(span, 3)}
 
-    # --- served
+    def size_hist(sizes):
+        """Requests by the size of the launch that carried them."""
+        buckets = [(1, 1), (2, 2), (3, 4), (5, 8), (9, 16), (17, 64), (65, 1 << 30)]
+        hist = {}
+        for lo, hi in buckets:
+            c = sum(1 for b in sizes if lo <= b <= hi)
+            if c:
+                hist[str(lo) if lo == hi else (f"{lo}-{hi}" if hi < (1 << 30) else f"{lo}+")] = c
+        return hist
+
+    # --- served: two streams, continuous batching
     srv = binding.Server(num_streams=2, hbm_budget_bytes=32 << 30)
-    t0 = time.monotonic_ns() + 20_000_000
-    arrivals = [t0 + int(r["t"] * 1e9) for r in trace]
-    live = {}
-    lat, t_done_last = [], t0
-    checks = []
-    k = 0
-    ops = {"add": binding.ADD, "max": binding.MAX}
-    while k < len(trace) or live:
-        now = time.monotonic_ns()
-        while k < len(trace) and arrivals[k] <= now:
-            r, x = trace[k], xs[k]
-            y = torch.empty(r["n"], dtype=x.dtype, device="cuda")
-            tk = srv.submit_raw(x.data_ptr(), y.data_ptr(), r["n"], binding.dtype_code(x), ops[r["op"]])
-            if tk < 0:
-                raise RuntimeError(f"submit refused: {tk}")
-            live[tk] = (k, y)
-            k += 1
-        for tk in list(live):
-            st, res = srv.poll(tk)
-            if st == binding.PENDING:
-                continue
-            if st != binding.OK:
-                raise RuntimeError(f"request failed: {st}")
-            idx, y = live.pop(tk)
-            lat.append(res.t_done_ns - arrivals[idx])
-            t_done_last = max(t_done_last, res.t_done_ns)
-            if idx % 997 == 0:
-                checks.append((idx, y))
+    lat, sizes, t_last, t_first, checks = run_trace(srv, lambda idx: idx % 997 == 0)
     stats = srv.stats()
     srv.close()
-    served = summarize(lat, arrivals[0], t_done_last)
-    served.update({"batches": int(stats.batches), "peak_bytes_in_flight": int(stats.peak_bytes_in_flight)})
+    served = summarize(lat, t_first, t_last)
+    served.update({"batches": int(stats.batches), "peak_bytes_in_flight": int(stats.peak_bytes_in_flight),
+                   "requests_by_batch_size": size_hist(sizes),
+                   "mean_batch_size_per_request": round(float(np.mean(sizes)), 3)})
     failed = []
     for idx, y in checks:
         alone = binding.inclusive(xs[idx], trace[idx]["op"])
@@ -671,22 +770,21 @@ def bench_serving(binding, workloads, seconds: float, rate: float):
     served["spot_check_failures"] = failed[:8]
     served["spot_checks"] = len(checks)
     out["served"] = served
+    del checks
 
-    # --- serial plain launches on the same trace
-    torch.cuda.synchronize()
-    t0 = time.monotonic_ns() + 20_000_000
-    arrivals = [t0 + int(r["t"] * 1e9) for r in trace]
-    lat = []
-    for k, (r, x) in enumerate(zip(trace, xs)):
-        while time.monotonic_ns() < arrivals[k]:
-            pass
-        y = torch.empty(r["n"], dtype=x.dtype, device="cuda")
-        binding.inclusive(x, r["op"], out=y)
-        torch.cuda.synchronize()
-        lat.append(time.monotonic_ns() - arrivals[k])
-    out["serial_plain"] = summarize(lat, arrivals[0], time.monotonic_ns())
+    # --- serial plain launches: one stream, every request alone on the
+    # full-device plain kernel, the next launched only after it completes
+    srv = binding.Server(num_streams=1, hbm_budget_bytes=32 << 30, max_batch=1, solo_bytes=1)
+    lat, sizes, t_last, t_first, _ = run_trace(srv, lambda idx: False)
+    stats = srv.stats()
+    srv.close()
+    serial = summarize(lat, t_first, t_last)
+    serial.update({"batches": int(stats.batches), "how": "request server, one stream, every request alone "
+                   "(full-device plain kernel), FIFO, no overlap"})
+    out["serial_plain"] = serial
     out["p99_speedup_vs_serial"] = round(out["serial_plain"]["p99_us"] / out["served"]["p99_us"], 2)
     out["p50_speedup_vs_serial"] = round(out["serial_plain"]["p50_us"] / out["served"]["p50_us"], 2)
+    out["clock"] = "both arms: server completion timestamp minus arrival, host monotonic clock"
     del pools, xs
     torch.cuda.empty_cache()
     return out
@@ -795,8 +893,8 @@ def main(argv=None) -> int:
                     "'bfs': only the breadth-first search line; 'custom': only the user-operator line")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
-    ap.add_argument("--serve-seconds", type=float, default=5.0,
-                    help="length of the Poisson request trace (the full trace is 60 s)")
+    ap.add_argument("--serve-seconds", type=float, default=60.0,
+                    help="length of the Poisson request trace (the workload's full trace: 60 s)")
     ap.add_argument("--serve-rate", type=float, default=2000.0)
     ap.add_argument("--serve-heavy-rate", type=float, default=20000.0,
                     help="a second, heavier trace where requests queue and batching pays")
@@ -844,8 +942,11 @@ def main(argv=None) -> int:
     log("headline: int32 add N=2^28")
     head = bench_plain(binding, x, "int32", "add", False, args.steps, args.warmup)
     log(f"  {head['gbs']} GB/s, {head['ms']} ms/step, grid {head['grid']} x {head['block_threads']}")
-    copy = bench_copy(n, args.steps, args.warmup)
-    log(f"  device copy of the same size: {copy['gbs']} GB/s")
+    copy = bench_copy(n, args.steps, args.warmup,
+                      (head["block_threads"], head["tile_elems"] // head["block_threads"] // 4,
+                       head["grid"] // dev.multi_processor_count))
+    log(f"  copies of the same bytes: persistent {copy['persistent']['gbs']} GB/s, flat {copy['flat']['gbs']} GB/s, "
+        f"torch {copy['torch']['gbs']} GB/s")
 
     configs = {"copy_int32_2p28": copy}
     if args.only != "1a":
@@ -967,7 +1068,9 @@ def main(argv=None) -> int:
         "frac_hbm_peak": round(achieved / HBM_PEAK_GBS, 4),
         "roofline": {"bound": "hbm", "achieved": round(kernel_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(kernel_gbs / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "algorithmic_bytes_per_launch": head["bytes"], "launch_ms_mean": head["launch_ms_mean"]},
+                     "algorithmic_bytes_per_launch": head["bytes"], "launch_ms_mean": head["launch_ms_mean"],
+                     "copy_ceiling": {k: copy[k]["gbs"] for k in ("persistent", "flat", "torch")},
+                     "frac_of_persistent_copy": round(achieved / copy["persistent"]["gbs"], 4)},
         "cpu_baseline": cpu,
         "settle_s": SETTLE_S,
         "step_ms_p50": head.get("ms_p50"),

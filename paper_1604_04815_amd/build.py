@@ -22,6 +22,10 @@ LIB = os.path.join(PKG, "liblscan.so")
 # into a library of its own (run through lscan_scan_custom).
 CUSTOM_SRC = os.path.join(PKG, "custom", "affine_scan.hip")
 CUSTOM_LIB = os.path.join(PKG, "custom", "libaffine_scan.so")
+# Streaming copies of the scan's structure (persistent cyclic) and of a flat
+# grid: the practical ceiling the benchmark measures beside the scan.
+CEILING_SRC = os.path.join(PKG, "ceiling", "copy_ceiling.hip")
+CEILING_LIB = os.path.join(PKG, "ceiling", "libcopy_ceiling.so")
 INCLUDE = os.path.join(ROOT, "include")
 
 ARCH = "gfx950"
@@ -65,16 +69,17 @@ def _link(objs: list[str], out: str) -> None:
 
 def build(jobs: int | None = None, verbose: bool = False) -> str:
     """Compile every unit and link the shared library (and the user-operator
-    example library); returns the main library's path."""
+    example and copy-ceiling libraries); returns the main library's path."""
     os.makedirs(BUILD, exist_ok=True)
     srcs = sources()
     jobs = jobs or min(16, os.cpu_count() or 4, len(srcs) + 1)
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
-        objs = list(ex.map(_compile, srcs + [CUSTOM_SRC]))
-    _link(objs[:-1], LIB)
-    _link(objs[-1:], CUSTOM_LIB)
+        objs = list(ex.map(_compile, srcs + [CUSTOM_SRC, CEILING_SRC]))
+    _link(objs[:-2], LIB)
+    _link(objs[-2:-1], CUSTOM_LIB)
+    _link(objs[-1:], CEILING_LIB)
     if verbose:
-        print(f"built {LIB} from {len(srcs)} units and {CUSTOM_LIB}", flush=True)
+        print(f"built {LIB} from {len(srcs)} units, {CUSTOM_LIB} and {CEILING_LIB}", flush=True)
     return LIB
 
 

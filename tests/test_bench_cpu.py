@@ -68,3 +68,25 @@ def test_oracle_rows_on_samples():
         row = configs[k]["oracle_cpu"]
         assert row["gelem_s"] > 0 and row["cores"] == 1 and row["sample"], k
     assert "oracle_cpu" not in configs["serving"]
+
+
+def test_float_error_ratio_by_hand():
+    # bench.float_error on host tensors: y = [1, 3, 2.5] against exact
+    # prefixes [1, 2, 2.5] of x = [1, 1, 0.5] -> errors [0, 1, 0] over
+    # A = [1, 2, 2.5]: ratio 0.5 at j = 1; segmented with offsets [0, 1, 3]:
+    # second segment prefixes [1, 1.5], y[1:] = [1, 2] -> ratio 0.5/1.5 at 2
+    import torch
+
+    sys.path.insert(0, ROOT)
+    import bench
+
+    x = torch.tensor([1.0, 1.0, 0.5], dtype=torch.float32)
+    r = bench.float_error(x, torch.tensor([1.0, 3.0, 2.5]))
+    assert r["argmax"] == 1 and abs(r["max_error_ratio"] - 0.5) < 1e-12
+    r = bench.float_error(x, torch.tensor([1.0, 1.0, 2.0]), torch.tensor([0, 1, 3]))
+    assert r["argmax"] == 2 and abs(r["max_error_ratio"] - 0.5 / 1.5) < 1e-12
+    r = bench.float_error(x, torch.tensor([1.0, 2.0, 2.5]))
+    assert r["max_error_ratio"] == 0.0
+    # a zero prefix sum of magnitudes admits only an exact zero
+    z = torch.tensor([0.0, 0.0], dtype=torch.float32)
+    assert bench.float_error(z, torch.tensor([0.0, 1e-30]))["max_error_ratio"] == float("inf")

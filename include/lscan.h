@@ -152,6 +152,33 @@ lscan_status lscan_exclusive(const void *x, void *y, int64_t n, lscan_dtype dt,
                              lscan_op op, uint32_t flags, void *stream);
 
 /*
+ * lscan_inclusive_noalloc -- lscan_inclusive for callers that cannot
+ * allocate device memory (tight serving loops, harnesses that forbid
+ * hipMalloc): same arguments, same kernels, same results bit for bit, but
+ * no allocation of any kind.  The flag words live in a static device array
+ * of the library (4 MiB of flag slots plus 256 bytes of control words, held
+ * by every GPU the library runs on until the process ends); the first call
+ * on a device looks up that device's copy and clears it, the first call of
+ * each kernel shape runs its co-residency test once on the same words.
+ *   Limit: the blocks of the scan (n / tile size, the tile of the kernel the
+ *   call selects) times its flag words per block must fit the 2^19 slots:
+ *   add / max / min scans of any type up to about 2^33 elements, running
+ *   argmax / argmin up to about 1.4e9.  Larger n: LSCAN_ERR_NO_MEMORY,
+ *   decided on the host before any device work.
+ *   Sharing: every call on one GPU uses that GPU's one array, and it keeps
+ *   the last call's contents (flag words carry launch tags, so they need no
+ *   clearing between calls).  Calls that overlap on one GPU -- on two
+ *   streams or threads at once, or at the same time as any other scan of
+ *   this library -- race on those words and may deadlock; order them.  A
+ *   stream being captured is refused (LSCAN_ERR_UNSUPPORTED), as for
+ *   lscan_inclusive.  A timed-out launch is reported by the next
+ *   lscan_check on any stream of the device.
+ */
+lscan_status lscan_inclusive_noalloc(const void *x, void *y, int64_t n,
+                                     lscan_dtype dt, lscan_op op,
+                                     uint32_t flags, void *stream);
+
+/*
  * lscan_segmented -- the scan of Section 1 applied independently to each
  * segment x[offsets[s], offsets[s+1]), s < num_segments, in ONE persistent
  * launch (the segmented operator on (head flag, value) pairs, which is

@@ -86,6 +86,7 @@ _vp, _i64, _i32, _u32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.
 SIGNATURES = {
     "lscan_inclusive": ([_vp, _vp, _i64, _i32, _i32, _u32, _vp], _i32),
     "lscan_exclusive": ([_vp, _vp, _i64, _i32, _i32, _u32, _vp], _i32),
+    "lscan_inclusive_noalloc": ([_vp, _vp, _i64, _i32, _i32, _u32, _vp], _i32),
     "lscan_segmented": ([_vp, _vp, _i64, _vp, _i64, _i32, _i32, _u32, _vp], _i32),
     "lscan_num_tile_shapes": ([], _i32),
     "lscan_tile_shape": ([_i32, ctypes.POINTER(Params)], _i32),
@@ -181,6 +182,10 @@ def lscan_inclusive(x: int, y: int, n: int, dt: int, op: int, flags: int = 0, st
 
 def lscan_exclusive(x: int, y: int, n: int, dt: int, op: int, flags: int = 0, stream: int = 0) -> int:
     return _check(load().lscan_exclusive(x, y, n, dt, op, flags, stream), "lscan_exclusive")
+
+
+def lscan_inclusive_noalloc(x: int, y: int, n: int, dt: int, op: int, flags: int = 0, stream: int = 0) -> int:
+    return _check(load().lscan_inclusive_noalloc(x, y, n, dt, op, flags, stream), "lscan_inclusive_noalloc")
 
 
 def lscan_segmented(x: int, y: int, n_total: int, offsets: int, num_segments: int, dt: int, op: int,

@@ -662,8 +662,11 @@ int64_t batch_blocks(const KernelEntry& k, const lscan_array& arr, int64_t L)
 // if this shape is new, upload batched descriptors, and fill the kernel
 // arguments.  Called with g_mu held.  ws_fixed is a workspace owned by a
 // graph, or null for the per-stream one.
-lscan_status plan_locked(const Request& r, int dev, Workspace* ws_fixed, hipStream_t stream, Plan* plan,
-                         Workspace** ws_used)
+// The parameters a request runs with: the caller's, else the operator's;
+// plain add / max / min scans of small arrays take the small-array tiles
+// while the operator's parameters are the library's own.  Host data only
+// (no HIP call).  Called with g_mu held.
+Params choose_params_locked(const Request& r)
 {
     init_params_locked();
     Params prm = r.custom ? Params{0, kCustomGroupsPerCu, LSCAN_HANDOFF_WINDOW} : g_params[r.mode][r.oc];
@@ -681,6 +684,13 @@ lscan_status plan_locked(const Request& r, int dev, Workspace* ws_fixed, hipStre
         prm.shape = shape_index(r.p->block_threads, r.p->vectors_per_lane);
     if (r.p && r.p->groups_per_cu > 0) prm.groups_per_cu = r.p->groups_per_cu;
     if (r.p) prm.handoff = r.p->handoff;
+    return prm;
+}
+
+lscan_status plan_locked(const Request& r, int dev, Workspace* ws_fixed, hipStream_t stream, Plan* plan,
+                         Workspace** ws_used)
+{
+    const Params prm = choose_params_locked(r);
     const KernelEntry& k = r.custom ? *r.custom : table()[r.mode][r.oc][prm.shape];
     if (!k.func) return LSCAN_ERR_UNSUPPORTED;  // no kernel of this kind for the operator
 
@@ -873,6 +883,63 @@ lscan_status order_after_locked(DeviceOrder* order, hipStream_t stream)
     return LSCAN_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Flag memory that needs no allocation (lscan_inclusive_noalloc)
+// ---------------------------------------------------------------------------
+
+// Control words (the first 256 bytes) and flag slots of the scans that
+// lscan_inclusive_noalloc launches.  Every GPU holds its own copy of this
+// array for as long as the library is loaded.  In host code `scratch` names
+// only a host-side stand-in: its device address on a device comes from
+// hipGetSymbolAddress with that device current, and only that address is
+// ever handed to HIP (kernel arguments, memsets, copies).
+constexpr size_t kNoAllocCtrlWords = 32;               // 256 bytes; the kernels use 7 32-bit words
+constexpr size_t kNoAllocSlotWords = size_t(1) << 19;  // 4 MiB of 64-bit flag words
+static __device__ __align__(256) uint64_t scratch[kNoAllocCtrlWords + kNoAllocSlotWords];
+
+constexpr int kMaxNoAllocDevices = 64;
+// The fixed workspace of each device, set up by its first call (scratch
+// address, cleared once); null until then.
+Workspace g_noalloc_ws[kMaxNoAllocDevices];
+bool g_noalloc_ready[kMaxNoAllocDevices] = {};
+
+// Set up the fixed workspace of device `dev` (current) on its first call:
+// look up this device's copy of `scratch` and clear it on the stream.  The
+// stream is not capturing (the caller checked).  Called with g_mu held.
+lscan_status noalloc_workspace_locked(int dev, hipStream_t stream, Workspace** out)
+{
+    if (dev < 0 || dev >= kMaxNoAllocDevices) return LSCAN_ERR_UNSUPPORTED;
+    Workspace& ws = g_noalloc_ws[dev];
+    if (!g_noalloc_ready[dev]) {
+        void* ptr = nullptr;
+        hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) return device_error(e != hipSuccess ? e : hipErrorInvalidSymbol);
+        e = hipMemsetAsync(ptr, 0, sizeof(scratch), stream);
+        if (e != hipSuccess) return device_error(e);
+        ws = Workspace();
+        ws.fixed = true;
+        ws.ctrl = static_cast<uint32_t*>(ptr);
+        ws.slots = static_cast<uint64_t*>(ptr) + kNoAllocCtrlWords;
+        ws.words = kNoAllocSlotWords;
+        g_noalloc_ready[dev] = true;
+    }
+    *out = &ws;
+    return LSCAN_OK;
+}
+
+// Whether the flag words of request r fit the fixed workspace, decided from
+// host data before any device work: M blocks of the kernel r would run
+// (counting the largest alignment shift of the block grid) times its flag
+// words per block.  Called with g_mu held.
+bool noalloc_fits_locked(const Request& r)
+{
+    const Params prm = choose_params_locked(r);
+    const KernelEntry& k = table()[r.mode][r.oc][prm.shape];
+    if (!k.func) return true;  // refused later as unsupported
+    const int64_t M = (r.n + k.elems_per_vec + k.tile_elems - 1) / k.tile_elems;
+    return uint64_t(M) * uint64_t(k.slot_words) <= kNoAllocSlotWords;
+}
+
 lscan_status run(const Request& r, void* stream_ptr)
 {
     if (r.empty) return LSCAN_OK;
@@ -905,6 +972,34 @@ lscan_status run(const Request& r, void* stream_ptr)
     if (e != hipSuccess) return device_error(e);
     ws->launches++;
     return order_after_locked(order, stream);
+}
+
+// One plain scan on the device's fixed workspace: no allocation of any kind
+// on the device (the co-residency test of a new shape runs once, eagerly, on
+// the same fixed words).  Not ordered after other streams' scans.
+lscan_status run_noalloc(const Request& r, void* stream_ptr)
+{
+    if (r.empty) return LSCAN_OK;
+    hipStream_t stream = static_cast<hipStream_t>(stream_ptr);
+    {
+        std::lock_guard<std::mutex> lock(g_mu);
+        if (!noalloc_fits_locked(r)) return LSCAN_ERR_NO_MEMORY;
+    }
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return device_error(e);
+    if (capturing(stream)) return LSCAN_ERR_UNSUPPORTED;
+    std::lock_guard<std::mutex> lock(g_mu);
+    Workspace* ws = nullptr;
+    lscan_status st = noalloc_workspace_locked(dev, stream, &ws);
+    if (st != LSCAN_OK) return st;
+    Plan plan;
+    st = plan_locked(r, dev, ws, stream, &plan, nullptr);
+    if (st != LSCAN_OK) return st;
+    e = plan.k->launch(plan.a, plan.grid, stream);
+    if (e != hipSuccess) return device_error(e);
+    ws->launches++;
+    return LSCAN_OK;
 }
 
 // ---------------------------------------------------------------------------
@@ -1226,6 +1321,14 @@ lscan_status lscan_exclusive(const void* x, void* y, int64_t n, lscan_dtype dt, 
     Request r;
     lscan_status st = make_request(kModePlain, x, y, n, nullptr, 0, nullptr, 0, dt, op, flags, true, nullptr, &r);
     return st != LSCAN_OK ? st : run(r, stream);
+}
+
+lscan_status lscan_inclusive_noalloc(const void* x, void* y, int64_t n, lscan_dtype dt, lscan_op op,
+                                     uint32_t flags, void* stream)
+{
+    Request r;
+    lscan_status st = make_request(kModePlain, x, y, n, nullptr, 0, nullptr, 0, dt, op, flags, false, nullptr, &r);
+    return st != LSCAN_OK ? st : run_noalloc(r, stream);
 }
 
 lscan_status lscan_segmented(const void* x, void* y, int64_t n_total, const int64_t* offsets,
@@ -1657,23 +1760,29 @@ lscan_status lscan_check(void* stream_ptr)
     if (e != hipSuccess) return device_error(e);
     e = hipStreamSynchronize(stream);
     if (e != hipSuccess) return device_error(e);
-    uint32_t* ctrl = nullptr;
+    // the stream's workspace, and the device's fixed one (shared by every
+    // stream) once lscan_inclusive_noalloc has set it up
+    uint32_t* ctrls[2] = {nullptr, nullptr};
     {
         std::lock_guard<std::mutex> lock(g_mu);
         auto it = g_ws.find(std::make_pair(dev, stream));
-        if (it == g_ws.end() || !it->second.ctrl) return LSCAN_OK;
-        ctrl = it->second.ctrl;
+        if (it != g_ws.end()) ctrls[0] = it->second.ctrl;
+        if (dev >= 0 && dev < kMaxNoAllocDevices && g_noalloc_ready[dev]) ctrls[1] = g_noalloc_ws[dev].ctrl;
     }
-    uint32_t flag = 0;
-    e = hipMemcpy(&flag, ctrl + 2, sizeof(flag), hipMemcpyDeviceToHost);
-    if (e != hipSuccess) return device_error(e);
-    if (flag) {
-        const uint32_t zero = 0;
-        e = hipMemcpy(ctrl + 2, &zero, sizeof(zero), hipMemcpyHostToDevice);
+    bool timed_out = false;
+    for (uint32_t* ctrl : ctrls) {
+        if (!ctrl) continue;
+        uint32_t flag = 0;
+        e = hipMemcpy(&flag, ctrl + 2, sizeof(flag), hipMemcpyDeviceToHost);
         if (e != hipSuccess) return device_error(e);
-        return LSCAN_ERR_TIMEOUT;
+        if (flag) {
+            const uint32_t zero = 0;
+            e = hipMemcpy(ctrl + 2, &zero, sizeof(zero), hipMemcpyHostToDevice);
+            if (e != hipSuccess) return device_error(e);
+            timed_out = true;
+        }
     }
-    return LSCAN_OK;
+    return timed_out ? LSCAN_ERR_TIMEOUT : LSCAN_OK;
 }
 
 lscan_status lscan_release_workspaces(void)

@@ -393,3 +393,16 @@ def test_epoch_test_hooks_validation(lib):
     n = ctypes.c_uint64()
     ctrl = (ctypes.c_uint32 * 4)()
     assert lib.lscan_test_graph_epoch_state(None, ctypes.byref(n), ctrl) == binding.ERR_INVALID_ARG
+
+
+def test_noalloc_size_limit_before_device_work(lib):
+    # lscan_inclusive_noalloc refuses scans whose flag words would not fit
+    # its static array, from host data alone (these pointers are never read)
+    x, y = 0x1000_0000_0000, 0x3000_0000_0000
+    assert lib.lscan_inclusive_noalloc(x, y, 1 << 34, binding.I32, binding.ADD, 0, None) == binding.ERR_NO_MEMORY
+    assert lib.lscan_inclusive_noalloc(x, y, 1 << 31, binding.I32, binding.ARGMAX, 0, None) == binding.ERR_NO_MEMORY
+    # argument checks come first, as for lscan_inclusive
+    assert lib.lscan_inclusive_noalloc(x, y, -1, binding.I32, binding.ADD, 0, None) == binding.ERR_INVALID_ARG
+    assert lib.lscan_inclusive_noalloc(x, y, 4, binding.I32, binding.MAX, binding.F_COMPENSATED, None) == \
+        binding.ERR_UNSUPPORTED
+    assert lib.lscan_inclusive_noalloc(None, None, 0, binding.I32, binding.ADD, 0, None) == binding.OK

@@ -889,7 +889,10 @@ def main(argv=None) -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--only", default="", help="'1a': only the headline scan and a same-size copy; 'serve': only the serving trace; "
+    ap.add_argument("--only", default="", help="'1a': only the headline scan and the copies of its bytes; a comma "
+                    "list of lines (int64_add_2p27, int32_max_2p28, float32_add_2p27[_compensated], "
+                    "bf16_add_2p27[_compensated], segmented, serving, latency, compact, argmax, radix, bfs, custom, "
+                    "chain, torch_cumsum): the headline plus those; 'serve': only the serving trace; "
                     "'bfs': only the breadth-first search line; 'custom': only the user-operator line")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
@@ -949,49 +952,66 @@ def main(argv=None) -> int:
         f"torch {copy['torch']['gbs']} GB/s")
 
     configs = {"copy_int32_2p28": copy}
-    if args.only != "1a":
+    only = set(args.only.split(",")) - {""} if args.only not in ("1a",) else set()
+
+    def want(line):
+        """Every line unless --only names lines (the headline always runs)."""
+        if args.only == "1a":
+            return False
+        return not only or line in only
+
+    if want("int64_add_2p27"):
         log("int64 add N=2^27")
         configs["int64_add_2p27"] = bench_plain(
             binding, workloads.int64_half_open(1 << 27, -(2 ** 31), 2 ** 31, workloads.seed_for(1, 1)),
             "int64", "add", False, args.steps, args.warmup)
+    if want("int32_max_2p28"):
         log("int32 max N=2^28")
         configs["int32_max_2p28"] = bench_plain(
             binding, workloads.full_range_int32(1 << 28, workloads.seed_for(1, 2)),
             "int32", "max", False, args.steps, args.warmup)
+    if want("float32_add_2p27") or want("float32_add_2p27_compensated"):
         xf = workloads.signed_lognormal_f32(1 << 27, workloads.seed_for(2))
         for comp in (False, True):
-            log(f"float32 add N=2^27 compensated={comp}")
-            configs[f"float32_add_2p27{'_compensated' if comp else ''}"] = bench_plain(
-                binding, xf, "float32", "add", comp, args.steps, args.warmup)
+            key = f"float32_add_2p27{'_compensated' if comp else ''}"
+            if want(key):
+                log(f"float32 add N=2^27 compensated={comp}")
+                configs[key] = bench_plain(binding, xf, "float32", "add", comp, args.steps, args.warmup)
         del xf
+    if want("bf16_add_2p27") or want("bf16_add_2p27_compensated"):
         xb = workloads.bf16_unit(1 << 27, workloads.seed_for(2, 1))
         for comp in (False, True):
-            log(f"bf16 -> float32 add N=2^27 compensated={comp}")
-            configs[f"bf16_add_2p27{'_compensated' if comp else ''}"] = bench_plain(
-                binding, xb, "bfloat16", "add", comp, args.steps, args.warmup)
+            key = f"bf16_add_2p27{'_compensated' if comp else ''}"
+            if want(key):
+                log(f"bf16 -> float32 add N=2^27 compensated={comp}")
+                configs[key] = bench_plain(binding, xb, "bfloat16", "add", comp, args.steps, args.warmup)
         del xb
+    if want("segmented"):
         log("segmented: 4096 arrays")
         configs.update(bench_segmented(binding, workloads, args.steps, args.warmup))
-        if args.serve_seconds > 0:
-            log(f"serving: Poisson {args.serve_rate:.0f} req/s for {args.serve_seconds:.0f} s")
-            configs["serving"] = bench_serving(binding, workloads, args.serve_seconds, args.serve_rate)
-            sv = configs["serving"]
-            log(f"  served p50/p99 {sv['served']['p50_us']}/{sv['served']['p99_us']} us, serial "
-                f"{sv['serial_plain']['p50_us']}/{sv['serial_plain']['p99_us']} us")
-            if args.serve_heavy_seconds > 0:
-                log(f"serving: Poisson {args.serve_heavy_rate:.0f} req/s for {args.serve_heavy_seconds:.0f} s")
-                configs["serving_heavy"] = bench_serving(binding, workloads, args.serve_heavy_seconds,
-                                                         args.serve_heavy_rate)
-                hv = configs["serving_heavy"]
-                log(f"  served p50/p99 {hv['served']['p50_us']}/{hv['served']['p99_us']} us, serial "
-                    f"{hv['serial_plain']['p50_us']}/{hv['serial_plain']['p99_us']} us")
+    if args.serve_seconds > 0 and want("serving"):
+        log(f"serving: Poisson {args.serve_rate:.0f} req/s for {args.serve_seconds:.0f} s")
+        configs["serving"] = bench_serving(binding, workloads, args.serve_seconds, args.serve_rate)
+        sv = configs["serving"]
+        log(f"  served p50/p99 {sv['served']['p50_us']}/{sv['served']['p99_us']} us, serial "
+            f"{sv['serial_plain']['p50_us']}/{sv['serial_plain']['p99_us']} us")
+        if args.serve_heavy_seconds > 0:
+            log(f"serving: Poisson {args.serve_heavy_rate:.0f} req/s for {args.serve_heavy_seconds:.0f} s")
+            configs["serving_heavy"] = bench_serving(binding, workloads, args.serve_heavy_seconds,
+                                                     args.serve_heavy_rate)
+            hv = configs["serving_heavy"]
+            log(f"  served p50/p99 {hv['served']['p50_us']}/{hv['served']['p99_us']} us, serial "
+                f"{hv['serial_plain']['p50_us']}/{hv['serial_plain']['p99_us']} us")
+    if want("latency"):
         log("latency: int32 add N=2^20")
         configs["int32_add_2p20_latency"] = bench_latency(binding, workloads, args.steps)
+    if want("compact"):
         log("stream compaction: int32 N=2^28, half kept")
         configs["compact_int32_2p28_half"] = bench_compact(binding, x, args.steps, args.warmup,
                                                            workloads.seed_for(5, 1))
         log(f"  {configs['compact_int32_2p28_half']['gbs']} GB/s, "
             f"{configs['compact_int32_2p28_half']['speedup_vs_torch_masked_select']}x torch.masked_select")
+    if want("argmax"):
         log("running argmax: int32 N=2^28 (int64 indices)")
         xa = to_device(workloads.full_range_int32(1 << 28, workloads.seed_for(7)), "int32")
         ya = torch.empty(1 << 28, dtype=torch.int64, device="cuda")
@@ -1005,23 +1025,28 @@ def main(argv=None) -> int:
         del xa, ya
         torch.cuda.empty_cache()
         log(f"  {configs['argmax_int32_2p28']['gbs']} GB/s")
+    if want("radix"):
         log("radix-sort digit offsets: 2^28 int32 keys, 8 bits, 16K-key blocks")
         configs["radix_offsets_int32_2p28_8bit"] = bench_radix(binding, workloads, args.steps, args.warmup)
         log(f"  {configs['radix_offsets_int32_2p28_8bit']['key_gbs']} GB/s of keys")
+    if want("bfs"):
         log("breadth-first search: R-MAT 2^22 vertices, edge factor 16, 8 sources")
         configs["bfs_rmat22"] = bench_bfs(binding, workloads, max(3, args.steps // 2), 1)
         bf = configs["bfs_rmat22"]
         log(f"  {bf['gteps_scanned_hmean']} G edges scanned/s (harmonic mean), median {bf['ms_median']} ms, "
             f"valid={bf['all_valid']}")
+    if want("custom"):
         log("user-defined operator: affine maps mod 2^32, 2^27 maps")
         configs["custom_affine_2p27"] = bench_custom_affine(binding, args.steps, args.warmup)
         log(f"  {configs['custom_affine_2p27']['gbs']} GB/s ({configs['custom_affine_2p27']['best_shape']})")
+    if want("chain"):
         log("the paper's prefix chain: int32 add N=2^20 and N=2^28")
         configs["int32_add_2p20_chain"] = bench_chain(
             binding, workloads.uniform_int(1 << 20, -1000, 1000, workloads.seed_for(0)), 10)
         configs["int32_add_2p28_chain"] = bench_chain(binding, x, 3)
         log(f"  chain {configs['int32_add_2p28_chain']['gbs']} GB/s, "
             f"{configs['int32_add_2p28_chain']['us_per_handoff']} us per hand-off")
+    if want("torch_cumsum"):
         try:
             xd = to_device(x, "int32")
             yd = torch.empty_like(xd)

@@ -163,6 +163,36 @@ def test_unaligned_pointers(gpu_lib):
                         compare(to_host(y), x[xo:xo + n], dtype, op, excl, what=what)
 
 
+def test_unaligned_compensated(gpu_lib):
+    # the compensated sums run lane-major (rows pass through LDS so that each
+    # lane scans consecutive elements): full blocks at a shifted grid, output
+    # at another phase than the input (staged row stores), partial blocks
+    # (lane-major element loads and stores), in place, both forms
+    for dtype in ("float32", "bfloat16"):
+        in_el, out_el, vec_in = (2, 4, 8) if dtype == "bfloat16" else (4, 4, 16)
+        for n in (2_000_003, 70_001, 5):
+            for xo, yo in ((0, 0), (1, 1), (3, 3), (1, 2), (2, 0)):
+                x = make_input(dtype, "add", n + 4, seed=19 + xo + n % 7)
+                base = to_device(x, dtype)
+                xd = base[xo:xo + n]
+                y_base = torch.empty(n + 4, dtype=torch.float32, device="cuda")
+                for excl in (False, True):
+                    fn = gpu_lib.exclusive if excl else gpu_lib.inclusive
+                    y = fn(xd, "add", True, out=y_base[yo:yo + n])
+                    gpu_lib.lscan_check(torch.cuda.current_stream().cuda_stream)
+                    info = gpu_lib.lscan_last_launch()
+                    same_phase = ((xo * in_el) % vec_in) // in_el * out_el % 16 == (yo * out_el) % 16
+                    assert info.vector_path == (1 if same_phase else 2), (dtype, xo, yo, info.vector_path)
+                    compare(to_host(y), x[xo:xo + n], dtype, "add", excl, True,
+                            what=f"unaligned compensated {dtype} n={n} x+{xo} y+{yo} excl={excl}")
+    for n in (3_000_017, 4099):
+        x = make_input("float32", "add", n, seed=23)
+        xd = to_device(x, "float32")
+        gpu_lib.inclusive(xd, "add", True, out=xd)
+        gpu_lib.lscan_check(torch.cuda.current_stream().cuda_stream)
+        compare(to_host(xd), x, "float32", "add", False, True, what=f"in-place compensated n={n}")
+
+
 def test_repeated_launches_reuse_flags(gpu_lib):
     # flag slots are never cleared between launches (epoch tags): many
     # launches of varying sizes on one stream must all be right

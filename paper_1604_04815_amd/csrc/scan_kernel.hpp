@@ -98,6 +98,30 @@ __device__ __forceinline__ void wave_lds_sync()
 }
 
 // ---------------------------------------------------------------------------
+// Next-block prefetch into LDS.  gfx950 loads 16 bytes per lane from global
+// memory straight into LDS (lane l's bytes land at M0 + 16 * l), with no
+// register held while the load is in flight.  The load is issued from inline
+// assembly so that the compiler, which does not track which LDS bytes such a
+// load writes, does not wait for it before every later LDS read; the kernel
+// places the waits itself: all vector memory operations drained (vmcnt(0))
+// before the prefetched rows are read, and the reads completed (lgkmcnt(0))
+// before the next prefetch overwrites them.  No VGPR is written by the load,
+// and the address registers are read when it issues.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t lds_address(const void* p)
+{
+    return static_cast<uint32_t>(reinterpret_cast<uintptr_t>((const __attribute__((address_space(3))) char*)p));
+}
+__device__ __forceinline__ void lds_load16(const void* g, uint32_t lds_byte)
+{
+    const uint32_t m0 = __builtin_amdgcn_readfirstlane(lds_byte);
+    asm volatile("s_mov_b32 m0, %1\n\tglobal_load_lds_dwordx4 %0, off nt" ::"v"(g), "s"(m0) : "memory");
+}
+
+__device__ __forceinline__ void vmem_drain() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+__device__ __forceinline__ void lds_reads_drain() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
+
+// ---------------------------------------------------------------------------
 // Flag slots: one 64-bit word per 32 bits of payload, (tag << 32) | data.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ uint64_t slot_load(const uint64_t* p)
@@ -315,6 +339,15 @@ __global__ void __launch_bounds__(T) scan_kernel(ScanArgs a)
     // x: each wave stages one output row here to write it as aligned vectors
     constexpr bool kStageY = (MODE == kModePlain || MODE == kModeSegmented) && E * sizeof(Out) == 16;
     __shared__ __attribute__((aligned(16))) Out s_ystage[kStageY ? NWAVE : 1][kStageY ? ROW + E : 1];
+    // plain and segmented scans reading 16-byte vectors: the next full block of
+    // the workgroup is prefetched into LDS (each wave its own R rows of 1 KiB)
+    // while the current block is scanned, so a workgroup's loads stay in flight
+    // through its compute.  (bf16 reads 8-byte vectors; gfx950 has no 8-byte
+    // form of the LDS load, and two 4-byte loads per row measured slower than
+    // the plain vector loads: 5.3 -> 4.8 TB/s.)
+    constexpr bool kPrefetch = (MODE == kModePlain || MODE == kModeSegmented) && E * sizeof(In) == 16;
+    constexpr uint32_t kRowBytes = 1024u;
+    __shared__ __attribute__((aligned(16))) u32x4 s_pf[kPrefetch ? T * R : 1];
     __shared__ V s_wave_total[2][NWAVE];
     __shared__ VB s_block_prefix[2];
     __shared__ int s_abort[2];
@@ -346,6 +379,26 @@ __global__ void __launch_bounds__(T) scan_kernel(ScanArgs a)
     V p_lp[R];
     VB p_agg = BOp::identity();         // wave 0: the pending block's aggregate
     VB carry = BOp::identity();         // wave 0: P(j - B) for the pending block j
+
+    // the prefetch: this wave's LDS rows, and whether they hold the block to scan next
+    const uint32_t pf_lds = kPrefetch ? lds_address(&s_pf[0]) + uint32_t(wave) * R * kRowBytes : 0u;
+    bool pf_have = false;
+    // plain and segmented: block i read with full vectors (every position inside the array)
+    auto full_block = [&](int64_t i) -> bool {
+        const int64_t t0 = i * L;
+        return a.vec_ok != 0 && t0 + L <= a.n + a.phase && t0 >= a.phase;
+    };
+    auto prefetch = [&](int64_t i) {
+        const In* xs = static_cast<const In*>(a.x) - a.phase + i * L + int64_t(wave) * (R * ROW) + int64_t(lane) * E;
+#pragma unroll
+        for (int r = 0; r < R; ++r) lds_load16(xs + int64_t(r) * ROW, pf_lds + uint32_t(r) * kRowBytes);
+    };
+    if constexpr (kPrefetch) {
+        if (int64_t(blockIdx.x) < a.num_blocks && full_block(blockIdx.x)) {
+            prefetch(blockIdx.x);
+            pf_have = true;
+        }
+    }
 
     int parity = 0;
     // Batched scans: the array of a block is found by a wave-uniform search
@@ -430,7 +483,22 @@ __global__ void __launch_bounds__(T) scan_kernel(ScanArgs a)
             }
             lane0 = tile0 + int64_t(wave) * (R * ROW) + int64_t(lane) * E;
             full = vec_ok && (tile0 + L <= n) && (tile0 >= ph);
-            if (full) {
+            if constexpr (kPrefetch) {
+                // a full block arrives through LDS: prefetched during the previous
+                // step (or, after a partial block, loaded that way now), so no
+                // data load of the compiler's own is ever pending past this point
+                if (full) {
+                    if (!pf_have) prefetch(i);
+                    vmem_drain();
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        const u32x4 w = s_pf[(wave * R + r) * 64 + lane];
+                        __builtin_memcpy(raw[r], &w, 16);
+                    }
+                    lds_reads_drain();  // the rows are read before the next prefetch overwrites them
+                }
+                pf_have = false;
+            } else if (full) {
 #pragma unroll
                 for (int r = 0; r < R; ++r) load_vector<In, E>(x + lane0 + int64_t(r) * ROW, raw[r]);
             } else if (MODE == kModeBatched && vec_ok) {
@@ -536,6 +604,17 @@ __global__ void __launch_bounds__(T) scan_kernel(ScanArgs a)
             }
         }
 
+        // the next full block of this workgroup goes out into LDS now, after every
+        // wait of this step on data or flag words: vector memory operations
+        // complete in issue order, so a later wait on a load of the compiler's own
+        // would also wait for the prefetch
+        if constexpr (kPrefetch) {
+            if (have_new && i + B < a.num_blocks && full_block(i + B)) {
+                prefetch(i + B);
+                pf_have = true;
+            }
+        }
+
         // -- 3. intra-wave local scan of the new block: in-lane, then across lanes per row
         V e[R][E];
         V lane_prefix[R];
@@ -567,10 +646,15 @@ __global__ void __launch_bounds__(T) scan_kernel(ScanArgs a)
                     for (int k = 0; k < E; ++k) {
                         const int64_t p = lane0 + int64_t(r) * ROW + k;
                         if (p < n && p >= ph) {
+                            In xv = x[p];
+                            // prefetching kernels: the load completes here, inside the
+                            // partial-block path, so the waits the compiler places for
+                            // it never land on the path of full blocks
+                            if constexpr (kPrefetch) asm volatile("" : "+v"(xv));
                             if constexpr (MODE == kModeSegmented)
-                                e[r][k] = EOp::make(lift_elem<BaseOp>(x[p], p - ph), (head[r] >> k) & 1u);
+                                e[r][k] = EOp::make(lift_elem<BaseOp>(xv, p - ph), (head[r] >> k) & 1u);
                             else
-                                e[r][k] = lift_elem<BaseOp>(x[p], p - ph);
+                                e[r][k] = lift_elem<BaseOp>(xv, p - ph);
                         } else {
                             e[r][k] = EOp::identity();
                         }
@@ -619,7 +703,10 @@ __global__ void __launch_bounds__(T) scan_kernel(ScanArgs a)
 
         // -- 5. intra-block global scan and one coalesced store per vector, for the pending block:
         //       the block prefix joins each row's lane prefix once, then each element
-        if (have_pend) {
+        //       (inclusive or exclusive is chosen once per block: the flag is uniform,
+        //       and every element's output is then one finish with fixed operands)
+        auto fix_up = [&](auto excl_tag) {
+            constexpr bool EXCL = decltype(excl_tag)::value;
             V prefix;
             if constexpr (MODE == kModeBatched)  // the first block of an array starts from the identity
                 prefix = p_block_head ? EOp::identity() : s_block_prefix[parity].v;
@@ -639,16 +726,23 @@ __global__ void __launch_bounds__(T) scan_kernel(ScanArgs a)
                 Out out[E];
 #pragma unroll
                 for (int k = 0; k < E; ++k) {
-                    V v;
-                    if (!a.exclusive)
-                        v = EOp::combine(q, ev[k]);
-                    else
-                        v = (k == 0) ? q : EOp::combine(q, ev[k - 1]);
-                    if constexpr (MODE == kModeSegmented)
-                        out[k] = (a.exclusive && ((p_head[r] >> k) & 1u)) ? BaseOp::lower(BaseOp::identity())
-                                                                          : BaseOp::lower(v.v);
-                    else
-                        out[k] = BaseOp::lower(v);
+                    if constexpr (MODE == kModeSegmented) {
+                        // a head inside the lane's vector at or before the element: its value alone
+                        if constexpr (!EXCL) {
+                            out[k] = ev[k].f ? BaseOp::lower(ev[k].v) : finish_of<BaseOp>(q.v, ev[k].v);
+                        } else if (k == 0) {
+                            out[k] = (p_head[r] & 1u) ? BaseOp::lower(BaseOp::identity()) : BaseOp::lower(q.v);
+                        } else {
+                            out[k] = ((p_head[r] >> k) & 1u) ? BaseOp::lower(BaseOp::identity())
+                                     : ev[k - 1].f          ? BaseOp::lower(ev[k - 1].v)
+                                                            : finish_of<BaseOp>(q.v, ev[k - 1].v);
+                        }
+                    } else {
+                        if constexpr (!EXCL)
+                            out[k] = finish_of<BaseOp>(q, ev[k]);
+                        else
+                            out[k] = (k == 0) ? BaseOp::lower(q) : finish_of<BaseOp>(q, ev[k - 1]);
+                    }
                 }
                 const int64_t p = p_lane0 + int64_t(r) * ROW;
                 if ((p_full && p_svec) || ((p_vrow >> r) & 1u)) {
@@ -685,6 +779,12 @@ __global__ void __launch_bounds__(T) scan_kernel(ScanArgs a)
                         if (p + k < p_n && p + k >= p_ph) p_y[p + k] = out[k];
                 }
             }
+        };
+        if (have_pend) {
+            if (a.exclusive)
+                fix_up(std::true_type{});
+            else
+                fix_up(std::false_type{});
         }
 
         // -- 6. the new block becomes the pending one
@@ -727,6 +827,7 @@ __global__ void __launch_bounds__(T) scan_kernel(ScanArgs a)
     for (; i < a.num_blocks; i += B, parity ^= 1)
         if (!(live = step(std::true_type{}, i))) break;
     if (live && have_pend) step(std::false_type{}, i);
+    if constexpr (kPrefetch) vmem_drain();  // no LDS load outlives the workgroup
 
     // Every workgroup counts itself out; the last one advances the epoch so
     // the next launch on this workspace uses a fresh tag (no memset needed).

@@ -178,6 +178,18 @@ struct AddF32 {
 // Combining two states adds the s parts with TwoSum (Knuth), which also
 // yields the exact rounding error of that addition, and folds that error
 // together with both c parts into c.  The output is fl(s + c).
+//
+// A lifted element carries c = -0.0: x + (-0.0) == x for every x (signed
+// zeros included), so the compiler drops the c addition of every combine
+// with a freshly lifted element.  (The identity keeps c = +0.0, which the
+// cross-lane moves supply for free to lanes without a source.)
+//
+// finish(q, e), the output of q (+) e, is fl(fl(q.s + e.s) + fl(q.c + e.c))
+// instead of a full TwoSum followed by fl(s + c): three additions instead
+// of nine.  With q the prefix before a lane's vector and e the in-lane
+// partial sum, |q.s + e.s| exceeds the result |y| only by the small
+// compensation terms, so the two extra roundings add at most about
+// u * |y| (u = 2^-24) to the rounding of the result itself.
 struct F32Pair {
     float s, c;
 };
@@ -197,8 +209,9 @@ struct AddF32Comp {
     static constexpr int E = 4;
     __device__ static V identity() { return F32Pair{0.0f, 0.0f}; }
     __device__ static V combine(V a, V b) { return two_sum_combine(a, b); }
-    __device__ static V lift(In x) { return F32Pair{bits_to_f32(x), 0.0f}; }
+    __device__ static V lift(In x) { return F32Pair{bits_to_f32(x), -0.0f}; }
     __device__ static Out lower(V v) { return v.s + v.c; }
+    __device__ static Out finish(V q, V e) { return (q.s + e.s) + (q.c + e.c); }
 };
 
 // float32 max / min under totalOrder, scanned on integer keys (exact).
@@ -364,6 +377,22 @@ __device__ __forceinline__ typename Op::V lift_elem(typename Op::In x, int64_t i
         return Op::lift(x);
 }
 
+// Output of q (+) e: the operator's own finish when it has one, else
+// lower(combine(q, e)).
+template <class Op, class = void>
+struct has_finish : std::false_type {};
+template <class Op>
+struct has_finish<Op, std::void_t<decltype(Op::finish(Op::identity(), Op::identity()))>> : std::true_type {};
+
+template <class Op>
+__device__ __forceinline__ typename Op::Out finish_of(const typename Op::V& q, const typename Op::V& e)
+{
+    if constexpr (has_finish<Op>::value)
+        return Op::finish(q, e);
+    else
+        return Op::lower(Op::combine(q, e));
+}
+
 // bfloat16 input: the 16 bits become the high half of an f32 (exact), then
 // the f32 operator runs.  Loads are 8 bytes (4 elements) per lane so that
 // the 4 float32 outputs fill one 16-byte store.
@@ -377,6 +406,7 @@ struct FromBF16 {
     __device__ static V combine(V a, V b) { return F32Op::combine(a, b); }
     __device__ static V lift(In x) { return F32Op::lift(bf16_bits_to_f32_bits(x)); }
     __device__ static Out lower(V v) { return F32Op::lower(v); }
+    __device__ static Out finish(V q, V e) { return finish_of<F32Op>(q, e); }
 };
 using AddBF16 = FromBF16<AddF32>;
 using AddBF16Comp = FromBF16<AddF32Comp>;

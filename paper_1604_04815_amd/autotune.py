@@ -145,11 +145,11 @@ def tune(x, op="add", compensated=False, kind="plain", offsets=None, arrays=None
     shapes = shapes or binding.lscan_tile_shapes()
     if kind == "batched":
         xs = arrays
-        ys = [torch.empty(t.shape[0], dtype=binding.out_dtype(t), device=t.device) for t in xs]
+        ys = [torch.empty(t.shape[0], dtype=binding.out_dtype(t, op), device=t.device) for t in xs]
         n = sum(int(t.shape[0]) for t in xs)
         dtype_t = xs[0]
     else:
-        y = torch.empty(x.shape[0], dtype=binding.out_dtype(x), device=x.device)
+        y = torch.empty(x.shape[0], dtype=binding.out_dtype(x, op), device=x.device)
         n = int(x.shape[0])
         dtype_t = x
     count = torch.empty(1, dtype=torch.int64, device=x.device) if kind == "compact" else None
@@ -181,7 +181,7 @@ def tune(x, op="add", compensated=False, kind="plain", offsets=None, arrays=None
                 print(f"  T={t} R={r} groups={c.groups_per_cu} grid={c.grid}: {c.ms * 1e3:.1f} us", flush=True)
     best = pick_best(cands)
     in_bytes = 2 if dtype_t.dtype == torch.bfloat16 else dtype_t.element_size()
-    out_bytes = 4 if dtype_t.dtype == torch.bfloat16 else dtype_t.element_size()
+    out_bytes = torch.empty(0, dtype=binding.out_dtype(dtype_t, op)).element_size()
     if kind == "compact":  # items and flags read, the kept items written
         fn()
         torch.cuda.synchronize()

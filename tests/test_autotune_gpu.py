@@ -56,3 +56,23 @@ def test_tune_compact(gpu_lib):
     want = torch.masked_select(x, keep.bool())
     assert int(count.item()) == want.shape[0] and torch.equal(out[:want.shape[0]], want)
     gpu_lib.lscan_set_params(gpu_lib.I32, gpu_lib.ADD, 0, gpu_lib.KIND_COMPACT, before)
+
+
+def test_tune_argmax(gpu_lib):
+    """The tuner sizes the running argmax's output as int64 indices; the
+    installed winner still matches the oracle element by element."""
+    import numpy as np
+    import oracle
+    from paper_1604_04815_amd import autotune
+    n = 3_000_017
+    x_host = np.random.default_rng(16).integers(-50, 50, n).astype(np.int32)  # many ties
+    x = to_device(x_host, "int32")
+    before = gpu_lib.lscan_get_params(gpu_lib.I32, gpu_lib.OPS["argmax"])
+    e = autotune.tune(x, "argmax", shapes=[(256, 8), (1024, 4)], groups=(1, 2), reps=2, warmup=1)
+    assert e.op == "argmax" and e.gbs > 0
+    autotune.apply(e)
+    y = gpu_lib.inclusive(x, "argmax")
+    torch.cuda.synchronize()
+    assert y.dtype == torch.int64
+    assert np.array_equal(to_host(y), oracle.argscan(x_host, "int32", "argmax", False))
+    gpu_lib.lscan_set_params(gpu_lib.I32, gpu_lib.OPS["argmax"], 0, gpu_lib.KIND_PLAIN, before)

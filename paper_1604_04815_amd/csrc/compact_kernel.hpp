@@ -120,6 +120,35 @@ __global__ void __launch_bounds__(TT) compact_kernel(ScanArgs a)
     VB p_agg = 0;    // wave 0: kept items in the pending block
     VB carry = 0;    // wave 0: kept items before block (pending - B + 1)
 
+    // The next full block of the workgroup is prefetched into LDS while the
+    // current one is counted and scattered, as in the scan: its items (each
+    // wave its R rows of 1 KiB) and its keep bytes (straight into the wave's
+    // flag span, which has the layout a 16-byte-per-lane LDS load writes).
+    // Shapes whose flag chunks are narrower than 16 bytes load as before.
+    constexpr bool kPrefetch = FC::C == 16;
+    __shared__ __attribute__((aligned(16))) u32x4 s_pfx[kPrefetch ? TT * R : 1];
+    const uint32_t pfx_lds = kPrefetch ? lds_address(&s_pfx[0]) + uint32_t(wave) * R * 1024u : 0u;
+    const uint32_t pff_lds = kPrefetch ? lds_address(&s_flags[wave][0]) : 0u;
+    bool pf_have = false;
+    auto full_block = [&](int64_t i) -> bool { return a.vec_ok && ((i + 1) * L <= n); };
+    auto prefetch = [&](int64_t i) {
+        const int64_t w0 = i * L + int64_t(wave) * (R * ROW);
+        const T* xs = x + w0 + int64_t(lane) * E;
+#pragma unroll
+        for (int r = 0; r < R; ++r) lds_load16(xs + int64_t(r) * ROW, pfx_lds + uint32_t(r) * 1024u);
+        if (keep) {
+            const uint8_t* kw = keep + w0 + lane * FC::C;
+#pragma unroll
+            for (int q = 0; q < FC::N; ++q) lds_load16(kw + q * 64 * FC::C, pff_lds + uint32_t(q) * 1024u);
+        }
+    };
+    if constexpr (kPrefetch) {
+        if (int64_t(blockIdx.x) < a.num_blocks && full_block(blockIdx.x)) {
+            prefetch(blockIdx.x);
+            pf_have = true;
+        }
+    }
+
     int parity = 0;
     auto step = [&](auto new_tag, int64_t i) -> bool {
         constexpr bool have_new = decltype(new_tag)::value;
@@ -131,7 +160,25 @@ __global__ void __launch_bounds__(TT) compact_kernel(ScanArgs a)
         T raw[R][E];
         uint32_t bits[R];
         typename FC::Word fw[FC::N];
-        if (have_new && full) {
+        if constexpr (kPrefetch) {
+            // a full block arrives through LDS (prefetched during the previous
+            // step, or loaded that way now after a partial block)
+            if (have_new && full) {
+                if (!pf_have) prefetch(i);
+                vmem_drain();
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const u32x4 w = s_pfx[(wave * R + r) * 64 + lane];
+                    __builtin_memcpy(raw[r], &w, 16);
+                }
+                if (keep) {
+#pragma unroll
+                    for (int r = 0; r < R; ++r) bits[r] = keep_bits<E>(s_flags[wave] + r * ROW + lane * E);
+                }
+                lds_reads_drain();  // read before the next prefetch overwrites them
+            }
+            if (have_new) pf_have = false;
+        } else if (have_new && full) {
 #pragma unroll
             for (int r = 0; r < R; ++r) load_vector<T, E>(x + lane0 + int64_t(r) * ROW, raw[r]);
             if (keep) {
@@ -165,6 +212,15 @@ __global__ void __launch_bounds__(TT) compact_kernel(ScanArgs a)
             }
         }
 
+        // the next full block goes out into LDS after every wait of this step on
+        // data or flag words (waits complete in issue order)
+        if constexpr (kPrefetch) {
+            if (have_new && i + B < a.num_blocks && full_block(i + B)) {
+                prefetch(i + B);
+                pf_have = true;
+            }
+        }
+
         // -- 3. counts of the new block: per lane-row, across the wave, across rows
         int32_t lane_prefix[R];
         int32_t row_prefix[R];
@@ -179,8 +235,13 @@ __global__ void __launch_bounds__(TT) compact_kernel(ScanArgs a)
                         const int64_t p = lane0 + int64_t(r) * ROW + k;
                         raw[r][k] = T(0);
                         if (p < n) {
-                            raw[r][k] = x[p];
-                            if (keep ? (keep[p] != 0) : (raw[r][k] != T(0))) m |= 1u << k;
+                            T xv = x[p];
+                            uint32_t kv = keep ? uint32_t(keep[p]) : 1u;
+                            // with the prefetch: the loads complete inside this partial-block
+                            // path, so the compiler's waits for them stay off full blocks
+                            if constexpr (kPrefetch) asm volatile("" : "+v"(xv), "+v"(kv));
+                            raw[r][k] = xv;
+                            if (keep ? (kv != 0) : (xv != T(0))) m |= 1u << k;
                         }
                     }
                     bits[r] = m;
@@ -193,7 +254,7 @@ __global__ void __launch_bounds__(TT) compact_kernel(ScanArgs a)
                     for (int k = 0; k < E; ++k) m |= (raw[r][k] != T(0) ? 1u : 0u) << k;
                     bits[r] = m;
                 }
-            } else {  // the flag span through LDS: each lane then takes its rows' E bytes
+            } else if constexpr (!kPrefetch) {  // the flag span through LDS: each lane then takes its rows' E bytes
                 uint8_t* sf = s_flags[wave];
 #pragma unroll
                 for (int q = 0; q < FC::N; ++q)
@@ -302,6 +363,7 @@ __global__ void __launch_bounds__(TT) compact_kernel(ScanArgs a)
     for (; i < a.num_blocks; i += B, parity ^= 1)
         if (!(live = step(std::true_type{}, i))) break;
     if (live && have_pend) step(std::false_type{}, i);
+    if constexpr (kPrefetch) vmem_drain();  // no LDS load outlives the workgroup
 
     // count out; the last workgroup advances the epoch (as in the scan)
     if (threadIdx.x == 0) {

@@ -134,20 +134,29 @@ def _time(fn, reps: int, warmup: int) -> float:
 
 
 def tune(x, op="add", compensated=False, kind="plain", offsets=None, arrays=None, keep=None, reps=8, warmup=2,
-         shapes=None, groups=GROUPS, verbose=False) -> Entry:
+         shapes=None, groups=GROUPS, verbose=False, outs=None) -> Entry:
     """Time every (shape, groups) for scanning device tensor ``x`` (or the
     batch ``arrays`` of device tensors, or ``x`` cut by ``offsets``, or
     compacting ``x`` by the ``keep`` flags) and return the best as an Entry
-    (not yet applied)."""
+    (not yet applied).  A batch is timed with the caller's output tensors
+    ``outs`` when given: where each output sits relative to its input's
+    16-byte alignment decides the kernel's path, so fresh outputs may time
+    another path than the caller's."""
     import torch
 
     binding.load()
     shapes = shapes or binding.lscan_tile_shapes()
     if kind == "batched":
         xs = arrays
-        ys = [torch.empty(t.shape[0], dtype=binding.out_dtype(t, op), device=t.device) for t in xs]
+        ys = list(outs) if outs is not None else [
+            torch.empty(t.shape[0], dtype=binding.out_dtype(t, op), device=t.device) for t in xs]
         n = sum(int(t.shape[0]) for t in xs)
         dtype_t = xs[0]
+        # the descriptor table is built once, so a large batch is timed by its
+        # launch and not by rebuilding thousands of descriptors in Python
+        table = binding.array_table([(t.data_ptr(), u.data_ptr(), t.shape[0]) for t, u in zip(xs, ys)])
+        bflags = binding.F_COMPENSATED if compensated else 0
+        bdt = binding.dtype_code(dtype_t)
     else:
         y = torch.empty(x.shape[0], dtype=binding.out_dtype(x, op), device=x.device)
         n = int(x.shape[0])
@@ -165,8 +174,8 @@ def tune(x, op="add", compensated=False, kind="plain", offsets=None, arrays=None
             elif kind == "compact":
                 fn = lambda p=p: binding.compact(x, keep, out=y, count=count, params=p)  # noqa: E731
             else:
-                fn = lambda p=p: binding.batched(xs, op, compensated=compensated, outs=ys,  # noqa: E731
-                                                 params=p)
+                fn = lambda p=p: binding.lscan_batched(table, bdt, binding.OPS[op], bflags,  # noqa: E731
+                                                       torch.cuda.current_stream().cuda_stream, p)
             fn()
             torch.cuda.synchronize()
             binding.lscan_check(torch.cuda.current_stream().cuda_stream)

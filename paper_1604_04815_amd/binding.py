@@ -214,10 +214,30 @@ def _array_table(arrays):
     return tab
 
 
+class ArrayTable:
+    """A batch's lscan_array table, built once: len() is the array count and
+    the object passes to the C call as the table itself."""
+
+    def __init__(self, arrays):
+        self._tab = _array_table(arrays)
+        self._count = len(arrays)
+        self._as_parameter_ = ctypes.cast(self._tab, ctypes.POINTER(Array))
+
+    def __len__(self):
+        return self._count
+
+
+def array_table(arrays) -> ArrayTable:
+    """arrays: list of (x_ptr, y_ptr, n)."""
+    return ArrayTable(arrays)
+
+
 def lscan_batched(arrays, dt: int, op: int, flags: int = 0, stream: int = 0,
                   params: Params | None = None) -> int:
-    """arrays: list of (x_ptr, y_ptr, n)."""
-    tab = _array_table(arrays)
+    """arrays: list of (x_ptr, y_ptr, n), or a table built once with
+    array_table (what a caller that launches the same batch many times
+    passes, so the per-call cost is the C call alone)."""
+    tab = arrays if isinstance(arrays, ArrayTable) else _array_table(arrays)
     if params is None:
         st = load().lscan_batched(tab, len(arrays), dt, op, flags, stream)
     else:

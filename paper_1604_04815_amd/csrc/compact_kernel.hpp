@@ -214,10 +214,16 @@ __global__ void __launch_bounds__(TT) compact_kernel(ScanArgs a)
 
         // the next full block goes out into LDS after every wait of this step on
         // data or flag words (waits complete in issue order)
+        // (after a partial block, only once its own loads are done: below)
+        bool pf_late = false;
         if constexpr (kPrefetch) {
             if (have_new && i + B < a.num_blocks && full_block(i + B)) {
-                prefetch(i + B);
-                pf_have = true;
+                if (full) {
+                    prefetch(i + B);
+                    pf_have = true;
+                } else {
+                    pf_late = true;
+                }
             }
         }
 
@@ -229,20 +235,25 @@ __global__ void __launch_bounds__(TT) compact_kernel(ScanArgs a)
             if (!full) {  // the tail block, or unaligned pointers: item by item
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
+                    uint32_t kv[E];
+#pragma unroll
+                    for (int k = 0; k < E; ++k) {
+                        const int64_t p = lane0 + int64_t(r) * ROW + k;
+                        raw[r][k] = (p < n) ? x[p] : T(0);
+                        kv[k] = (p < n && keep) ? uint32_t(keep[p]) : 0u;
+                    }
+                    // with the prefetch: the row's loads complete inside this partial-block
+                    // path, so the compiler's waits for them stay off full blocks
+                    if constexpr (kPrefetch) {
+                        complete_loads(raw[r]);
+#pragma unroll
+                        for (int k = 0; k < E; ++k) asm volatile("" : "+v"(kv[k]));
+                    }
                     uint32_t m = 0;
 #pragma unroll
                     for (int k = 0; k < E; ++k) {
                         const int64_t p = lane0 + int64_t(r) * ROW + k;
-                        raw[r][k] = T(0);
-                        if (p < n) {
-                            T xv = x[p];
-                            uint32_t kv = keep ? uint32_t(keep[p]) : 1u;
-                            // with the prefetch: the loads complete inside this partial-block
-                            // path, so the compiler's waits for them stay off full blocks
-                            if constexpr (kPrefetch) asm volatile("" : "+v"(xv), "+v"(kv));
-                            raw[r][k] = xv;
-                            if (keep ? (kv != 0) : (xv != T(0))) m |= 1u << k;
-                        }
+                        if (p < n && (keep ? (kv[k] != 0) : (raw[r][k] != T(0)))) m |= 1u << k;
                     }
                     bits[r] = m;
                 }
@@ -263,6 +274,12 @@ __global__ void __launch_bounds__(TT) compact_kernel(ScanArgs a)
 #pragma unroll
                 for (int r = 0; r < R; ++r) bits[r] = keep_bits<E>(sf + r * ROW + lane * E);
                 wave_lds_sync();
+            }
+            if constexpr (kPrefetch) {
+                if (pf_late) {  // the partial block's loads are done: the next block goes out now
+                    prefetch(i + B);
+                    pf_have = true;
+                }
             }
 #pragma unroll
             for (int r = 0; r < R; ++r) {

@@ -119,6 +119,18 @@ __device__ __forceinline__ void lds_load16(const void* g, uint32_t lds_byte)
 }
 
 __device__ __forceinline__ void vmem_drain() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+// Make the compiler complete the loads that produced v here (it must have
+// the value in registers before the empty statement), so that its waits
+// for them stay on the path that issued them.
+template <class T, int N>
+__device__ __forceinline__ void complete_loads(T (&v)[N])
+{
+    static_assert(sizeof(T) * N == 16, "one 16-byte lane vector");
+    u32x4 w;
+    __builtin_memcpy(&w, v, 16);
+    asm volatile("" : "+v"(w));
+    __builtin_memcpy(v, &w, 16);
+}
 __device__ __forceinline__ void lds_reads_drain() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
 
 // ---------------------------------------------------------------------------
@@ -339,12 +351,15 @@ __global__ void __launch_bounds__(T) scan_kernel(ScanArgs a)
     // x: each wave stages one output row here to write it as aligned vectors
     constexpr bool kStageY = (MODE == kModePlain || MODE == kModeSegmented) && E * sizeof(Out) == 16;
     __shared__ __attribute__((aligned(16))) Out s_ystage[kStageY ? NWAVE : 1][kStageY ? ROW + E : 1];
-    // plain and segmented scans reading 16-byte vectors: the next full block of
-    // the workgroup is prefetched into LDS (each wave its own R rows of 1 KiB)
-    // while the current block is scanned, so a workgroup's loads stay in flight
-    // through its compute.  (bf16 reads 8-byte vectors; gfx950 has no 8-byte
-    // form of the LDS load, and two 4-byte loads per row measured slower than
-    // the plain vector loads: 5.3 -> 4.8 TB/s.)
+    // plain and segmented scans reading 16-byte vectors: the next full block
+    // of the workgroup is prefetched into LDS (each wave its own R rows of
+    // 1 KiB) while the current block is scanned, so a workgroup's loads stay
+    // in flight through its compute.  (bf16 reads 8-byte vectors; gfx950 has
+    // no 8-byte form of the LDS load, and two 4-byte loads per row measured
+    // slower than the plain vector loads: 5.3 -> 4.8 TB/s.  Batched scans
+    // load as before: with arrays of a few blocks, a workgroup's next block
+    // usually lies in another array and is often partial, and the prefetch
+    // measured slower, 4096 arrays: 4.87 -> 4.64 TB/s.)
     constexpr bool kPrefetch = (MODE == kModePlain || MODE == kModeSegmented) && E * sizeof(In) == 16;
     constexpr uint32_t kRowBytes = 1024u;
     __shared__ __attribute__((aligned(16))) u32x4 s_pf[kPrefetch ? T * R : 1];
@@ -383,22 +398,11 @@ __global__ void __launch_bounds__(T) scan_kernel(ScanArgs a)
     // the prefetch: this wave's LDS rows, and whether they hold the block to scan next
     const uint32_t pf_lds = kPrefetch ? lds_address(&s_pf[0]) + uint32_t(wave) * R * kRowBytes : 0u;
     bool pf_have = false;
-    // plain and segmented: block i read with full vectors (every position inside the array)
-    auto full_block = [&](int64_t i) -> bool {
-        const int64_t t0 = i * L;
-        return a.vec_ok != 0 && t0 + L <= a.n + a.phase && t0 >= a.phase;
-    };
-    auto prefetch = [&](int64_t i) {
-        const In* xs = static_cast<const In*>(a.x) - a.phase + i * L + int64_t(wave) * (R * ROW) + int64_t(lane) * E;
+    auto prefetch = [&](const In* xg, int64_t t0) {  // xg: the array's grid origin, t0: the block's first position
+        const In* xs = xg + t0 + int64_t(wave) * (R * ROW) + int64_t(lane) * E;
 #pragma unroll
         for (int r = 0; r < R; ++r) lds_load16(xs + int64_t(r) * ROW, pf_lds + uint32_t(r) * kRowBytes);
     };
-    if constexpr (kPrefetch) {
-        if (int64_t(blockIdx.x) < a.num_blocks && full_block(blockIdx.x)) {
-            prefetch(blockIdx.x);
-            pf_have = true;
-        }
-    }
 
     int parity = 0;
     // Batched scans: the array of a block is found by a wave-uniform search
@@ -431,6 +435,30 @@ __global__ void __launch_bounds__(T) scan_kernel(ScanArgs a)
     };
     if constexpr (MODE == kModeBatched) {
         if (int64_t(blockIdx.x) < a.num_blocks) find_array(blockIdx.x);
+    }
+    // Block i read with full vectors (every position inside its array): its grid
+    // origin and first position.  Batched scans take block i's array from
+    // next_d, which the lookup one step ahead has filled.
+    auto full_src = [&](int64_t i, const In*& xg, int64_t& t0) -> bool {
+        if constexpr (MODE == kModeBatched) {
+            const int64_t ph = next_d.phase;
+            if (ph < 0) return false;
+            xg = static_cast<const In*>(next_d.x) - ph;
+            t0 = (i - next_d.first_block) * L;
+            return t0 + L <= next_d.n + ph && t0 >= ph;
+        } else {
+            xg = static_cast<const In*>(a.x) - a.phase;
+            t0 = i * L;
+            return a.vec_ok != 0 && t0 + L <= a.n + a.phase && t0 >= a.phase;
+        }
+    };
+    if constexpr (kPrefetch) {
+        const In* xg;
+        int64_t t0;
+        if (int64_t(blockIdx.x) < a.num_blocks && full_src(blockIdx.x, xg, t0)) {
+            prefetch(xg, t0);
+            pf_have = true;
+        }
     }
     // One pipeline step: load and scan block i (when have_new) while the pending
     // block is resolved and stored.  The step that only drains the last
@@ -483,12 +511,12 @@ __global__ void __launch_bounds__(T) scan_kernel(ScanArgs a)
             }
             lane0 = tile0 + int64_t(wave) * (R * ROW) + int64_t(lane) * E;
             full = vec_ok && (tile0 + L <= n) && (tile0 >= ph);
-            if constexpr (kPrefetch) {
-                // a full block arrives through LDS: prefetched during the previous
-                // step (or, after a partial block, loaded that way now), so no
-                // data load of the compiler's own is ever pending past this point
-                if (full) {
-                    if (!pf_have) prefetch(i);
+            if (full) {
+                if constexpr (kPrefetch) {
+                    // a full block arrives through LDS: prefetched during the previous
+                    // step (or, after a partial block, loaded that way now), so no
+                    // data load of the compiler's own is ever pending past this point
+                    if (!pf_have) prefetch(x, tile0);
                     vmem_drain();
 #pragma unroll
                     for (int r = 0; r < R; ++r) {
@@ -496,11 +524,10 @@ __global__ void __launch_bounds__(T) scan_kernel(ScanArgs a)
                         __builtin_memcpy(raw[r], &w, 16);
                     }
                     lds_reads_drain();  // the rows are read before the next prefetch overwrites them
-                }
-                pf_have = false;
-            } else if (full) {
+                } else {
 #pragma unroll
-                for (int r = 0; r < R; ++r) load_vector<In, E>(x + lane0 + int64_t(r) * ROW, raw[r]);
+                    for (int r = 0; r < R; ++r) load_vector<In, E>(x + lane0 + int64_t(r) * ROW, raw[r]);
+                }
             } else if (MODE == kModeBatched && vec_ok) {
                 // an array's first or last block: whole rows of the wave (a
                 // wave-uniform choice) still move as vectors
@@ -514,6 +541,7 @@ __global__ void __launch_bounds__(T) scan_kernel(ScanArgs a)
                     }
                 }
             }
+            if constexpr (kPrefetch) pf_have = false;
             if constexpr (MODE == kModeBatched) {  // while the loads are in flight: the next block's array
                 if (i + B < a.num_blocks) find_array(i + B);
             }
@@ -608,10 +636,18 @@ __global__ void __launch_bounds__(T) scan_kernel(ScanArgs a)
         // wait of this step on data or flag words: vector memory operations
         // complete in issue order, so a later wait on a load of the compiler's own
         // would also wait for the prefetch
+        // (after a partial block, only once its own loads are done: below)
+        bool pf_late = false;
         if constexpr (kPrefetch) {
-            if (have_new && i + B < a.num_blocks && full_block(i + B)) {
-                prefetch(i + B);
-                pf_have = true;
+            const In* xg;
+            int64_t t0;
+            if (have_new && i + B < a.num_blocks && full_src(i + B, xg, t0)) {
+                if (full) {
+                    prefetch(xg, t0);
+                    pf_have = true;
+                } else {
+                    pf_late = true;
+                }
             }
         }
 
@@ -634,31 +670,46 @@ __global__ void __launch_bounds__(T) scan_kernel(ScanArgs a)
             } else {
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
+                    // prefetching kernels complete this row's loads here, inside the
+                    // partial-block path, so that the waits the compiler places for
+                    // them never land on the path of full blocks (nor wait for a prefetch)
                     if constexpr (MODE == kModeBatched) {
                         if ((vrow >> r) & 1u) {  // a whole row, read as vectors in stage 1
+                            if constexpr (kPrefetch) complete_loads(raw[r]);
 #pragma unroll
                             for (int k = 0; k < E; ++k)
                                 e[r][k] = lift_elem<BaseOp>(raw[r][k], lane0 + int64_t(r) * ROW + k - ph);
                             continue;
                         }
                     }
+                    In xv[E];
+#pragma unroll
+                    for (int k = 0; k < E; ++k) {
+                        const int64_t p = lane0 + int64_t(r) * ROW + k;
+                        xv[k] = (p < n && p >= ph) ? x[p] : In{};
+                    }
+                    if constexpr (kPrefetch) complete_loads(xv);
 #pragma unroll
                     for (int k = 0; k < E; ++k) {
                         const int64_t p = lane0 + int64_t(r) * ROW + k;
                         if (p < n && p >= ph) {
-                            In xv = x[p];
-                            // prefetching kernels: the load completes here, inside the
-                            // partial-block path, so the waits the compiler places for
-                            // it never land on the path of full blocks
-                            if constexpr (kPrefetch) asm volatile("" : "+v"(xv));
                             if constexpr (MODE == kModeSegmented)
-                                e[r][k] = EOp::make(lift_elem<BaseOp>(xv, p - ph), (head[r] >> k) & 1u);
+                                e[r][k] = EOp::make(lift_elem<BaseOp>(xv[k], p - ph), (head[r] >> k) & 1u);
                             else
-                                e[r][k] = lift_elem<BaseOp>(xv, p - ph);
+                                e[r][k] = lift_elem<BaseOp>(xv[k], p - ph);
                         } else {
                             e[r][k] = EOp::identity();
                         }
                     }
+                }
+            }
+            if constexpr (kPrefetch) {
+                if (pf_late) {  // the partial block's loads are done: the next block goes out now
+                    const In* xg;
+                    int64_t t0;
+                    full_src(i + B, xg, t0);
+                    prefetch(xg, t0);
+                    pf_have = true;
                 }
             }
 #pragma unroll

@@ -406,3 +406,14 @@ def test_noalloc_size_limit_before_device_work(lib):
     assert lib.lscan_inclusive_noalloc(x, y, 4, binding.I32, binding.MAX, binding.F_COMPENSATED, None) == \
         binding.ERR_UNSUPPORTED
     assert lib.lscan_inclusive_noalloc(None, None, 0, binding.I32, binding.ADD, 0, None) == binding.OK
+
+
+def test_array_table_built_once():
+    """A batch's descriptor table built once (what repeated launches of one
+    batch pass) holds every array's pointers and length in order."""
+    from paper_1604_04815_amd import binding
+    rows = [(0x1000, 0x2000, 5), (0x3010, 0x4020, 0), (0x5000, 0x6000, 1 << 33)]
+    t = binding.array_table(rows)
+    assert len(t) == 3
+    p = t._as_parameter_
+    assert [(p[i].x, p[i].y, p[i].n) for i in range(3)] == rows

@@ -15,8 +15,10 @@ struct BatchArray {
     void* y;
     int64_t n;
     int64_t first_block;
-    int64_t phase;  // -1: element path; else x and y sit this many elements past a vector
-                    // boundary and the array's blocks cover n + phase positions
+    int64_t phase;    // -1: element path; else x sits this many elements past a vector
+                      // boundary and the array's blocks cover n + phase positions
+    int64_t stage_y;  // 1: y sits at another phase than x; rows read as vectors are
+                      // written through the LDS stage as aligned vectors
 };
 
 // Kernel flavours: one array; one array cut into segments by offsets (heads
@@ -67,7 +69,7 @@ hipError_t launch_segment_table(const ScanArgs& a, int64_t tile_elems, hipStream
 // the same layout as the runtime.  High half: a fixed mark; then the size
 // of ScanArgs; low nibble: a revision for same-size layout changes.
 constexpr uint32_t kKernelAbiMark = 0x4C530000u;
-constexpr uint32_t kKernelAbi = kKernelAbiMark | (uint32_t(sizeof(ScanArgs)) << 4) | 2u;
+constexpr uint32_t kKernelAbi = kKernelAbiMark | (uint32_t(sizeof(ScanArgs)) << 4) | 3u;
 static_assert(sizeof(ScanArgs) < 4096, "the size of ScanArgs fits the tag");
 
 struct KernelEntry {

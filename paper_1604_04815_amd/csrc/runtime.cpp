@@ -216,9 +216,11 @@ void init_params_locked()
     // max / min batches: 512 x 8 fits one group per CU there too (int32 max
     // 4.75 -> 4.83 TB/s, int64 max 3.95 -> 4.37 at 1024 x 4)
     for (int o : {kI32Max, kI32Min, kI64Max, kI64Min, kF32Max, kF32Min}) g_params[kModeBatched][o] = t1024x4;
-    // (float32 max 4.39 -> 4.75); bf16 max / min fit two 512 x 8 groups: 3.45 -> 3.87
-    g_params[kModeBatched][kBF16Max] = t512x8g2;
-    g_params[kModeBatched][kBF16Min] = t512x8g2;
+    // (float32 max 4.39 -> 4.75); bf16 max / min too, since the y stage of
+    // arrays at another phase took their 512 x 8 kernel to 129 VGPRs (4096
+    // arrays: 1024 x 4 540 us, 256 x 16 two per CU 564 us)
+    g_params[kModeBatched][kBF16Max] = t1024x4;
+    g_params[kModeBatched][kBF16Min] = t1024x4;
     for (int m = 0; m < kNumModes; ++m)
         for (int o = 0; o < kNumOpCodes; ++o) g_default_params[m][o] = g_params[m][o];
     g_params_init = true;
@@ -657,11 +659,31 @@ int64_t alignment_phase(const KernelEntry& k, const void* x, const void* y)
     return ya % 16 == (ph * uintptr_t(k.out_bytes)) % 16 ? int64_t(ph) : -1;
 }
 
+// The path of one array of a batch: x's element phase when x is read with
+// vectors (-1: the element path).  *stage_y is set when y sits at another
+// phase than x, so that rows read as vectors are written through the LDS
+// stage; that needs 16-byte output vectors, else the array takes the element
+// path.
+int64_t batch_phase(const KernelEntry& k, const lscan_array& arr, bool* stage_y)
+{
+    *stage_y = false;
+    const int64_t ph = alignment_phase(k, arr.x, arr.y);
+    if (ph >= 0) return ph;
+    const uintptr_t xa = reinterpret_cast<uintptr_t>(arr.x), ya = reinterpret_cast<uintptr_t>(arr.y);
+    const uintptr_t vec_bytes = uintptr_t(k.in_bytes) * uintptr_t(k.elems_per_vec);
+    if (xa % uintptr_t(k.in_bytes) != 0 || ya % uintptr_t(k.out_bytes) != 0 ||
+        k.out_bytes * k.elems_per_vec != 16)
+        return -1;
+    *stage_y = true;
+    return int64_t((xa % vec_bytes) / uintptr_t(k.in_bytes));
+}
+
 // Blocks of one array of a batch: its n elements after its alignment phase.
 int64_t batch_blocks(const KernelEntry& k, const lscan_array& arr, int64_t L)
 {
     if (arr.n <= 0) return 0;
-    return (arr.n + std::max<int64_t>(alignment_phase(k, arr.x, arr.y), 0) + L - 1) / L;
+    bool stage_y;
+    return (arr.n + std::max<int64_t>(batch_phase(k, arr, &stage_y), 0) + L - 1) / L;
 }
 
 // Choose the kernel and grid, size the workspace, run the co-residency test
@@ -779,10 +801,12 @@ lscan_status plan_locked(const Request& r, int dev, Workspace* ws_fixed, hipStre
             ws->desc_host[i].y = r.arrays[i].y;
             ws->desc_host[i].n = r.arrays[i].n;
             ws->desc_host[i].first_block = first;
-            ws->desc_host[i].phase = alignment_phase(k, r.arrays[i].x, r.arrays[i].y);
+            bool stage_y = false;
+            ws->desc_host[i].phase = batch_phase(k, r.arrays[i], &stage_y);
+            ws->desc_host[i].stage_y = stage_y ? 1 : 0;
             first += batch_blocks(k, r.arrays[i], L);
         }
-        ws->desc_host[r.num_arrays] = BatchArray{nullptr, nullptr, 0, first, 0};
+        ws->desc_host[r.num_arrays] = BatchArray{nullptr, nullptr, 0, first, 0, 0};
         e = hipMemcpyAsync(ws->desc, ws->desc_host, desc_entries * sizeof(BatchArray), hipMemcpyHostToDevice,
                            stream);
         if (e != hipSuccess) return device_error(e);

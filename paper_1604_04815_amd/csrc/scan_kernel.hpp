@@ -325,8 +325,17 @@ struct ModeOps<BaseOp, kModeBatched> {
     using BlkOp = Seg<BaseOp>;
 };
 
+// Batches of int32 arrays run 512 x 8 with two workgroups per CU, so four
+// waves per SIMD: those kernels' registers are held to the 128 that allows
+// (the y stage of arrays at another phase would otherwise take them to 129;
+// the other types spill at this bound and run other shapes).
 template <class BaseOp, int T, int R, int MODE>
-__global__ void __launch_bounds__(T) scan_kernel(ScanArgs a)
+constexpr int kMinWavesPerSimd = (MODE == kModeBatched && T == 512 && R == 8 &&
+                                  std::is_same<typename BaseOp::In, int32_t>::value &&
+                                  sizeof(typename BaseOp::V) == 4) ? 4 : 1;
+
+template <class BaseOp, int T, int R, int MODE>
+__global__ void __launch_bounds__(T, (kMinWavesPerSimd<BaseOp, T, R, MODE>)) scan_kernel(ScanArgs a)
 {
     using EOp = typename ModeOps<BaseOp, MODE>::ElemOp;
     using BOp = typename ModeOps<BaseOp, MODE>::BlkOp;
@@ -347,9 +356,9 @@ __global__ void __launch_bounds__(T) scan_kernel(ScanArgs a)
         return;
     }
 
-    // plain and segmented scans whose y sits at another alignment phase than
-    // x: each wave stages one output row here to write it as aligned vectors
-    constexpr bool kStageY = (MODE == kModePlain || MODE == kModeSegmented) && E * sizeof(Out) == 16;
+    // arrays whose y sits at another alignment phase than x: each wave stages
+    // one output row here to write it as aligned vectors
+    constexpr bool kStageY = E * sizeof(Out) == 16;
     __shared__ __attribute__((aligned(16))) Out s_ystage[kStageY ? NWAVE : 1][kStageY ? ROW + E : 1];
     // plain and segmented scans reading 16-byte vectors: the next full block
     // of the workgroup is prefetched into LDS (each wave its own R rows of
@@ -416,6 +425,7 @@ __global__ void __launch_bounds__(T) scan_kernel(ScanArgs a)
     next_d.n = 0;
     next_d.first_block = 0;
     next_d.phase = 0;
+    next_d.stage_y = 0;
     auto find_array = [&](int64_t blk) {
         const CBatchArray* arr = (const CBatchArray*)(a.arrays);
         int64_t lo = arr_lo, hi = a.num_arrays;
@@ -432,6 +442,7 @@ __global__ void __launch_bounds__(T) scan_kernel(ScanArgs a)
         next_d.n = arr[lo].n;
         next_d.first_block = arr[lo].first_block;
         next_d.phase = arr[lo].phase;
+        next_d.stage_y = arr[lo].stage_y;
     };
     if constexpr (MODE == kModeBatched) {
         if (int64_t(blockIdx.x) < a.num_blocks) find_array(blockIdx.x);
@@ -495,6 +506,7 @@ __global__ void __launch_bounds__(T) scan_kernel(ScanArgs a)
                 n = d.n + ph;
                 tile0 = (i - d.first_block) * L;
                 block_head = (tile0 == 0) ? 1u : 0u;
+                svec = d.stage_y == 0;
             } else {
                 // arrays that start ph elements past a vector boundary run in
                 // virtual positions v = index + ph, so that every block but
@@ -796,9 +808,12 @@ __global__ void __launch_bounds__(T) scan_kernel(ScanArgs a)
                     }
                 }
                 const int64_t p = p_lane0 + int64_t(r) * ROW;
-                if ((p_full && p_svec) || ((p_vrow >> r) & 1u)) {
+                // rows read as vectors (a full block, or a whole row of an array's
+                // first or last block) are written as vectors too
+                const bool vec_row = p_full || ((p_vrow >> r) & 1u);
+                if (vec_row && p_svec) {
                     store_vector<Out, E>(p_y + p, out);
-                } else if (kStageY && p_full) {
+                } else if (kStageY && vec_row) {
                     // y at another phase than the grid: stage the wave's row
                     // at its offset from the aligned vector below it, then
                     // write whole aligned vectors (and the partial vectors at

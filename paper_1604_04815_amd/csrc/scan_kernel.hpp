@@ -360,6 +360,13 @@ __global__ void __launch_bounds__(T, (kMinWavesPerSimd<BaseOp, T, R, MODE>)) sca
     // one output row here to write it as aligned vectors
     constexpr bool kStageY = E * sizeof(Out) == 16;
     __shared__ __attribute__((aligned(16))) Out s_ystage[kStageY ? NWAVE : 1][kStageY ? ROW + E : 1];
+    // 32-byte lane outputs (int64 indices of 16-byte key vectors): each wave
+    // passes its row through LDS, so that every store instruction writes one
+    // contiguous 1 KiB span instead of 16 bytes at a 32-byte stride (which
+    // left lines half-written per instruction: 1.14x the output bytes reached
+    // HBM)
+    constexpr bool kStage32 = E * sizeof(Out) == 32;
+    __shared__ __attribute__((aligned(16))) u32x4 s_out32[kStage32 ? NWAVE : 1][kStage32 ? 128 : 1];
     // plain and segmented scans reading 16-byte vectors: the next full block
     // of the workgroup is prefetched into LDS (each wave its own R rows of
     // 1 KiB) while the current block is scanned, so a workgroup's loads stay
@@ -811,7 +818,20 @@ __global__ void __launch_bounds__(T, (kMinWavesPerSimd<BaseOp, T, R, MODE>)) sca
                 // rows read as vectors (a full block, or a whole row of an array's
                 // first or last block) are written as vectors too
                 const bool vec_row = p_full || ((p_vrow >> r) & 1u);
-                if (vec_row && p_svec) {
+                if (kStage32 && vec_row && p_svec) {
+                    // lane l's 32 bytes are 16-byte chunks 2l and 2l + 1 of the row;
+                    // store k writes chunks 64k .. 64k + 63, one per lane
+                    u32x4 w[2];
+                    __builtin_memcpy(w, out, 32);
+                    u32x4* stage = s_out32[kStage32 ? wave : 0];
+                    stage[2 * lane] = w[0];
+                    stage[2 * lane + 1] = w[1];
+                    wave_lds_sync();  // lanes read what other lanes wrote
+                    u32x4* dst = reinterpret_cast<u32x4*>(p_y + (p - int64_t(lane) * E));  // the row's first output
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) __builtin_nontemporal_store(stage[64 * h + lane], dst + 64 * h + lane);
+                    wave_lds_sync();  // the next row's stage writes come after every lane's reads
+                } else if (vec_row && p_svec) {
                     store_vector<Out, E>(p_y + p, out);
                 } else if (kStageY && vec_row) {
                     // y at another phase than the grid: stage the wave's row

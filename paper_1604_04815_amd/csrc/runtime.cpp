@@ -178,23 +178,25 @@ void init_params_locked()
     if (g_params_init) return;
     // measured on MI355X (shape x groups/CU sweep of the persistent scan).
     // Kernels reading 16-byte vectors prefetch each workgroup's next block into
-    // LDS; with that, one 1024 x 4 workgroup per CU measured best for 4-byte
-    // types (int32 add 2^28: 5.68 -> 6.05 TB/s; float32 add 2^27: 5.6 -> 6.0)
-    // and 256 x 16 with two per CU for int64 (5.39 -> 5.90)
-    const Params t512x8g2{1, 2}, t1024x4{4, 1}, t256x16g2{3, 2};
+    // LDS and fold windows copied into LDS a step earlier; with that, one
+    // workgroup of 16 waves per CU measured best: 1024 x 4 for 4-byte types
+    // (int32 add 2^28: 6.43 TB/s, 512 x 8 the same), 512 x 8 for int64
+    // (6.45 TB/s; 256 x 16 two per CU 5.7) and for the compensated sum, whose
+    // 1024 x 4 kernel spills (6.0 TB/s against 4.7)
+    const Params t512x8g2{1, 2}, t1024x4{4, 1}, t256x16g2{3, 2}, t512x8g1{1, 1};
     g_params[kModePlain][kI32Add] = t1024x4;
     g_params[kModePlain][kI32Max] = t1024x4;
     g_params[kModePlain][kI32Min] = t1024x4;
-    for (int o = kI64Add; o <= kI64Min; ++o) g_params[kModePlain][o] = t256x16g2;
+    for (int o = kI64Add; o <= kI64Min; ++o) g_params[kModePlain][o] = t512x8g1;
     g_params[kModePlain][kF32Add] = t1024x4;
-    g_params[kModePlain][kF32AddComp] = t1024x4;
+    g_params[kModePlain][kF32AddComp] = t512x8g1;
     g_params[kModePlain][kF32Max] = t1024x4;
     g_params[kModePlain][kF32Min] = t1024x4;
     g_params[kModePlain][kBF16Add] = t256x16g2;
-    g_params[kModePlain][kBF16AddComp] = t1024x4;
+    g_params[kModePlain][kBF16AddComp] = t512x8g1;  // 220 us at 2^27, 1024 x 4 226
     g_params[kModePlain][kBF16Max] = t256x16g2;
     g_params[kModePlain][kBF16Min] = t256x16g2;
-    const Params t1024x2{5, 1}, t512x8g1{1, 1};
+    const Params t1024x2{5, 1};
     for (int o = kI32ArgMax; o <= kF32ArgMin; ++o) g_params[kModePlain][o] = t1024x2;
     // the 32-bit-index argmax / argmin kernels prefetch too (int32 keys, 2^28:
     // 256 x 8 two per CU 773 us, 512 x 8 one per CU 677 us)
@@ -202,7 +204,10 @@ void init_params_locked()
     g_params[kModePlain][kI64ArgMaxS] = t1024x4;
     g_params[kModePlain][kI64ArgMinS] = t1024x4;
     for (int o = 0; o < kNumOpCodes; ++o) {
-        g_params[kModeSegmented][o] = t1024x4;  // with the per-block segment table (measured)
+        // with the per-block segment table; 512 x 8 (4096 segments, int32 add:
+        // 5.38 TB/s), whose kernels keep their registers where 1024 x 4 spills
+        const bool comp = o == kF32AddComp || o == kBF16AddComp;
+        g_params[kModeSegmented][o] = comp ? t1024x4 : t512x8g1;
         g_params[kModeBatched][o] = g_params[kModePlain][o];
         g_params[kModeCompact][o] = t1024x4;
     }

@@ -30,13 +30,17 @@
 //     kept as a launch option (ScanArgs::chain): block i waits for the
 //     inclusive prefix P(i - 1) that block i - 1 published, then publishes
 //     P(i).
-//   * Software pipeline: a block's prefix is resolved one round late.  The
-//     iteration that loads block i folds the window of the previous block
-//     i - B (whose aggregates were published a round earlier) while the
-//     loads are in flight, and stores block i - B; block i waits in
-//     registers as block-local values.  The last step, which only drains the
-//     pending block, is a separate instantiation so that inside the loop
-//     every load is consumed on every path.
+//   * Software pipeline: a block's prefix is resolved one round late.  Each
+//     step loads and scans block i and publishes A(i) before it waits for
+//     anything, then folds the window of the previous block i - B (whose
+//     aggregates were published a round earlier) and stores block i - B;
+//     block i waits in registers as block-local values.  The flag words of
+//     that window were copied into LDS at the end of the previous step, so
+//     their round trip through the memory system overlaps a whole step, and
+//     the next full block of the workgroup is prefetched into LDS while the
+//     current one is scanned.  The last step, which only drains the pending
+//     block, is a separate instantiation so that inside the loop every load
+//     is consumed on every path.
 //   * Intra-block global scan (Algorithm 5): each element becomes
 //     (P(i - 1) (+) (wave prefix (+) row prefix (+) lane prefix)) (+) its
 //     in-lane scan value -- the block prefix joins each lane-row once, then
@@ -118,7 +122,25 @@ __device__ __forceinline__ void lds_load16(const void* g, uint32_t lds_byte)
     asm volatile("s_mov_b32 m0, %1\n\tglobal_load_lds_dwordx4 %0, off nt" ::"v"(g), "s"(m0) : "memory");
 }
 
+// The same load with the cache policy of agent-scope atomic loads (sc1): flag
+// words published by workgroups on other XCDs are read from where those
+// writes land, never from a stale line of this XCD's L2.
+__device__ __forceinline__ void lds_load16_coherent(const void* g, uint32_t lds_byte)
+{
+    const uint32_t m0 = __builtin_amdgcn_readfirstlane(lds_byte);
+    asm volatile("s_mov_b32 m0, %1\n\tglobal_load_lds_dwordx4 %0, off sc1" ::"v"(g), "s"(m0) : "memory");
+}
+
 __device__ __forceinline__ void vmem_drain() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+// Wait until at most N vector memory operations of the wave are outstanding.
+// They complete in issue order, so with N stores issued after a prefetch this
+// waits for the prefetch (and everything before it) but not for those stores.
+template <int N>
+__device__ __forceinline__ void vmem_wait_keep()
+{
+    static_assert(N >= 0 && N < 64, "vmcnt range");
+    asm volatile("s_waitcnt vmcnt(%0)" ::"n"(N) : "memory");
+}
 // Make the compiler complete the loads that produced v here (it must have
 // the value in registers before the empty statement), so that its waits
 // for them stay on the path that issued them.
@@ -132,6 +154,43 @@ __device__ __forceinline__ void complete_loads(T (&v)[N])
     __builtin_memcpy(v, &w, 16);
 }
 __device__ __forceinline__ void lds_reads_drain() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
+
+// ---------------------------------------------------------------------------
+// Lane-blocked rows.  Operators whose combine is expensive (the compensated
+// sums) give each lane R consecutive 16-byte vectors of the block instead of
+// one vector per wave-row: a lane then scans R * E consecutive elements in
+// registers and the wave needs one cross-lane scan per block instead of one
+// per row.  The loads still read whole 1 KiB spans (into LDS), and the
+// outputs go back through LDS to leave as 1 KiB spans too.  Within a wave's
+// LDS rows, chunk c (16 bytes, in memory order) sits in slot lds_slot(c): a
+// permutation inside each aligned group of 64 chunks under which the
+// lane-blocked accesses (chunks 4l .. 4l + 3 of lane l) and the striped ones
+// (chunk 64r + l) both run without bank conflicts (measured: 16-byte reads
+// are served 16 lanes at a time, writes 8 at a time; the blocked accesses
+// without the permutation take 4 times the LDS cycles).  lds_chunk inverts it.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int lds_slot(int c)
+{
+    return c ^ (((c >> 4) & 1) | (((c >> 3) & 1) << 1) | (((c >> 5) & 1) << 3));
+}
+__device__ __forceinline__ int lds_chunk(int s)
+{
+    return s ^ (((s >> 4) & 1) | ((((s >> 3) ^ (s >> 5)) & 1) << 1) | (((s >> 5) & 1) << 3));
+}
+// The lane id as a value the compiler cannot see through: slots computed from
+// it where they are used are not hoisted out of the block loop, where they
+// would hold registers across it (the compensated kernels at 1024 x 4 spilled
+// them, and every reload inside the loop then waited for the prefetch too).
+__device__ __forceinline__ int opaque_lane()
+{
+    int l = static_cast<int>(threadIdx.x & 63u);
+    asm volatile("" : "+v"(l));
+    return l;
+}
+template <class Op, class = void>
+struct blocked_lanes : std::false_type {};
+template <class Op>
+struct blocked_lanes<Op, std::void_t<decltype(Op::kBlockedLanes)>> : std::bool_constant<Op::kBlockedLanes> {};
 
 // ---------------------------------------------------------------------------
 // Flag slots: one 64-bit word per 32 bits of payload, (tag << 32) | data.
@@ -183,13 +242,17 @@ __device__ __forceinline__ uint64_t await_word(const uint64_t* p, uint64_t w, ui
 // Fold of the aggregates in slots [lo, lo + cnt) in index order, read by one
 // wave: 64 consecutive slots per load round, each round reduced with the
 // cross-lane scan (a fixed tree), rounds folded left to right.
-template <class Op>
-__device__ typename Op::V window_fold(const uint64_t* slots, int64_t lo, int64_t cnt, uint32_t tag,
-                                      uint64_t limit, const uint32_t* abort_word, int lane, bool& ok)
+// first(j, k) gives the first reading of word k of window slot j (the
+// flag word itself, or a copy fetched earlier); words not yet published are
+// re-read from the slots.  QC rounds of 64 slots are read at once (8 KiB of
+// flag words from global memory, 4 KiB from an LDS copy).
+template <class Op, int QC, class First>
+__device__ typename Op::V window_fold_from(First first, const uint64_t* slots, int64_t lo, int64_t cnt,
+                                           uint32_t tag, uint64_t limit, const uint32_t* abort_word, int lane,
+                                           bool& ok)
 {
     using V = typename Op::V;
     constexpr int W = sizeof(V) / 4;
-    constexpr int QC = (W == 1) ? 8 : (W == 2) ? 4 : 2;  // load rounds in flight
     V acc = Op::identity();
     for (int64_t q0 = 0; q0 < cnt; q0 += 64 * QC) {
         uint64_t w[QC][W];
@@ -197,8 +260,7 @@ __device__ typename Op::V window_fold(const uint64_t* slots, int64_t lo, int64_t
         for (int q = 0; q < QC; ++q) {
             const int64_t j = q0 + 64 * q + lane;
 #pragma unroll
-            for (int k = 0; k < W; ++k)
-                w[q][k] = (j < cnt) ? slot_load(slots + (lo + j) * W + k) : (uint64_t(tag) << 32);
+            for (int k = 0; k < W; ++k) w[q][k] = (j < cnt) ? first(j, k) : (uint64_t(tag) << 32);
         }
 #pragma unroll
         for (int q = 0; q < QC; ++q) {
@@ -226,6 +288,15 @@ __device__ typename Op::V window_fold(const uint64_t* slots, int64_t lo, int64_t
         }
     }
     return acc;
+}
+template <class Op>
+__device__ typename Op::V window_fold(const uint64_t* slots, int64_t lo, int64_t cnt, uint32_t tag,
+                                      uint64_t limit, const uint32_t* abort_word, int lane, bool& ok)
+{
+    constexpr int W = sizeof(typename Op::V) / 4;
+    constexpr int QC = (W == 1) ? 8 : (W == 2) ? 4 : 2;
+    auto first = [&](int64_t j, int k) { return slot_load(slots + (lo + j) * W + k); };
+    return window_fold_from<Op, QC>(first, slots, lo, cnt, tag, limit, abort_word, lane, ok);
 }
 
 // The paper's hand-off (Algorithm 4): wait for the inclusive prefix that the
@@ -379,6 +450,14 @@ __global__ void __launch_bounds__(T, (kMinWavesPerSimd<BaseOp, T, R, MODE>)) sca
     constexpr bool kPrefetch = (MODE == kModePlain || MODE == kModeSegmented) && E * sizeof(In) == 16;
     constexpr uint32_t kRowBytes = 1024u;
     __shared__ __attribute__((aligned(16))) u32x4 s_pf[kPrefetch ? T * R : 1];
+    // lane-blocked rows (lds_slot): plain scans of the operators that ask for them.
+    // Lane l's first element sits kLaneElems after lane l - 1's, and its rows
+    // kRowStep apart; s_tr turns each wave's outputs back into 1 KiB spans
+    constexpr bool kBlocked =
+        kPrefetch && MODE == kModePlain && blocked_lanes<BaseOp>::value && E * sizeof(Out) == 16;
+    constexpr int64_t kLaneElems = kBlocked ? int64_t(R) * E : E;
+    constexpr int64_t kRowStep = kBlocked ? E : ROW;
+    __shared__ __attribute__((aligned(16))) u32x4 s_tr[kBlocked ? T * R : 1];
     __shared__ V s_wave_total[2][NWAVE];
     __shared__ VB s_block_prefix[2];
     __shared__ int s_abort[2];
@@ -405,7 +484,8 @@ __global__ void __launch_bounds__(T, (kMinWavesPerSimd<BaseOp, T, R, MODE>)) sca
     // keep each value's head flag as a bit of p_seen (a head lies at or
     // before it inside the lane's vector)
     using PV = typename BaseOp::V;
-    PV pe[R][E];
+    PV pe[kBlocked ? 1 : R][E];
+    In p_raw[kBlocked ? R : 1][E];  // lane-blocked rows: the raw inputs
     uint32_t p_seen[R];
     V p_lp[R];
     VB p_agg = BOp::identity();         // wave 0: the pending block's aggregate
@@ -414,8 +494,39 @@ __global__ void __launch_bounds__(T, (kMinWavesPerSimd<BaseOp, T, R, MODE>)) sca
     // the prefetch: this wave's LDS rows, and whether they hold the block to scan next
     const uint32_t pf_lds = kPrefetch ? lds_address(&s_pf[0]) + uint32_t(wave) * R * kRowBytes : 0u;
     bool pf_have = false;
+    // the previous step wrote its pending block with at least R vector stores per
+    // wave, all issued after the prefetch that the next step waits for
+    bool pf_then_stores = false;
+    // The flag words of the window that the next step folds, copied into LDS by
+    // wave 0 at the end of a step (so the round trip to them, about 2 us under a
+    // full memory load, overlaps a whole step); windows of up to 8 KiB.
+    constexpr int kFlagChunks = 512;
+    __shared__ __attribute__((aligned(16))) u32x4 s_flags[kFlagChunks];
+    const uint32_t flags_lds = lds_address(&s_flags[0]);
+    bool flags_have = false;  // wave 0: s_flags holds the pending block's window
+    int flags_shift = 0;      // the window's first word is word flags_shift of s_flags
+    // wave 0: copy the flag words of slots [lo, lo + cnt) into s_flags, in 16-byte
+    // chunks from the aligned chunk that holds the first word (every chunk read
+    // lies inside the slot array: it starts 16-byte aligned and holds the slot of
+    // the block whose window this is, right after the window)
+    auto flags_fetch = [&](int64_t lo, int64_t cnt) -> bool {
+        const uintptr_t ab = reinterpret_cast<uintptr_t>(a.slots + lo * W);
+        const int shift = int((ab & 15u) >> 3);
+        const int64_t chunks = (int64_t(shift) * 8 + cnt * (W * 8) + 15) >> 4;
+        if ((reinterpret_cast<uintptr_t>(a.slots) & 15u) != 0 || chunks > kFlagChunks) return false;
+        const char* c0 = reinterpret_cast<const char*>(ab - uintptr_t(shift) * 8);
+        lds_reads_drain();  // the previous window's words are read
+        for (int64_t d = 0; d * 64 < chunks; ++d) {
+            const int64_t c = (d * 64 + lane < chunks) ? d * 64 + lane : chunks - 1;
+            lds_load16_coherent(c0 + c * 16, flags_lds + uint32_t(d) * 1024u);
+        }
+        flags_shift = shift;
+        return true;
+    };
     auto prefetch = [&](const In* xg, int64_t t0) {  // xg: the array's grid origin, t0: the block's first position
-        const In* xs = xg + t0 + int64_t(wave) * (R * ROW) + int64_t(lane) * E;
+        // (lane-blocked rows: slot 64r + l of the wave's rows receives chunk 64r + lds_chunk(l))
+        const int src = kBlocked ? lds_chunk(lane) : lane;
+        const In* xs = xg + t0 + int64_t(wave) * (R * ROW) + int64_t(src) * E;
 #pragma unroll
         for (int r = 0; r < R; ++r) lds_load16(xs + int64_t(r) * ROW, pf_lds + uint32_t(r) * kRowBytes);
     };
@@ -528,18 +639,24 @@ __global__ void __launch_bounds__(T, (kMinWavesPerSimd<BaseOp, T, R, MODE>)) sca
                 vec_ok = a.vec_ok != 0;
                 svec = a.store_vec != 0;
             }
-            lane0 = tile0 + int64_t(wave) * (R * ROW) + int64_t(lane) * E;
+            lane0 = tile0 + int64_t(wave) * (R * ROW) + int64_t(lane) * kLaneElems;
             full = vec_ok && (tile0 + L <= n) && (tile0 >= ph);
             if (full) {
                 if constexpr (kPrefetch) {
                     // a full block arrives through LDS: prefetched during the previous
                     // step (or, after a partial block, loaded that way now), so no
                     // data load of the compiler's own is ever pending past this point
-                    if (!pf_have) prefetch(x, tile0);
-                    vmem_drain();
+                    if (pf_have && pf_then_stores) {
+                        vmem_wait_keep<R>();
+                    } else {
+                        if (!pf_have) prefetch(x, tile0);
+                        vmem_drain();
+                    }
+                    const int lb = kBlocked ? opaque_lane() * R : 0;
 #pragma unroll
                     for (int r = 0; r < R; ++r) {
-                        const u32x4 w = s_pf[(wave * R + r) * 64 + lane];
+                        const int c = kBlocked ? lds_slot(lb + r) : r * 64 + lane;
+                        const u32x4 w = s_pf[wave * R * 64 + c];
                         __builtin_memcpy(raw[r], &w, 16);
                     }
                     lds_reads_drain();  // the rows are read before the next prefetch overwrites them
@@ -622,41 +739,71 @@ __global__ void __launch_bounds__(T, (kMinWavesPerSimd<BaseOp, T, R, MODE>)) sca
             }
         }
 
-        // -- 2. inter-block communication for the pending block (wave 0)
-        if (have_pend && wave == 0) {
-            const int64_t j = p_i;
-            bool ok = true;
-            VB prefix;  // P(j - 1)
-            if (a.chain) {
-                // the paper's chain: P(j - 1) from block j - 1's slot, then P(j) published
-                prefix = (j == 0) ? BOp::identity() : chain_prefix<BOp>(a.slots + (j - 1) * W, tag, a.spin_limit,
-                                                                        a.ctrl + 3, lane, ok);
-                publish_slot(a.slots + j * W, BOp::combine(prefix, p_agg), tag, lane);
-            } else {
-                const int64_t cnt = (j < B - 1) ? j : (B - 1);
-                const VB win = window_fold<BOp>(a.slots, j - cnt, cnt, tag, a.spin_limit, a.ctrl + 3, lane, ok);
-                prefix = BOp::combine(carry, win);
-                carry = BOp::combine(prefix, p_agg);  // P(j)
-            }
-            const bool abort = __ballot(!ok) != 0;
-            if (lane == 0) {
-                s_block_prefix[parity] = prefix;
-                s_abort[parity] = abort ? 1 : 0;
-                if (abort) {
-                    __hip_atomic_store(a.ctrl + 2, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    __hip_atomic_store(a.ctrl + 3, tag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    if (a.status_host)
-                        __hip_atomic_store(a.status_host, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        // -- 2. inter-block communication for the pending block (wave 0).  Kernels
+        //       that prefetch run it after the new block's aggregate is out (so no
+        //       workgroup waits on this one's waits), on flag words copied into LDS
+        //       a step earlier; the others run it while their data loads are in
+        //       flight, on flag words read then.
+        auto resolve_pending = [&](bool pf_now) {
+            if (have_pend && wave == 0) {
+                const int64_t j = p_i;
+                bool ok = true;
+                VB prefix;  // P(j - 1)
+                if (a.chain) {
+                    // the paper's chain: P(j - 1) from block j - 1's slot, then P(j) published
+                    prefix = (j == 0) ? BOp::identity() : chain_prefix<BOp>(a.slots + (j - 1) * W, tag, a.spin_limit,
+                                                                            a.ctrl + 3, lane, ok);
+                    publish_slot(a.slots + j * W, BOp::combine(prefix, p_agg), tag, lane);
+                } else {
+                    const int64_t cnt = (j < B - 1) ? j : (B - 1);
+                    VB win;
+                    if (flags_have) {
+                        // the copy made at the end of the previous step is complete once
+                        // no more than the operations issued after it are outstanding that
+                        // this step may still have in flight: its R prefetch loads and the
+                        // new block's aggregate (data loads of this step were waited for)
+                        const bool published = have_new;
+                        if (pf_now && published)
+                            vmem_wait_keep<R + 1>();
+                        else if (pf_now)
+                            vmem_wait_keep<R>();
+                        else if (published)
+                            vmem_wait_keep<1>();
+                        else
+                            vmem_drain();
+                        const uint64_t* fw = reinterpret_cast<const uint64_t*>(&s_flags[0]) + flags_shift;
+                        auto first = [&](int64_t q, int k) { return fw[q * W + k]; };
+                        constexpr int QC = (W == 1) ? 4 : (W == 2) ? 2 : 1;
+                        win = window_fold_from<BOp, QC>(first, a.slots, j - cnt, cnt, tag, a.spin_limit, a.ctrl + 3,
+                                                        lane, ok);
+                    } else {
+                        win = window_fold<BOp>(a.slots, j - cnt, cnt, tag, a.spin_limit, a.ctrl + 3, lane, ok);
+                    }
+                    prefix = BOp::combine(carry, win);
+                    carry = BOp::combine(prefix, p_agg);  // P(j)
+                }
+                const bool abort = __ballot(!ok) != 0;
+                if (lane == 0) {
+                    s_block_prefix[parity] = prefix;
+                    s_abort[parity] = abort ? 1 : 0;
+                    if (abort) {
+                        __hip_atomic_store(a.ctrl + 2, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        __hip_atomic_store(a.ctrl + 3, tag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        if (a.status_host)
+                            __hip_atomic_store(a.status_host, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                    }
                 }
             }
-        }
+        };
+        if constexpr (!kPrefetch) resolve_pending(false);
 
         // the next full block of this workgroup goes out into LDS now, after every
-        // wait of this step on data or flag words: vector memory operations
-        // complete in issue order, so a later wait on a load of the compiler's own
-        // would also wait for the prefetch
+        // wait of this step on data: vector memory operations complete in issue
+        // order, so a later wait on a load of the compiler's own would also wait
+        // for the prefetch
         // (after a partial block, only once its own loads are done: below)
         bool pf_late = false;
+        bool pf_now = false;  // R prefetch loads per wave issued in this step
         if constexpr (kPrefetch) {
             const In* xg;
             int64_t t0;
@@ -664,6 +811,7 @@ __global__ void __launch_bounds__(T, (kMinWavesPerSimd<BaseOp, T, R, MODE>)) sca
                 if (full) {
                     prefetch(xg, t0);
                     pf_have = true;
+                    pf_now = true;
                 } else {
                     pf_late = true;
                 }
@@ -676,15 +824,16 @@ __global__ void __launch_bounds__(T, (kMinWavesPerSimd<BaseOp, T, R, MODE>)) sca
         V row_prefix[R];
         if (have_new) {
             if (full) {
+                // (lane-blocked rows keep the raw inputs: lifted below)
 #pragma unroll
-                for (int r = 0; r < R; ++r)
+                for (int r = 0; r < R && !kBlocked; ++r)
 #pragma unroll
                     for (int k = 0; k < E; ++k) {
                         if constexpr (MODE == kModeSegmented)
-                            e[r][k] = EOp::make(lift_elem<BaseOp>(raw[r][k], lane0 + int64_t(r) * ROW + k - ph),
+                            e[r][k] = EOp::make(lift_elem<BaseOp>(raw[r][k], lane0 + int64_t(r) * kRowStep + k - ph),
                                                 (head[r] >> k) & 1u);
                         else
-                            e[r][k] = lift_elem<BaseOp>(raw[r][k], lane0 + int64_t(r) * ROW + k - ph);
+                            e[r][k] = lift_elem<BaseOp>(raw[r][k], lane0 + int64_t(r) * kRowStep + k - ph);
                     }
             } else {
 #pragma unroll
@@ -704,13 +853,18 @@ __global__ void __launch_bounds__(T, (kMinWavesPerSimd<BaseOp, T, R, MODE>)) sca
                     In xv[E];
 #pragma unroll
                     for (int k = 0; k < E; ++k) {
-                        const int64_t p = lane0 + int64_t(r) * ROW + k;
+                        const int64_t p = lane0 + int64_t(r) * kRowStep + k;
                         xv[k] = (p < n && p >= ph) ? x[p] : In{};
                     }
                     if constexpr (kPrefetch) complete_loads(xv);
+                    if constexpr (kBlocked) {  // a zero input word lifts to the identity
+#pragma unroll
+                        for (int k = 0; k < E; ++k) raw[r][k] = xv[k];
+                        continue;
+                    }
 #pragma unroll
                     for (int k = 0; k < E; ++k) {
-                        const int64_t p = lane0 + int64_t(r) * ROW + k;
+                        const int64_t p = lane0 + int64_t(r) * kRowStep + k;
                         if (p < n && p >= ph) {
                             if constexpr (MODE == kModeSegmented)
                                 e[r][k] = EOp::make(lift_elem<BaseOp>(xv[k], p - ph), (head[r] >> k) & 1u);
@@ -729,28 +883,57 @@ __global__ void __launch_bounds__(T, (kMinWavesPerSimd<BaseOp, T, R, MODE>)) sca
                     full_src(i + B, xg, t0);
                     prefetch(xg, t0);
                     pf_have = true;
+                    pf_now = true;
                 }
             }
+            if constexpr (!kBlocked) {
 #pragma unroll
-            for (int r = 0; r < R; ++r)
+                for (int r = 0; r < R; ++r)
 #pragma unroll
-                for (int k = 1; k < E; ++k) e[r][k] = EOp::combine(e[r][k - 1], e[r][k]);
-            V row_total[R];
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const V sc = wave_inclusive_scan<EOp>(e[r][E - 1]);
-                row_total[r] = read_lane(sc, 63);
-                lane_prefix[r] = wave_shift_right<EOp>(sc);
+                    for (int k = 1; k < E; ++k) e[r][k] = EOp::combine(e[r][k - 1], e[r][k]);
             }
-            row_prefix[0] = EOp::identity();
+            if constexpr (kBlocked) {
+                // the lane's rows are consecutive: their totals (the scan inside
+                // each row is redone from the raw inputs at the fix-up, which keeps
+                // the pending block in half the registers), their running totals,
+                // then one cross-lane scan of the lane totals.  lane_prefix[0] holds
+                // the lanes before this one, lane_prefix[r] (r > 0) this lane's rows
+                // before r
+                V run = EOp::identity();
 #pragma unroll
-            for (int r = 1; r < R; ++r) row_prefix[r] = EOp::combine(row_prefix[r - 1], row_total[r - 1]);
-            // -- intra-block local scan: wave totals through LDS
-            if (lane == 0) s_wave_total[parity][wave] = EOp::combine(row_prefix[R - 1], row_total[R - 1]);
+                for (int r = 0; r < R; ++r) {
+                    V t = lift_elem<BaseOp>(raw[r][0], lane0 + int64_t(r) * kRowStep - ph);
+#pragma unroll
+                    for (int k = 1; k < E; ++k)
+                        t = EOp::combine(t, lift_elem<BaseOp>(raw[r][k], lane0 + int64_t(r) * kRowStep + k - ph));
+                    if (r == 0) {
+                        run = t;
+                    } else {
+                        lane_prefix[r] = run;
+                        run = EOp::combine(run, t);
+                    }
+                }
+                const V sc = wave_inclusive_scan<EOp>(run);
+                lane_prefix[0] = wave_shift_right<EOp>(sc);
+                const V wave_total = read_lane(sc, 63);
+                if (lane == 0) s_wave_total[parity][wave] = wave_total;
+            } else {
+                V row_total[R];
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const V sc = wave_inclusive_scan<EOp>(e[r][E - 1]);
+                    row_total[r] = read_lane(sc, 63);
+                    lane_prefix[r] = wave_shift_right<EOp>(sc);
+                }
+                row_prefix[0] = EOp::identity();
+#pragma unroll
+                for (int r = 1; r < R; ++r) row_prefix[r] = EOp::combine(row_prefix[r - 1], row_total[r - 1]);
+                // -- intra-block local scan: wave totals through LDS
+                if (lane == 0) s_wave_total[parity][wave] = EOp::combine(row_prefix[R - 1], row_total[R - 1]);
+            }
         }
 
-        __syncthreads();  // wave totals of the new block and the pending block's prefix are visible
-        if (have_pend && s_abort[parity]) return false;
+        __syncthreads();  // wave totals of the new block (and, without the prefetch, the pending block's prefix) are visible
 
         // -- 4. the new block's aggregate (published by wave 0) and its block-local
         //       scan: wave prefix, row prefix and lane prefix folded into each value,
@@ -771,6 +954,12 @@ __global__ void __launch_bounds__(T, (kMinWavesPerSimd<BaseOp, T, R, MODE>)) sca
             }
         }
 
+        if constexpr (kPrefetch) {
+            resolve_pending(pf_now);
+            __syncthreads();  // the pending block's prefix is visible
+        }
+        if (have_pend && s_abort[parity]) return false;
+
         // -- 5. intra-block global scan and one coalesced store per vector, for the pending block:
         //       the block prefix joins each row's lane prefix once, then each element
         //       (inclusive or exclusive is chosen once per block: the flag is uniform,
@@ -782,39 +971,11 @@ __global__ void __launch_bounds__(T, (kMinWavesPerSimd<BaseOp, T, R, MODE>)) sca
                 prefix = p_block_head ? EOp::identity() : s_block_prefix[parity].v;
             else
                 prefix = s_block_prefix[parity];
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const V q = EOp::combine(prefix, p_lp[r]);  // everything before this lane's vector
-                V ev[E];
-#pragma unroll
-                for (int k = 0; k < E; ++k) {
-                    if constexpr (MODE == kModeSegmented)
-                        ev[k] = EOp::make(pe[r][k], (p_seen[r] >> k) & 1u);
-                    else
-                        ev[k] = pe[r][k];
-                }
-                Out out[E];
-#pragma unroll
-                for (int k = 0; k < E; ++k) {
-                    if constexpr (MODE == kModeSegmented) {
-                        // a head inside the lane's vector at or before the element: its value alone
-                        if constexpr (!EXCL) {
-                            out[k] = ev[k].f ? BaseOp::lower(ev[k].v) : finish_of<BaseOp>(q.v, ev[k].v);
-                        } else if (k == 0) {
-                            out[k] = (p_head[r] & 1u) ? BaseOp::lower(BaseOp::identity()) : BaseOp::lower(q.v);
-                        } else {
-                            out[k] = ((p_head[r] >> k) & 1u) ? BaseOp::lower(BaseOp::identity())
-                                     : ev[k - 1].f          ? BaseOp::lower(ev[k - 1].v)
-                                                            : finish_of<BaseOp>(q.v, ev[k - 1].v);
-                        }
-                    } else {
-                        if constexpr (!EXCL)
-                            out[k] = finish_of<BaseOp>(q, ev[k]);
-                        else
-                            out[k] = (k == 0) ? BaseOp::lower(q) : finish_of<BaseOp>(q, ev[k - 1]);
-                    }
-                }
-                const int64_t p = p_lane0 + int64_t(r) * ROW;
+            // lane-blocked rows: the lane's first chunk, and its slot in a striped row
+            const int tb = kBlocked ? opaque_lane() * R : 0;
+            const int ts = kBlocked ? lds_slot(opaque_lane()) : 0;
+            // one row of outputs (lane vector r, first position p) to y
+            auto store_row = [&](int r, const Out (&out)[E], int64_t p) __attribute__((always_inline)) {
                 // rows read as vectors (a full block, or a whole row of an array's
                 // first or last block) are written as vectors too
                 const bool vec_row = p_full || ((p_vrow >> r) & 1u);
@@ -872,6 +1033,61 @@ __global__ void __launch_bounds__(T, (kMinWavesPerSimd<BaseOp, T, R, MODE>)) sca
                     for (int k = 0; k < E; ++k)
                         if (p + k < p_n && p + k >= p_ph) p_y[p + k] = out[k];
                 }
+            };
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const V q = EOp::combine(prefix, p_lp[r]);  // everything before this lane's vector
+                V ev[E];
+#pragma unroll
+                for (int k = 0; k < E; ++k) {
+                    if constexpr (MODE == kModeSegmented)
+                        ev[k] = EOp::make(pe[r][k], (p_seen[r] >> k) & 1u);
+                    else if constexpr (kBlocked) {  // the in-row scan, again from the raw inputs
+                        const V xk = lift_elem<BaseOp>(p_raw[r][k], p_lane0 + int64_t(r) * kRowStep + k - p_ph);
+                        ev[k] = (k == 0) ? xk : EOp::combine(ev[k - 1], xk);
+                    } else
+                        ev[k] = pe[r][k];
+                }
+                Out out[E];
+#pragma unroll
+                for (int k = 0; k < E; ++k) {
+                    if constexpr (MODE == kModeSegmented) {
+                        // a head inside the lane's vector at or before the element: its value alone
+                        if constexpr (!EXCL) {
+                            out[k] = ev[k].f ? BaseOp::lower(ev[k].v) : finish_of<BaseOp>(q.v, ev[k].v);
+                        } else if (k == 0) {
+                            out[k] = (p_head[r] & 1u) ? BaseOp::lower(BaseOp::identity()) : BaseOp::lower(q.v);
+                        } else {
+                            out[k] = ((p_head[r] >> k) & 1u) ? BaseOp::lower(BaseOp::identity())
+                                     : ev[k - 1].f          ? BaseOp::lower(ev[k - 1].v)
+                                                            : finish_of<BaseOp>(q.v, ev[k - 1].v);
+                        }
+                    } else {
+                        if constexpr (!EXCL)
+                            out[k] = finish_of<BaseOp>(q, ev[k]);
+                        else
+                            out[k] = (k == 0) ? BaseOp::lower(q) : finish_of<BaseOp>(q, ev[k - 1]);
+                    }
+                }
+                if constexpr (kBlocked) {  // through LDS: lane-blocked in, striped out
+                    u32x4 w;
+                    __builtin_memcpy(&w, out, 16);
+                    s_tr[wave * R * 64 + lds_slot(tb + r)] = w;
+                } else {
+                    store_row(r, out, p_lane0 + int64_t(r) * ROW);
+                }
+            }
+            if constexpr (kBlocked) {
+                wave_lds_sync();  // lanes read what other lanes wrote
+                const int64_t p0 = p_lane0 - int64_t(lane) * (kLaneElems - E);  // striped: lane l's vector of row r
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const u32x4 w = s_tr[wave * R * 64 + r * 64 + ts];  // chunk 64r + l
+                    Out out[E];
+                    __builtin_memcpy(out, &w, 16);
+                    store_row(r, out, p0 + int64_t(r) * ROW);
+                }
+                wave_lds_sync();  // the next block's writes come after every lane's reads
             }
         };
         if (have_pend) {
@@ -879,6 +1095,17 @@ __global__ void __launch_bounds__(T, (kMinWavesPerSimd<BaseOp, T, R, MODE>)) sca
                 fix_up(std::true_type{});
             else
                 fix_up(std::false_type{});
+        }
+        // full blocks with y at the grid's phase leave through one vector store per
+        // row (two for 32-byte lane outputs), after any prefetch of this step
+        pf_then_stores = have_pend && p_full && p_svec;
+        // the window of the new block, for the next step's fold
+        if (kPrefetch && wave == 0) {
+            flags_have = false;
+            if (have_new && !a.chain) {
+                const int64_t cnt = (i < B - 1) ? i : (B - 1);
+                if (cnt > 0) flags_have = flags_fetch(i - cnt, cnt);
+            }
         }
 
         // -- 6. the new block becomes the pending one
@@ -894,11 +1121,16 @@ __global__ void __launch_bounds__(T, (kMinWavesPerSimd<BaseOp, T, R, MODE>)) sca
             p_full = full;
             p_block_head = block_head;
             p_agg = agg;
+            V wl = EOp::identity();
+            if constexpr (kBlocked) wl = EOp::combine(wave_prefix, lane_prefix[0]);  // waves and lanes before
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 p_head[r] = head[r];
                 // local prefix of this lane's row: waves before, rows before, lanes before
-                p_lp[r] = EOp::combine(EOp::combine(wave_prefix, row_prefix[r]), lane_prefix[r]);
+                if constexpr (kBlocked)
+                    p_lp[r] = (r == 0) ? wl : EOp::combine(wl, lane_prefix[r]);
+                else
+                    p_lp[r] = EOp::combine(EOp::combine(wave_prefix, row_prefix[r]), lane_prefix[r]);
                 if constexpr (MODE == kModeSegmented) {
                     uint32_t seen = 0;
 #pragma unroll
@@ -907,6 +1139,9 @@ __global__ void __launch_bounds__(T, (kMinWavesPerSimd<BaseOp, T, R, MODE>)) sca
                         seen |= (e[r][k].f ? 1u : 0u) << k;
                     }
                     p_seen[r] = seen;
+                } else if constexpr (kBlocked) {
+#pragma unroll
+                    for (int k = 0; k < E; ++k) p_raw[r][k] = raw[r][k];
                 } else {
 #pragma unroll
                     for (int k = 0; k < E; ++k) pe[r][k] = e[r][k];
@@ -921,7 +1156,7 @@ __global__ void __launch_bounds__(T, (kMinWavesPerSimd<BaseOp, T, R, MODE>)) sca
     for (; i < a.num_blocks; i += B, parity ^= 1)
         if (!(live = step(std::true_type{}, i))) break;
     if (live && have_pend) step(std::false_type{}, i);
-    if constexpr (kPrefetch) vmem_drain();  // no LDS load outlives the workgroup
+    vmem_drain();  // no load into LDS outlives the workgroup
 
     // Every workgroup counts itself out; the last one advances the epoch so
     // the next launch on this workspace uses a fresh tag (no memset needed).

@@ -207,6 +207,8 @@ __device__ __forceinline__ F32Pair two_sum_combine(F32Pair a, F32Pair b)
 struct AddF32Comp {
     using In = uint32_t; using V = F32Pair; using Out = float;
     static constexpr int E = 4;
+    // a lane scans R consecutive vectors (a zero input word lifts to an identity)
+    static constexpr bool kBlockedLanes = true;
     __device__ static V identity() { return F32Pair{0.0f, 0.0f}; }
     __device__ static V combine(V a, V b) { return two_sum_combine(a, b); }
     __device__ static V lift(In x) { return F32Pair{bits_to_f32(x), -0.0f}; }

@@ -183,7 +183,7 @@ void init_params_locked()
     // (int32 add 2^28: 6.43 TB/s, 512 x 8 the same), 512 x 8 for int64
     // (6.45 TB/s; 256 x 16 two per CU 5.7) and for the compensated sum, whose
     // 1024 x 4 kernel spills (6.0 TB/s against 4.7)
-    const Params t512x8g2{1, 2}, t1024x4{4, 1}, t256x16g2{3, 2}, t512x8g1{1, 1};
+    const Params t512x8g2{1, 2}, t1024x4{4, 1}, t512x8g1{1, 1};
     g_params[kModePlain][kI32Add] = t1024x4;
     g_params[kModePlain][kI32Max] = t1024x4;
     g_params[kModePlain][kI32Min] = t1024x4;
@@ -192,10 +192,13 @@ void init_params_locked()
     g_params[kModePlain][kF32AddComp] = t512x8g1;
     g_params[kModePlain][kF32Max] = t1024x4;
     g_params[kModePlain][kF32Min] = t1024x4;
-    g_params[kModePlain][kBF16Add] = t256x16g2;
-    g_params[kModePlain][kBF16AddComp] = t512x8g1;  // 220 us at 2^27, 1024 x 4 226
-    g_params[kModePlain][kBF16Max] = t256x16g2;
-    g_params[kModePlain][kBF16Min] = t256x16g2;
+    // bf16 prefetches too (two 8-byte rows per 16-byte LDS load): 2^27 elements,
+    // add 131 us at 1024 x 4 (256 x 16 two per CU 143), max 129, the
+    // compensated sum 166 at 512 x 8 (1024 x 4 spills: 197)
+    g_params[kModePlain][kBF16Add] = t1024x4;
+    g_params[kModePlain][kBF16AddComp] = t512x8g1;
+    g_params[kModePlain][kBF16Max] = t1024x4;
+    g_params[kModePlain][kBF16Min] = t1024x4;
     const Params t1024x2{5, 1};
     for (int o = kI32ArgMax; o <= kF32ArgMin; ++o) g_params[kModePlain][o] = t1024x2;
     // the 32-bit-index argmax / argmin kernels prefetch too (int32 keys, 2^28:

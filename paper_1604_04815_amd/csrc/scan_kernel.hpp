@@ -147,11 +147,18 @@ __device__ __forceinline__ void vmem_wait_keep()
 template <class T, int N>
 __device__ __forceinline__ void complete_loads(T (&v)[N])
 {
-    static_assert(sizeof(T) * N == 16, "one 16-byte lane vector");
-    u32x4 w;
-    __builtin_memcpy(&w, v, 16);
-    asm volatile("" : "+v"(w));
-    __builtin_memcpy(v, &w, 16);
+    static_assert(sizeof(T) * N == 16 || sizeof(T) * N == 8, "one 8- or 16-byte lane vector");
+    if constexpr (sizeof(T) * N == 16) {
+        u32x4 w;
+        __builtin_memcpy(&w, v, 16);
+        asm volatile("" : "+v"(w));
+        __builtin_memcpy(v, &w, 16);
+    } else {
+        u32x2 w;
+        __builtin_memcpy(&w, v, 8);
+        asm volatile("" : "+v"(w));
+        __builtin_memcpy(v, &w, 8);
+    }
 }
 __device__ __forceinline__ void lds_reads_drain() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
 
@@ -187,10 +194,6 @@ __device__ __forceinline__ int opaque_lane()
     asm volatile("" : "+v"(l));
     return l;
 }
-template <class Op, class = void>
-struct blocked_lanes : std::false_type {};
-template <class Op>
-struct blocked_lanes<Op, std::void_t<decltype(Op::kBlockedLanes)>> : std::bool_constant<Op::kBlockedLanes> {};
 
 // ---------------------------------------------------------------------------
 // Flag slots: one 64-bit word per 32 bits of payload, (tag << 32) | data.
@@ -438,18 +441,21 @@ __global__ void __launch_bounds__(T, (kMinWavesPerSimd<BaseOp, T, R, MODE>)) sca
     // HBM)
     constexpr bool kStage32 = E * sizeof(Out) == 32;
     __shared__ __attribute__((aligned(16))) u32x4 s_out32[kStage32 ? NWAVE : 1][kStage32 ? 128 : 1];
-    // plain and segmented scans reading 16-byte vectors: the next full block
-    // of the workgroup is prefetched into LDS (each wave its own R rows of
-    // 1 KiB) while the current block is scanned, so a workgroup's loads stay
-    // in flight through its compute.  (bf16 reads 8-byte vectors; gfx950 has
-    // no 8-byte form of the LDS load, and two 4-byte loads per row measured
-    // slower than the plain vector loads: 5.3 -> 4.8 TB/s.  Batched scans
+    // plain and segmented scans: the next full block of the workgroup is
+    // prefetched into LDS (each wave its own R rows, a byte image of them)
+    // while the current block is scanned, so a workgroup's loads stay in
+    // flight through its compute.  Each 16-byte LDS load of a wave moves one
+    // 1 KiB span: one row of 16-byte lane vectors, or two rows of 8-byte ones
+    // (bf16), read back from LDS one lane vector at a time.  (Batched scans
     // load as before: with arrays of a few blocks, a workgroup's next block
     // usually lies in another array and is often partial, and the prefetch
     // measured slower, 4096 arrays: 4.87 -> 4.64 TB/s.)
-    constexpr bool kPrefetch = (MODE == kModePlain || MODE == kModeSegmented) && E * sizeof(In) == 16;
-    constexpr uint32_t kRowBytes = 1024u;
-    __shared__ __attribute__((aligned(16))) u32x4 s_pf[kPrefetch ? T * R : 1];
+    constexpr int kVecBytes = E * int(sizeof(In));  // one lane-row of input
+    constexpr bool kPrefetch = (MODE == kModePlain || MODE == kModeSegmented) &&
+                               (kVecBytes == 16 || (kVecBytes == 8 && R % 2 == 0));
+    constexpr int kPfOps = R * kVecBytes / 16;        // 16-byte LDS loads per lane and block
+    constexpr int kChunkElems = 16 / int(sizeof(In)); // elements per 16-byte chunk
+    __shared__ __attribute__((aligned(16))) u32x4 s_pf[kPrefetch ? T * kPfOps : 1];
     // lane-blocked rows (lds_slot): plain scans of the operators that ask for them.
     // Lane l's first element sits kLaneElems after lane l - 1's, and its rows
     // kRowStep apart; s_tr turns each wave's outputs back into 1 KiB spans
@@ -492,7 +498,12 @@ __global__ void __launch_bounds__(T, (kMinWavesPerSimd<BaseOp, T, R, MODE>)) sca
     VB carry = BOp::identity();         // wave 0: P(j - B) for the pending block j
 
     // the prefetch: this wave's LDS rows, and whether they hold the block to scan next
-    const uint32_t pf_lds = kPrefetch ? lds_address(&s_pf[0]) + uint32_t(wave) * R * kRowBytes : 0u;
+    const uint32_t pf_lds = kPrefetch ? lds_address(&s_pf[0]) + uint32_t(wave) * kPfOps * 1024u : 0u;
+    // the 16-byte LDS loads need 16-byte aligned chunks: a grid origin of 8-byte
+    // vectors that is not (bf16 input 8 bytes past a 16-byte boundary) has its
+    // full blocks loaded straight into registers instead
+    const bool pf_ok = kPrefetch && (kVecBytes == 16 ||
+                                     ((reinterpret_cast<uintptr_t>(a.x) - uintptr_t(a.phase) * sizeof(In)) & 15u) == 0);
     bool pf_have = false;
     // the previous step wrote its pending block with at least R vector stores per
     // wave, all issued after the prefetch that the next step waits for
@@ -524,11 +535,12 @@ __global__ void __launch_bounds__(T, (kMinWavesPerSimd<BaseOp, T, R, MODE>)) sca
         return true;
     };
     auto prefetch = [&](const In* xg, int64_t t0) {  // xg: the array's grid origin, t0: the block's first position
-        // (lane-blocked rows: slot 64r + l of the wave's rows receives chunk 64r + lds_chunk(l))
+        // load d puts chunk 64d + l of the wave's rows in slot 64d + l (lane-blocked
+        // rows: chunk 64d + lds_chunk(l))
         const int src = kBlocked ? lds_chunk(lane) : lane;
-        const In* xs = xg + t0 + int64_t(wave) * (R * ROW) + int64_t(src) * E;
+        const In* xs = xg + t0 + int64_t(wave) * (R * ROW) + int64_t(src) * kChunkElems;
 #pragma unroll
-        for (int r = 0; r < R; ++r) lds_load16(xs + int64_t(r) * ROW, pf_lds + uint32_t(r) * kRowBytes);
+        for (int d = 0; d < kPfOps; ++d) lds_load16(xs + int64_t(d) * (64 * kChunkElems), pf_lds + uint32_t(d) * 1024u);
     };
 
     int parity = 0;
@@ -578,7 +590,7 @@ __global__ void __launch_bounds__(T, (kMinWavesPerSimd<BaseOp, T, R, MODE>)) sca
         } else {
             xg = static_cast<const In*>(a.x) - a.phase;
             t0 = i * L;
-            return a.vec_ok != 0 && t0 + L <= a.n + a.phase && t0 >= a.phase;
+            return pf_ok && a.vec_ok != 0 && t0 + L <= a.n + a.phase && t0 >= a.phase;
         }
     };
     if constexpr (kPrefetch) {
@@ -642,7 +654,7 @@ __global__ void __launch_bounds__(T, (kMinWavesPerSimd<BaseOp, T, R, MODE>)) sca
             lane0 = tile0 + int64_t(wave) * (R * ROW) + int64_t(lane) * kLaneElems;
             full = vec_ok && (tile0 + L <= n) && (tile0 >= ph);
             if (full) {
-                if constexpr (kPrefetch) {
+                if (kPrefetch && pf_ok) {
                     // a full block arrives through LDS: prefetched during the previous
                     // step (or, after a partial block, loaded that way now), so no
                     // data load of the compiler's own is ever pending past this point
@@ -652,17 +664,37 @@ __global__ void __launch_bounds__(T, (kMinWavesPerSimd<BaseOp, T, R, MODE>)) sca
                         if (!pf_have) prefetch(x, tile0);
                         vmem_drain();
                     }
-                    const int lb = kBlocked ? opaque_lane() * R : 0;
+                    const u32x4* pw = &s_pf[wave * kPfOps * 64];  // this wave's rows
+                    if constexpr (kBlocked) {  // the lane's kPfOps consecutive chunks
+                        const int lb = opaque_lane() * kPfOps;
+                        u32x4 w[kPfOps];
 #pragma unroll
-                    for (int r = 0; r < R; ++r) {
-                        const int c = kBlocked ? lds_slot(lb + r) : r * 64 + lane;
-                        const u32x4 w = s_pf[wave * R * 64 + c];
-                        __builtin_memcpy(raw[r], &w, 16);
+                        for (int h = 0; h < kPfOps; ++h) w[h] = pw[lds_slot(lb + h)];
+                        static_assert(sizeof(w) == sizeof(raw), "the lane's rows");
+                        __builtin_memcpy(raw, w, sizeof(raw));
+                    } else if constexpr (kVecBytes == 16) {
+#pragma unroll
+                        for (int r = 0; r < R; ++r) {
+                            const u32x4 w = pw[r * 64 + lane];
+                            __builtin_memcpy(raw[r], &w, 16);
+                        }
+                    } else {  // 8-byte lane vectors: row r of lane l is 8-byte unit 64r + l
+                        const u32x2* pw8 = reinterpret_cast<const u32x2*>(pw);
+#pragma unroll
+                        for (int r = 0; r < R; ++r) {
+                            const u32x2 w = pw8[r * 64 + lane];
+                            __builtin_memcpy(raw[r], &w, 8);
+                        }
                     }
                     lds_reads_drain();  // the rows are read before the next prefetch overwrites them
                 } else {
 #pragma unroll
-                    for (int r = 0; r < R; ++r) load_vector<In, E>(x + lane0 + int64_t(r) * ROW, raw[r]);
+                    for (int r = 0; r < R; ++r) load_vector<In, E>(x + lane0 + int64_t(r) * kRowStep, raw[r]);
+                    // (kernels that prefetch: completed here, off the path of the LDS reads)
+                    if constexpr (kPrefetch) {
+#pragma unroll
+                        for (int r = 0; r < R; ++r) complete_loads(raw[r]);
+                    }
                 }
             } else if (MODE == kModeBatched && vec_ok) {
                 // an array's first or last block: whole rows of the wave (a
@@ -760,13 +792,13 @@ __global__ void __launch_bounds__(T, (kMinWavesPerSimd<BaseOp, T, R, MODE>)) sca
                     if (flags_have) {
                         // the copy made at the end of the previous step is complete once
                         // no more than the operations issued after it are outstanding that
-                        // this step may still have in flight: its R prefetch loads and the
+                        // this step may still have in flight: its kPfOps prefetch loads and the
                         // new block's aggregate (data loads of this step were waited for)
                         const bool published = have_new;
                         if (pf_now && published)
-                            vmem_wait_keep<R + 1>();
+                            vmem_wait_keep<kPfOps + 1>();
                         else if (pf_now)
-                            vmem_wait_keep<R>();
+                            vmem_wait_keep<kPfOps>();
                         else if (published)
                             vmem_wait_keep<1>();
                         else
@@ -803,7 +835,7 @@ __global__ void __launch_bounds__(T, (kMinWavesPerSimd<BaseOp, T, R, MODE>)) sca
         // for the prefetch
         // (after a partial block, only once its own loads are done: below)
         bool pf_late = false;
-        bool pf_now = false;  // R prefetch loads per wave issued in this step
+        bool pf_now = false;  // kPfOps prefetch loads per wave issued in this step
         if constexpr (kPrefetch) {
             const In* xg;
             int64_t t0;

@@ -400,6 +400,11 @@ __device__ __forceinline__ typename Op::Out finish_of(const typename Op::V& q, c
 // the 4 float32 outputs fill one 16-byte store.
 __device__ __forceinline__ uint32_t bf16_bits_to_f32_bits(uint16_t h) { return (uint32_t)h << 16; }
 
+// Whether an operator asks for lane-blocked rows (its kBlockedLanes member).
+template <class Op, class = void>
+struct blocked_lanes : std::false_type {};
+template <class Op>
+struct blocked_lanes<Op, std::void_t<decltype(Op::kBlockedLanes)>> : std::bool_constant<Op::kBlockedLanes> {};
 template <class F32Op>
 struct FromBF16 {
     using In = uint16_t; using V = typename F32Op::V; using Out = typename F32Op::Out;
@@ -409,6 +414,7 @@ struct FromBF16 {
     __device__ static V lift(In x) { return F32Op::lift(bf16_bits_to_f32_bits(x)); }
     __device__ static Out lower(V v) { return F32Op::lower(v); }
     __device__ static Out finish(V q, V e) { return finish_of<F32Op>(q, e); }
+    static constexpr bool kBlockedLanes = blocked_lanes<F32Op>::value;
 };
 using AddBF16 = FromBF16<AddF32>;
 using AddBF16Comp = FromBF16<AddF32Comp>;

@@ -193,6 +193,26 @@ def test_unaligned_compensated(gpu_lib):
         compare(to_host(xd), x, "float32", "add", False, True, what=f"in-place compensated n={n}")
 
 
+def test_bf16_grid_origin_off_16_bytes(gpu_lib):
+    # bf16 lane vectors are 8 bytes, so the shifted block grid may start 8 bytes
+    # past a 16-byte boundary: such launches cannot use the 16-byte loads into
+    # LDS and read full blocks straight into registers (lane-blocked rows of the
+    # compensated sum included); x offsets 4..7 elements put the origin there
+    for op, comp in (("add", False), ("add", True), ("max", False)):
+        for n in (2_000_003, 70_001):
+            for xo, yo in ((4, 4), (5, 5), (7, 3), (4, 1)):
+                x = make_input("bfloat16", op, n + 8, seed=31 + xo + n % 5)
+                base = to_device(x, "bfloat16")
+                xd = base[xo:xo + n]
+                y_base = torch.empty(n + 8, dtype=torch.float32, device="cuda")
+                for excl in (False, True):
+                    fn = gpu_lib.exclusive if excl else gpu_lib.inclusive
+                    y = fn(xd, op, comp, out=y_base[yo:yo + n])
+                    gpu_lib.lscan_check(torch.cuda.current_stream().cuda_stream)
+                    compare(to_host(y), x[xo:xo + n], "bfloat16", op, excl, comp,
+                            what=f"bf16 origin 8 bytes off {op} comp={comp} n={n} x+{xo} y+{yo} excl={excl}")
+
+
 def test_repeated_launches_reuse_flags(gpu_lib):
     # flag slots are never cleared between launches (epoch tags): many
     # launches of varying sizes on one stream must all be right

@@ -302,6 +302,31 @@ __device__ typename Op::V window_fold(const uint64_t* slots, int64_t lo, int64_t
     return window_fold_from<Op, QC>(first, slots, lo, cnt, tag, limit, abort_word, lane, ok);
 }
 
+// Wave-wide copy of the flag words of slots [lo, lo + cnt) (W words each)
+// into LDS at lds_base, in 16-byte loads from the aligned chunk that holds the
+// first word (every chunk read lies inside the slot array: it starts 16-byte
+// aligned and holds, right after the window, the slot of the block the window
+// belongs to).  *shift receives the first word's index in the copy.  Issues
+// nothing and returns false when the window needs more than max_chunks loads'
+// worth of chunks or the slots are not 16-byte aligned.
+template <int W>
+__device__ __forceinline__ bool fetch_window_flags(const uint64_t* slots, int64_t lo, int64_t cnt, uint32_t lds_base,
+                                                   int64_t max_chunks, int lane, int& shift)
+{
+    const uintptr_t ab = reinterpret_cast<uintptr_t>(slots + lo * W);
+    const int sh = int((ab & 15u) >> 3);
+    const int64_t chunks = (int64_t(sh) * 8 + cnt * (W * 8) + 15) >> 4;
+    if ((reinterpret_cast<uintptr_t>(slots) & 15u) != 0 || chunks > max_chunks) return false;
+    const char* c0 = reinterpret_cast<const char*>(ab - uintptr_t(sh) * 8);
+    lds_reads_drain();  // the previous window's words are read
+    for (int64_t d = 0; d * 64 < chunks; ++d) {
+        const int64_t c = (d * 64 + lane < chunks) ? d * 64 + lane : chunks - 1;
+        lds_load16_coherent(c0 + c * 16, lds_base + uint32_t(d) * 1024u);
+    }
+    shift = sh;
+    return true;
+}
+
 // The paper's hand-off (Algorithm 4): wait for the inclusive prefix that the
 // previous block published in its slot.  Lanes 0 .. W-1 each wait for one
 // word; the value is assembled from their lanes.
@@ -516,23 +541,8 @@ __global__ void __launch_bounds__(T, (kMinWavesPerSimd<BaseOp, T, R, MODE>)) sca
     const uint32_t flags_lds = lds_address(&s_flags[0]);
     bool flags_have = false;  // wave 0: s_flags holds the pending block's window
     int flags_shift = 0;      // the window's first word is word flags_shift of s_flags
-    // wave 0: copy the flag words of slots [lo, lo + cnt) into s_flags, in 16-byte
-    // chunks from the aligned chunk that holds the first word (every chunk read
-    // lies inside the slot array: it starts 16-byte aligned and holds the slot of
-    // the block whose window this is, right after the window)
     auto flags_fetch = [&](int64_t lo, int64_t cnt) -> bool {
-        const uintptr_t ab = reinterpret_cast<uintptr_t>(a.slots + lo * W);
-        const int shift = int((ab & 15u) >> 3);
-        const int64_t chunks = (int64_t(shift) * 8 + cnt * (W * 8) + 15) >> 4;
-        if ((reinterpret_cast<uintptr_t>(a.slots) & 15u) != 0 || chunks > kFlagChunks) return false;
-        const char* c0 = reinterpret_cast<const char*>(ab - uintptr_t(shift) * 8);
-        lds_reads_drain();  // the previous window's words are read
-        for (int64_t d = 0; d * 64 < chunks; ++d) {
-            const int64_t c = (d * 64 + lane < chunks) ? d * 64 + lane : chunks - 1;
-            lds_load16_coherent(c0 + c * 16, flags_lds + uint32_t(d) * 1024u);
-        }
-        flags_shift = shift;
-        return true;
+        return fetch_window_flags<W>(a.slots, lo, cnt, flags_lds, kFlagChunks, lane, flags_shift);
     };
     auto prefetch = [&](const In* xg, int64_t t0) {  // xg: the array's grid origin, t0: the block's first position
         // load d puts chunk 64d + l of the wave's rows in slot 64d + l (lane-blocked

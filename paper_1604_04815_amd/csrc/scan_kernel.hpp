@@ -455,10 +455,6 @@ __global__ void __launch_bounds__(T, (kMinWavesPerSimd<BaseOp, T, R, MODE>)) sca
         return;
     }
 
-    // arrays whose y sits at another alignment phase than x: each wave stages
-    // one output row here to write it as aligned vectors
-    constexpr bool kStageY = E * sizeof(Out) == 16;
-    __shared__ __attribute__((aligned(16))) Out s_ystage[kStageY ? NWAVE : 1][kStageY ? ROW + E : 1];
     // 32-byte lane outputs (int64 indices of 16-byte key vectors): each wave
     // passes its row through LDS, so that every store instruction writes one
     // contiguous 1 KiB span instead of 16 bytes at a 32-byte stride (which
@@ -489,6 +485,16 @@ __global__ void __launch_bounds__(T, (kMinWavesPerSimd<BaseOp, T, R, MODE>)) sca
     constexpr int64_t kLaneElems = kBlocked ? int64_t(R) * E : E;
     constexpr int64_t kRowStep = kBlocked ? E : ROW;
     __shared__ __attribute__((aligned(16))) u32x4 s_tr[kBlocked ? T * R : 1];
+    // arrays whose y sits at another alignment phase than x: each wave stages
+    // one output row here to write it as aligned vectors
+    constexpr bool kStageY = E * sizeof(Out) == 16;
+    // the rows written as vectors stage the wave's span of them (a wave's rows are
+    // contiguous, and so are the rows of a partial batched block that lie inside
+    // its array) and write it after the last row: one LDS round trip and two
+    // partial vectors per block instead of per row (lane-blocked kernels, whose
+    // LDS holds the transpose, stage row by row)
+    constexpr bool kStageSpan = kStageY && !kBlocked;
+    __shared__ __attribute__((aligned(16))) Out s_ystage[kStageY ? NWAVE : 1][kStageY ? (kStageSpan ? R * ROW : ROW) + E : 1];
     __shared__ V s_wave_total[2][NWAVE];
     __shared__ VB s_block_prefix[2];
     __shared__ int s_abort[2];
@@ -1016,6 +1022,10 @@ __global__ void __launch_bounds__(T, (kMinWavesPerSimd<BaseOp, T, R, MODE>)) sca
             // lane-blocked rows: the lane's first chunk, and its slot in a striped row
             const int tb = kBlocked ? opaque_lane() * R : 0;
             const int ts = kBlocked ? lds_slot(opaque_lane()) : 0;
+            // staged full blocks: the wave span's offset from the aligned vector below it
+            const int32_t span_shift =
+                kStageSpan ? int32_t((reinterpret_cast<uintptr_t>(p_y + (p_lane0 - int64_t(lane) * E)) % 16) / sizeof(Out))
+                           : 0;
             // one row of outputs (lane vector r, first position p) to y
             auto store_row = [&](int r, const Out (&out)[E], int64_t p) __attribute__((always_inline)) {
                 // rows read as vectors (a full block, or a whole row of an array's
@@ -1044,6 +1054,10 @@ __global__ void __launch_bounds__(T, (kMinWavesPerSimd<BaseOp, T, R, MODE>)) sca
                     wave_lds_sync();  // the next row's stage writes come after every lane's reads
                 } else if (vec_row && p_svec) {
                     store_vector<Out, E>(p_y + p, out);
+                } else if (kStageSpan && vec_row) {  // staged here, written after the last row
+                    Out* stage = s_ystage[kStageY ? wave : 0];
+#pragma unroll
+                    for (int k = 0; k < E; ++k) stage[span_shift + r * ROW + lane * E + k] = out[k];
                 } else if (kStageY && vec_row) {
                     // y at another phase than the grid: stage the wave's row
                     // at its offset from the aligned vector below it, then
@@ -1117,6 +1131,30 @@ __global__ void __launch_bounds__(T, (kMinWavesPerSimd<BaseOp, T, R, MODE>)) sca
                     s_tr[wave * R * 64 + lds_slot(tb + r)] = w;
                 } else {
                     store_row(r, out, p_lane0 + int64_t(r) * ROW);
+                }
+            }
+            if constexpr (kStageSpan) {
+                const uint32_t vmask = p_full ? ((R == 32) ? ~0u : ((1u << R) - 1u)) : p_vrow;
+                if (!p_svec && vmask != 0) {  // the staged rows: aligned vectors, partial ones at both ends
+                    wave_lds_sync();  // lanes read what other lanes wrote
+                    const Out* stage = s_ystage[kStageY ? wave : 0];
+                    Out* dst = p_y + (p_lane0 - int64_t(lane) * E) - span_shift;
+                    // staged outputs occupy [lo, hi): rows r0 .. r1, shifted by span_shift
+                    const int32_t r0 = __builtin_ctz(vmask), r1 = 31 - __builtin_clz(vmask);
+                    const int32_t lo = span_shift + r0 * ROW, hi = span_shift + (r1 + 1) * ROW;
+                    for (int32_t c = r0 * ROW + lane * E; c < hi; c += 64 * E) {
+                        if (c >= lo && c + E <= hi) {
+                            Out v[E];
+#pragma unroll
+                            for (int k = 0; k < E; ++k) v[k] = stage[c + k];
+                            store_vector<Out, E>(dst + c, v);
+                        } else {
+#pragma unroll
+                            for (int k = 0; k < E; ++k)
+                                if (c + k >= lo && c + k < hi) dst[c + k] = stage[c + k];
+                        }
+                    }
+                    wave_lds_sync();  // the next block's stage writes come after every lane's reads
                 }
             }
             if constexpr (kBlocked) {

@@ -1159,13 +1159,50 @@ __global__ void __launch_bounds__(T, (kMinWavesPerSimd<BaseOp, T, R, MODE>)) sca
             }
             if constexpr (kBlocked) {
                 wave_lds_sync();  // lanes read what other lanes wrote
-                const int64_t p0 = p_lane0 - int64_t(lane) * (kLaneElems - E);  // striped: lane l's vector of row r
+                if (p_full && !p_svec) {
+                    // y at another phase than the grid: aligned output vector k holds the
+                    // wave's outputs k*E - shift .. k*E - shift + E - 1, taken from
+                    // staged chunks k - 1 and k (the partial vectors at both ends of the
+                    // wave's span element by element)
+                    static_assert(E == 4, "4-byte outputs in 16-byte chunks");
+                    const u32x4* tw = &s_tr[wave * R * 64];
+                    Out* wave_y = p_y + (p_lane0 - int64_t(lane) * kLaneElems);
+                    const int32_t shift = int32_t((reinterpret_cast<uintptr_t>(wave_y) % 16) / sizeof(Out));
+                    Out* dst = wave_y - shift;
+                    constexpr int32_t kWaveOut = R * 64 * E;
+                    auto staged = [&](int32_t c, Out (&o)[E]) {
+                        const u32x4 w = tw[(c & ~63) | lds_slot(c & 63)];
+                        __builtin_memcpy(o, &w, 16);
+                    };
+                    for (int32_t k = lane; k <= R * 64; k += 64) {
+                        Out prev[E] = {}, cur[E] = {};
+                        if (k > 0) staged(k - 1, prev);
+                        if (k < R * 64) staged(k, cur);
+                        Out v[E];
+                        switch (shift) {  // wave-uniform
+                        case 0: v[0] = cur[0]; v[1] = cur[1]; v[2] = cur[2]; v[3] = cur[3]; break;
+                        case 1: v[0] = prev[3]; v[1] = cur[0]; v[2] = cur[1]; v[3] = cur[2]; break;
+                        case 2: v[0] = prev[2]; v[1] = prev[3]; v[2] = cur[0]; v[3] = cur[1]; break;
+                        default: v[0] = prev[1]; v[1] = prev[2]; v[2] = prev[3]; v[3] = cur[0]; break;
+                        }
+                        const int32_t first = k * E - shift;  // wave output index of v[0]
+                        if (first >= 0 && first + E <= kWaveOut) {
+                            store_vector<Out, E>(dst + k * E, v);
+                        } else {
 #pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    const u32x4 w = s_tr[wave * R * 64 + r * 64 + ts];  // chunk 64r + l
-                    Out out[E];
-                    __builtin_memcpy(out, &w, 16);
-                    store_row(r, out, p0 + int64_t(r) * ROW);
+                            for (int j = 0; j < E; ++j)
+                                if (first + j >= 0 && first + j < kWaveOut) dst[k * E + j] = v[j];
+                        }
+                    }
+                } else {
+                    const int64_t p0 = p_lane0 - int64_t(lane) * (kLaneElems - E);  // striped: lane l's vector of row r
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        const u32x4 w = s_tr[wave * R * 64 + r * 64 + ts];  // chunk 64r + l
+                        Out out[E];
+                        __builtin_memcpy(out, &w, 16);
+                        store_row(r, out, p0 + int64_t(r) * ROW);
+                    }
                 }
                 wave_lds_sync();  // the next block's writes come after every lane's reads
             }

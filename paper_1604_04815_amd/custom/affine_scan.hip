@@ -32,4 +32,4 @@ struct AffineOp {
 // Handles of the operator's scan kernel at three tile shapes.
 extern "C" const void* lscan_affine_kernel() { return lscan_custom::kernel<AffineOp, 256, 8>(); }
 extern "C" const void* lscan_affine_kernel_small() { return lscan_custom::kernel<AffineOp, 64, 1>(); }
-extern "C" const void* lscan_affine_kernel_wide() { return lscan_custom::kernel<AffineOp, 1024, 2>(); }
+extern "C" const void* lscan_affine_kernel_wide() { return lscan_custom::kernel<AffineOp, 512, 8>(); }

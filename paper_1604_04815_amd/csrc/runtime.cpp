@@ -207,10 +207,10 @@ void init_params_locked()
     g_params[kModePlain][kI64ArgMaxS] = t1024x4;
     g_params[kModePlain][kI64ArgMinS] = t1024x4;
     for (int o = 0; o < kNumOpCodes; ++o) {
-        // with the per-block segment table; 512 x 8 (4096 segments, int32 add:
-        // 5.38 TB/s), whose kernels keep their registers where 1024 x 4 spills
-        const bool comp = o == kF32AddComp || o == kBF16AddComp;
-        g_params[kModeSegmented][o] = comp ? t1024x4 : t512x8g1;
+        // with the per-block segment table and (sums) lane-blocked rows; 512 x 8
+        // (4096 segments, int32 add: 5.81 TB/s), whose kernels keep their
+        // registers where 1024 x 4 spills
+        g_params[kModeSegmented][o] = t512x8g1;
         g_params[kModeBatched][o] = g_params[kModePlain][o];
         g_params[kModeCompact][o] = t1024x4;
     }

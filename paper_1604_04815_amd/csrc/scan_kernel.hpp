@@ -195,6 +195,21 @@ __device__ __forceinline__ int opaque_lane()
     return l;
 }
 
+// Segmented scans of sums take lane-blocked rows too (a zero input word, which
+// partial blocks hold outside the array, lifts to the identity of a sum).
+template <class Op>
+struct blocked_segmented : std::false_type {};
+template <>
+struct blocked_segmented<AddI32> : std::true_type {};
+template <>
+struct blocked_segmented<AddI64> : std::true_type {};
+template <>
+struct blocked_segmented<AddF32> : std::true_type {};
+template <>
+struct blocked_segmented<AddF32Comp> : std::true_type {};
+template <class F>
+struct blocked_segmented<FromBF16<F>> : blocked_segmented<F> {};
+
 // ---------------------------------------------------------------------------
 // Flag slots: one 64-bit word per 32 bits of payload, (tag << 32) | data.
 // ---------------------------------------------------------------------------
@@ -480,8 +495,9 @@ __global__ void __launch_bounds__(T, (kMinWavesPerSimd<BaseOp, T, R, MODE>)) sca
     // lane-blocked rows (lds_slot): plain scans of the operators that ask for them.
     // Lane l's first element sits kLaneElems after lane l - 1's, and its rows
     // kRowStep apart; s_tr turns each wave's outputs back into 1 KiB spans
-    constexpr bool kBlocked =
-        kPrefetch && MODE == kModePlain && blocked_lanes<BaseOp>::value && E * sizeof(Out) == 16;
+    constexpr bool kBlocked = kPrefetch && E * sizeof(Out) == 16 &&
+                              ((MODE == kModePlain && blocked_lanes<BaseOp>::value) ||
+                               (MODE == kModeSegmented && blocked_segmented<BaseOp>::value));
     constexpr int64_t kLaneElems = kBlocked ? int64_t(R) * E : E;
     constexpr int64_t kRowStep = kBlocked ? E : ROW;
     __shared__ __attribute__((aligned(16))) u32x4 s_tr[kBlocked ? T * R : 1];
@@ -766,14 +782,14 @@ __global__ void __launch_bounds__(T, (kMinWavesPerSimd<BaseOp, T, R, MODE>)) sca
                         const int64_t rel = off[k] + ph - lane0;
 #pragma unroll
                         for (int r = 0; r < R; ++r) {
-                            const int64_t d = rel - int64_t(r) * ROW;
+                            const int64_t d = rel - int64_t(r) * kRowStep;
                             if (uint64_t(d) < uint64_t(E)) head[r] |= 1u << uint32_t(d);
                         }
                     }
                 } else {
 #pragma unroll
                     for (int r = 0; r < R; ++r) {
-                        const int64_t p = lane0 + int64_t(r) * ROW;
+                        const int64_t p = lane0 + int64_t(r) * kRowStep;
                         int64_t k = lower_bound_i64(a.offsets, s_lo, s_hi, p - ph);
                         uint32_t h = 0;
                         for (; k < s_hi; ++k) {
@@ -948,12 +964,18 @@ __global__ void __launch_bounds__(T, (kMinWavesPerSimd<BaseOp, T, R, MODE>)) sca
                 // the lanes before this one, lane_prefix[r] (r > 0) this lane's rows
                 // before r
                 V run = EOp::identity();
+                auto lifted = [&](int r, int k) -> V {
+                    const auto v = lift_elem<BaseOp>(raw[r][k], lane0 + int64_t(r) * kRowStep + k - ph);
+                    if constexpr (MODE == kModeSegmented)
+                        return EOp::make(v, (head[r] >> k) & 1u);
+                    else
+                        return v;
+                };
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
-                    V t = lift_elem<BaseOp>(raw[r][0], lane0 + int64_t(r) * kRowStep - ph);
+                    V t = lifted(r, 0);
 #pragma unroll
-                    for (int k = 1; k < E; ++k)
-                        t = EOp::combine(t, lift_elem<BaseOp>(raw[r][k], lane0 + int64_t(r) * kRowStep + k - ph));
+                    for (int k = 1; k < E; ++k) t = EOp::combine(t, lifted(r, k));
                     if (r == 0) {
                         run = t;
                     } else {
@@ -1096,13 +1118,19 @@ __global__ void __launch_bounds__(T, (kMinWavesPerSimd<BaseOp, T, R, MODE>)) sca
                 V ev[E];
 #pragma unroll
                 for (int k = 0; k < E; ++k) {
-                    if constexpr (MODE == kModeSegmented)
-                        ev[k] = EOp::make(pe[r][k], (p_seen[r] >> k) & 1u);
-                    else if constexpr (kBlocked) {  // the in-row scan, again from the raw inputs
-                        const V xk = lift_elem<BaseOp>(p_raw[r][k], p_lane0 + int64_t(r) * kRowStep + k - p_ph);
+                    if constexpr (kBlocked) {  // the in-row scan, again from the raw inputs
+                        const auto xv = lift_elem<BaseOp>(p_raw[r][k], p_lane0 + int64_t(r) * kRowStep + k - p_ph);
+                        V xk;
+                        if constexpr (MODE == kModeSegmented)
+                            xk = EOp::make(xv, (p_head[r] >> k) & 1u);
+                        else
+                            xk = xv;
                         ev[k] = (k == 0) ? xk : EOp::combine(ev[k - 1], xk);
-                    } else
+                    } else if constexpr (MODE == kModeSegmented) {
+                        ev[k] = EOp::make(pe[r][k], (p_seen[r] >> k) & 1u);
+                    } else {
                         ev[k] = pe[r][k];
+                    }
                 }
                 Out out[E];
 #pragma unroll
@@ -1164,7 +1192,7 @@ __global__ void __launch_bounds__(T, (kMinWavesPerSimd<BaseOp, T, R, MODE>)) sca
                     // wave's outputs k*E - shift .. k*E - shift + E - 1, taken from
                     // staged chunks k - 1 and k (the partial vectors at both ends of the
                     // wave's span element by element)
-                    static_assert(E == 4, "4-byte outputs in 16-byte chunks");
+                    static_assert(E * sizeof(Out) == 16, "16-byte output chunks");
                     const u32x4* tw = &s_tr[wave * R * 64];
                     Out* wave_y = p_y + (p_lane0 - int64_t(lane) * kLaneElems);
                     const int32_t shift = int32_t((reinterpret_cast<uintptr_t>(wave_y) % 16) / sizeof(Out));
@@ -1179,11 +1207,17 @@ __global__ void __launch_bounds__(T, (kMinWavesPerSimd<BaseOp, T, R, MODE>)) sca
                         if (k > 0) staged(k - 1, prev);
                         if (k < R * 64) staged(k, cur);
                         Out v[E];
-                        switch (shift) {  // wave-uniform
-                        case 0: v[0] = cur[0]; v[1] = cur[1]; v[2] = cur[2]; v[3] = cur[3]; break;
-                        case 1: v[0] = prev[3]; v[1] = cur[0]; v[2] = cur[1]; v[3] = cur[2]; break;
-                        case 2: v[0] = prev[2]; v[1] = prev[3]; v[2] = cur[0]; v[3] = cur[1]; break;
-                        default: v[0] = prev[1]; v[1] = prev[2]; v[2] = prev[3]; v[3] = cur[0]; break;
+#pragma unroll
+                        for (int sh = 0; sh < E; ++sh) {  // shift is wave-uniform
+                            if (shift == sh) {
+#pragma unroll
+                                for (int j = 0; j < E; ++j) {
+                                    if (j < sh)
+                                        v[j] = prev[E - sh + j];
+                                    else
+                                        v[j] = cur[j - sh];
+                                }
+                            }
                         }
                         const int32_t first = k * E - shift;  // wave output index of v[0]
                         if (first >= 0 && first + E <= kWaveOut) {
@@ -1248,7 +1282,10 @@ __global__ void __launch_bounds__(T, (kMinWavesPerSimd<BaseOp, T, R, MODE>)) sca
                     p_lp[r] = (r == 0) ? wl : EOp::combine(wl, lane_prefix[r]);
                 else
                     p_lp[r] = EOp::combine(EOp::combine(wave_prefix, row_prefix[r]), lane_prefix[r]);
-                if constexpr (MODE == kModeSegmented) {
+                if constexpr (kBlocked) {
+#pragma unroll
+                    for (int k = 0; k < E; ++k) p_raw[r][k] = raw[r][k];
+                } else if constexpr (MODE == kModeSegmented) {
                     uint32_t seen = 0;
 #pragma unroll
                     for (int k = 0; k < E; ++k) {
@@ -1256,9 +1293,6 @@ __global__ void __launch_bounds__(T, (kMinWavesPerSimd<BaseOp, T, R, MODE>)) sca
                         seen |= (e[r][k].f ? 1u : 0u) << k;
                     }
                     p_seen[r] = seen;
-                } else if constexpr (kBlocked) {
-#pragma unroll
-                    for (int k = 0; k < E; ++k) p_raw[r][k] = raw[r][k];
                 } else {
 #pragma unroll
                     for (int k = 0; k < E; ++k) pe[r][k] = e[r][k];

@@ -102,7 +102,7 @@ def test_heads_per_block_around_matching_limit(gpu_lib, max_len):
 
 
 SEG_UNALIGNED = [("int32", "add", False), ("int64", "max", False), ("float32", "add", True),
-                 ("bfloat16", "add", False), ("float32", "min", False)]
+                 ("bfloat16", "add", False), ("float32", "min", False), ("int64", "add", False)]
 
 
 @pytest.mark.parametrize("dtype,op,comp", SEG_UNALIGNED,

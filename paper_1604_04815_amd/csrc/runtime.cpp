@@ -193,9 +193,9 @@ void init_params_locked()
     g_params[kModePlain][kF32Max] = t1024x4;
     g_params[kModePlain][kF32Min] = t1024x4;
     // bf16 prefetches too (two 8-byte rows per 16-byte LDS load): 2^27 elements,
-    // add 131 us at 1024 x 4 (256 x 16 two per CU 143), max 129, the
-    // compensated sum 166 at 512 x 8 (1024 x 4 spills: 197)
-    g_params[kModePlain][kBF16Add] = t1024x4;
+    // add 127 us at 512 x 8 (1024 x 4 131, 256 x 16 two per CU 143), max 129
+    // at 1024 x 4, the compensated sum 166 at 512 x 8 (1024 x 4 spills: 197)
+    g_params[kModePlain][kBF16Add] = t512x8g1;
     g_params[kModePlain][kBF16AddComp] = t512x8g1;
     g_params[kModePlain][kBF16Max] = t1024x4;
     g_params[kModePlain][kBF16Min] = t1024x4;

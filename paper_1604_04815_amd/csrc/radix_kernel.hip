@@ -59,7 +59,23 @@ __global__ void __launch_bounds__(kHistThreads) digit_count_kernel(RadixArgs a)
         int64_t p = lo;
         if (a.vec_ok) {  // 16-byte vectors over the aligned body of the block
             const int64_t v_end = lo + ((hi - lo) / E) * E;
-            for (int64_t q = lo + int64_t(tid) * E; q < v_end; q += int64_t(kHistThreads) * E) {
+            const int64_t stride = int64_t(kHistThreads) * E;
+            int64_t q = lo + int64_t(tid) * E;
+            // four vectors in flight per thread before their counts go to LDS
+            for (; q + 3 * stride < v_end; q += 4 * stride) {
+                u32x4v w[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    w[u] = __builtin_nontemporal_load(reinterpret_cast<const u32x4v*>(keys + q + u * stride));
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    K k[E];
+                    __builtin_memcpy(k, &w[u], 16);
+#pragma unroll
+                    for (int e = 0; e < E; ++e) atomicAdd(&hist[digit_of(k[e], a.shift, mask)], 1u);
+                }
+            }
+            for (; q < v_end; q += stride) {
                 u32x4v w = __builtin_nontemporal_load(reinterpret_cast<const u32x4v*>(keys + q));
                 K k[E];
                 __builtin_memcpy(k, &w, 16);
